@@ -1,0 +1,356 @@
+"""Pins for oracle/lbm.py (the FP64 lattice update) against what the paper, kinetic
+theory and symmetry fix.  Each plausible mistake (a dropped term, a wrong sign or
+index, a transposed operand) fails at least one check here; the mutation tests
+at the end plant a few such mistakes in the oracle and show that they are caught.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm, thermo
+from paper_2106_01557_amd import inputs
+
+
+@pytest.fixture(scope="module")
+def model():
+    return lbm.Model.build(thermo.paper_cs_eos(), thermo.Params())
+
+
+@pytest.fixture(scope="module")
+def profile_table(model):
+    d = model.d
+    return thermo.flat_profile_table(model.eos, d.T0, d.kappa, 120)
+
+
+# --- lattice structure -------------------------------------------------------------------
+
+def test_velocity_set_geometry():
+    """SM Eq. (1): rest, four unit axis vectors, four diagonals; opposite pairs; the set is
+    mapped onto itself by a quarter turn (1->2->3->4, 5->6->7->8)."""
+    E = lbm.E
+    n2 = (E ** 2).sum(axis=1)
+    assert list(n2) == [0, 1, 1, 1, 1, 2, 2, 2, 2]
+    for i, j in [(1, 3), (2, 4), (5, 7), (6, 8)]:
+        assert (E[i] == -E[j]).all()
+    rot = lambda v: np.array([-v[1], v[0]])
+    for i in range(1, 5):
+        assert (rot(E[i]) == E[i % 4 + 1]).all()
+    for i in range(5, 9):
+        assert (rot(E[i]) == E[(i - 4) % 4 + 5]).all()
+
+
+def test_moment_matrix_is_lallemand_luo_polynomials():
+    """SM Eq. (2) rebuilt from the moment polynomials of the cited construction
+    (rho; e = 3|e|^2 - 4; eps = (9|e|^4 - 21|e|^2 + 8)/2; j; q = (3|e|^2 - 5) e; pxx = ex^2 - ey^2;
+    pxy = ex ey) evaluated on the velocity set, and M M^T diagonal."""
+    ex, ey = lbm.EF[:, 0], lbm.EF[:, 1]
+    e2 = ex * ex + ey * ey
+    rows = np.stack([np.ones(9), 3 * e2 - 4, (9 * e2 * e2 - 21 * e2 + 8) / 2, ex, (3 * e2 - 5) * ex,
+                     ey, (3 * e2 - 5) * ey, ex * ex - ey * ey, ex * ey])
+    assert np.array_equal(rows, lbm.M)
+    G = lbm.M @ lbm.M.T
+    assert np.array_equal(G, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]).astype(float))
+
+
+def test_stencil_isotropy():
+    """Eq. (13) weights: sum w e = 0, sum w e e = I, third moment 0 -> isotropic gradient."""
+    w, E = lbm.OMEGA, lbm.EF
+    assert np.allclose((w[:, None] * E).sum(0), 0, atol=0)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, E, E), np.eye(2), rtol=0, atol=1e-15)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, E, E, E), 0, atol=0)
+
+
+def test_pair_force_exact_for_quadratic_density(model):
+    """F_pair = G^2 dx^2 rho grad(rho) exactly when rho is quadratic (interior nodes)."""
+    ny, nx = 24, 20
+    y, x = np.meshgrid(np.arange(ny, dtype=float), np.arange(nx, dtype=float), indexing="ij")
+    rho = 0.2 + 0.003 * x - 0.002 * y + 1e-4 * x * x + 2e-4 * x * y - 5e-5 * y * y
+    gx = 0.003 + 2e-4 * x + 2e-4 * y
+    gy = -0.002 + 2e-4 * x - 1e-4 * y
+    Fx, Fy = lbm.pair_force(model, rho)
+    inner = (slice(1, -1), slice(1, -1))
+    G2 = model.d.G2
+    scale = G2 * rho.max() * max(np.abs(gx).max(), np.abs(gy).max())
+    assert np.allclose(Fx[inner], (G2 * rho * gx)[inner], rtol=0, atol=1e-13 * scale)
+    assert np.allclose(Fy[inner], (G2 * rho * gy)[inner], rtol=0, atol=1e-13 * scale)
+    # and the quadratic term is really there: a forward difference would be off by O(dx)
+    assert np.abs(gx).max() * 1e-3 < 2e-4
+
+
+def test_pair_force_sums_to_zero_on_periodic_domain(model):
+    """Pairwise antisymmetry: sum_x F_pair = 0 (momentum conservation of Eq. (13))."""
+    f = inputs.random_smooth(33, 29, 0.15, model.d.T0, 0.5, 0.0, 0.0, seed=7)
+    Fx, Fy = lbm.pair_force(model, f.rho)
+    scale = np.abs(Fx).sum()
+    assert abs(Fx.sum()) < 1e-14 * scale and abs(Fy.sum()) < 1e-14 * scale
+
+
+# --- equilibria -----------------------------------------------------------------------------
+
+def test_equilibrium_moments_follow_kinetic_theory(model):
+    """f^eq = M^-1 m^eq (SM Eq. (3a)) has density rho, momentum rho u and momentum flux
+    p_LBE I + rho u u with p_LBE = c_s^2 (rho + eta) (Eq. (15)) - the Euler flux."""
+    d = model.d
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.05, 0.3, 50)
+    ux, uy = rng.uniform(-0.1, 0.1, 50), rng.uniform(-0.1, 0.1, 50)
+    T = rng.uniform(0.7, 0.9, 50) * d.Tc
+    st = lbm.init_state(model, rho, ux, uy, T)
+    e = d.c * lbm.EF
+    f = st.f
+    eta = lbm.p_be(model, rho, T) / d.cs ** 2 - rho
+    p_lbe = d.cs ** 2 * (rho + eta)
+    assert np.allclose(f.sum(0), rho, rtol=1e-14)
+    atol1 = 1e-14 * d.c * np.abs(f).max()
+    atol2 = 1e-14 * d.c ** 2 * np.abs(f).max()
+    assert np.allclose(np.einsum("ia,i...->a...", e, f), np.stack([rho * ux, rho * uy]), rtol=0, atol=atol1)
+    Pi = np.einsum("ia,ib,i...->ab...", e, e, f)
+    assert np.allclose(Pi[0, 0], p_lbe + rho * ux * ux, rtol=0, atol=atol2)
+    assert np.allclose(Pi[1, 1], p_lbe + rho * uy * uy, rtol=0, atol=atol2)
+    assert np.allclose(Pi[0, 1], rho * ux * uy, rtol=0, atol=atol2)
+    # p_LBE equals p_BE (closure Eq. (15)) and p_BE - a rho^2 is the EOS of Eq. (17)
+    assert np.allclose(p_lbe - d.a_mf * rho * rho, lbm.p_eos(model, rho, T), rtol=1e-12)
+
+
+def test_energy_equilibrium_moments(model):
+    """g^eq = M^-1 n^eq (SM Eq. (4a)): sum g = rho e_k and energy flux sum e g = rho h_k u with
+    rho h_k = rho e_k + p_BE (enthalpy flux), rho e_k = rho (c_v T + |u|^2 / 2)."""
+    d = model.d
+    rng = np.random.default_rng(4)
+    rho = rng.uniform(0.05, 0.3, 40)
+    ux, uy = rng.uniform(-0.1, 0.1, 40), rng.uniform(-0.1, 0.1, 40)
+    T = rng.uniform(0.7, 0.9, 40) * d.Tc
+    st = lbm.init_state(model, rho, ux, uy, T)
+    rho_ek = rho * (d.cv * T + 0.5 * (ux * ux + uy * uy))
+    rho_hk = rho_ek + lbm.p_be(model, rho, T)
+    e = d.c * lbm.EF
+    assert np.allclose(st.g.sum(0), rho_ek, rtol=1e-14)
+    flux = np.einsum("ia,i...->a...", e, st.g)
+    atol = 1e-14 * d.c * np.abs(st.g).max()
+    assert np.allclose(flux, np.stack([rho_hk * ux, rho_hk * uy]), rtol=0, atol=atol)
+
+
+def test_rest_equilibrium_closed_forms(model):
+    """Hand-derived rest populations for varpi = 1/6 (beta = -12/5), gamma1 = -2, gamma2 = 2:
+    f0 = 4 rho/9 - 22 eta/45, f1..4 = rho/9 + 7 eta/90, f5..8 = rho/36 + 2 eta/45;
+    g0 = rho e_k - 4 C_ref T / 9, g1..8 = C_ref T / 18."""
+    d = model.d
+    rho, T = np.array([0.3, 0.02]), np.array([0.8, 0.8]) * d.Tc
+    st = lbm.init_state(model, rho, 0 * rho, 0 * rho, T)
+    eta = lbm.p_be(model, rho, T) / d.cs ** 2 - rho
+    want_f = [4 * rho / 9 - 22 * eta / 45] + [rho / 9 + 7 * eta / 90] * 4 + [rho / 36 + 2 * eta / 45] * 4
+    assert np.allclose(st.f, np.stack(want_f), rtol=1e-13, atol=1e-17)
+    rho_ek = rho * d.cv * T
+    want_g = [rho_ek - 4 * d.C_ref * T / 9] + [d.C_ref * T / 18] * 8
+    assert np.allclose(st.g, np.stack(want_g), rtol=1e-13)
+
+
+# --- the step ---------------------------------------------------------------------------------
+
+def _random_state(model, nx=21, ny=17, seed=11):
+    d = model.d
+    f = inputs.random_smooth(nx, ny, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.8, 0.05 * d.cs, 0.05, seed=seed)
+    return lbm.init_state(model, *f.as_tuple())
+
+
+def test_conservation_each_step(model):
+    """P8: mass and momentum invariant (no external acceleration); the energy DF obeys
+    sum_g(t + dt) = sum_g(t) + dt sum_x q(t) (row 0 of Eq. (12c))."""
+    st = _random_state(model)
+    inv0 = lbm.invariants(model, st)
+    for _ in range(15):
+        before = lbm.invariants(model, st)
+        st = lbm.step(model, st)
+        after = lbm.invariants(model, st)
+        assert abs(after["mass"] / inv0["mass"] - 1) < 1e-14
+        mom_scale = model.d.c * st.f.sum()
+        assert abs(after["mom_x"] - inv0["mom_x"]) < 1e-13 * mom_scale
+        assert abs(after["mom_y"] - inv0["mom_y"]) < 1e-13 * mom_scale
+        assert abs(after["sum_g"] - (before["sum_g"] + before["dt_sum_q"])) < 1e-13 * abs(before["sum_g"])
+
+
+def test_momentum_changes_by_external_force(model):
+    """With an acceleration a, total momentum grows by dt * sum(rho) a each step (Eq. (14))."""
+    p = thermo.Params(accel_x=1e-4, accel_y=-2e-4)
+    m2 = lbm.Model(model.eos, model.d, p)
+    st = _random_state(m2)
+    mass = st.f.sum()
+    i0 = lbm.invariants(m2, st)
+    st = lbm.run(m2, st, 3)
+    i1 = lbm.invariants(m2, st)
+    assert abs((i1["mom_x"] - i0["mom_x"]) / (3 * m2.d.dt * mass * 1e-4) - 1) < 1e-9
+    assert abs((i1["mom_y"] - i0["mom_y"]) / (3 * m2.d.dt * mass * -2e-4) - 1) < 1e-9
+
+
+@pytest.mark.parametrize("u", [(0.0, 0.0), (0.03, -0.02)])
+def test_uniform_state_is_steady(model, u):
+    """P9: a uniform state at rest or in uniform motion is an exact fixed point."""
+    d = model.d
+    f = inputs.uniform(8, 6, d.rho_l, d.T0, u[0] * d.c, u[1] * d.c)
+    st0 = lbm.init_state(model, *f.as_tuple())
+    st = lbm.run(model, st0, 5)
+    assert np.allclose(st.f, st0.f, rtol=0, atol=1e-15)
+    assert np.allclose(st.g, st0.g, rtol=0, atol=1e-15)
+
+
+def _rot90_state(st: lbm.State) -> lbm.State:
+    """Rotate the whole lattice state by +90 degrees: node (x, y) -> (-y, x); population i
+    goes to the rotated velocity (1->2->3->4->1, 5->6->7->8->5)."""
+    perm = [0, 2, 3, 4, 1, 6, 7, 8, 5]
+
+    def rot(p):
+        out = np.empty_like(p)
+        for i in range(9):
+            # new[y', x'] with x' = -y, y' = x  ->  new[x, -y] = old[y, x]
+            out[perm[i]] = np.rot90(p[i], k=1, axes=(1, 0))
+        return out
+    return lbm.State(rot(st.f), rot(st.g), st.step)
+
+
+def _flipx_state(st: lbm.State) -> lbm.State:
+    perm = [0, 3, 2, 1, 4, 6, 5, 8, 7]
+
+    def fl(p):
+        out = np.empty_like(p)
+        for i in range(9):
+            out[perm[i]] = p[i][:, ::-1]
+        return out
+    return lbm.State(fl(st.f), fl(st.g), st.step)
+
+
+def test_rotation_and_reflection_equivariance(model):
+    """P10: stepping commutes with a quarter turn and with the x-reflection of the lattice.
+    This is what catches a sign or index error in the velocity-dependent entries of S and Y."""
+    st0 = _random_state(model, 18, 18, seed=5)
+    n = 6
+    a = _rot90_state(lbm.run(model, st0, n))
+    b = lbm.run(model, _rot90_state(st0), n)
+    assert np.allclose(a.f, b.f, rtol=0, atol=1e-13 * np.abs(a.f).max())
+    assert np.allclose(a.g, b.g, rtol=0, atol=1e-13 * np.abs(a.g).max())
+    a = _flipx_state(lbm.run(model, st0, n))
+    b = lbm.run(model, _flipx_state(st0), n)
+    assert np.allclose(a.f, b.f, rtol=0, atol=1e-13 * np.abs(a.f).max())
+    assert np.allclose(a.g, b.g, rtol=0, atol=1e-13 * np.abs(a.g).max())
+
+
+def test_translation_invariance(model):
+    st0 = _random_state(model, 16, 12, seed=9)
+    sh = lambda p: np.roll(p, shift=(3, -5), axis=(1, 2))
+    a = lbm.run(model, lbm.State(sh(st0.f), sh(st0.g)), 4)
+    b = lbm.run(model, st0, 4)
+    assert np.array_equal(a.f, sh(b.f)) and np.array_equal(a.g, sh(b.g))
+
+
+def _shear_run(model, steps=200, ny=64):
+    d = model.d
+    f = inputs.shear_wave(1, ny, d.rho_v, d.T0, 0.02)
+    st = lbm.init_state(model, *f.as_tuple())
+    k = 2 * np.pi / ny
+    y = np.arange(ny)
+    amps = []
+    for n in range(steps + 1):
+        rho, ux, uy, T = lbm.moments(model, st)
+        amps.append(2 * np.mean(ux[:, 0] * np.sin(k * y)))
+        if n < steps:
+            st = lbm.step(model, st)
+    return np.array(amps), T[:, 0], k
+
+
+def test_shear_wave_decays_with_paper_viscosity(model):
+    """nu = c_s^2 dt (1/s_p - 1/2) (text after Eq. (15)): a transverse wave decays as
+    exp(-nu k^2 t).  Lattice dispersion at k = 2 pi / 64 leaves ~1e-3."""
+    d = model.d
+    amps, _, k = _shear_run(model)
+    t = np.arange(len(amps)) * d.dt
+    rate = -np.polyfit(t[20:], np.log(amps[20:]), 1)[0]
+    nu = d.cs ** 2 * d.dt * (1 / d.s_p - 0.5)
+    assert abs(rate / k ** 2 / nu - 1) < 3e-3
+
+
+def test_viscous_heating_appears_where_shear_is_largest(model):
+    """The Y term of Eq. (12c) (SM Eq. (6b)) carries the viscous dissipation: a decaying shear
+    wave u = U sin(ky) heats the fluid as cos^2(ky), so the cos(2ky) mode of T is positive and
+    close to the incompressible estimate; without (or with a wrongly signed) Y it is negative."""
+    d = model.d
+    amps, T, k = _shear_run(model)
+    y = np.arange(len(T))
+    T2 = 2 * np.mean((T - T.mean()) * np.cos(2 * k * y))
+    nu = d.cs ** 2 * d.dt * (1 / d.s_p - 0.5)
+    lam = (4 + 3 * model.params.gamma1 + 2 * model.params.gamma2) / 6 * d.C_ref * d.c ** 2 * d.dt * d.tau_j_v
+    alpha = lam / (d.rho_v * d.cv)
+    A = amps[0] ** 2 * nu * k ** 2 / (2 * d.cv)
+    t = (len(amps) - 1) * d.dt
+    pred = A * (np.exp(-2 * nu * k ** 2 * t) - np.exp(-4 * alpha * k ** 2 * t)) / (4 * alpha * k ** 2 - 2 * nu * k ** 2)
+    assert 0.8 < T2 / pred < 1.1
+    # all kinetic energy lost reappears as heat (sum g conserved when q = 0)
+    assert abs((T.mean() - d.T0) / ((amps[0] ** 2 - amps[-1] ** 2) / (4 * d.cv)) - 1) < 2e-3
+
+
+def _slab_run(model, table, ny=64, steps=12000):
+    d = model.d
+    z, r = table
+    y = np.arange(ny, dtype=float)
+    dist = np.abs(y - (ny - 1) / 2) - ny / 4
+    rho = np.interp(dist, z, r)[:, None]
+    st = lbm.init_state(model, rho, 0 * rho, 0 * rho, 0 * rho + d.T0)
+    st = lbm.run(model, st, steps)
+    return lbm.moments(model, st)
+
+
+@pytest.mark.slow
+def test_flat_interface_coexistence_matches_maxwell(model, profile_table):
+    """P11 (thermodynamic consistency): a flat liquid slab equilibrates to the Maxwell
+    densities of p_EOS at its own bulk temperature (reading: T drifts from T0 as latent
+    heat moves; compare at the measured bulk T), and the 5%-95% interface width to the
+    prescribed W = 10 (the paper's own LB measurement gave 9.961104)."""
+    rho, ux, uy, T = _slab_run(model, profile_table)
+    ny = rho.shape[0]
+    rl, rv = rho[ny // 2, 0], rho[0, 0]
+    Tb = 0.5 * (T[ny // 2, 0] + T[0, 0])
+    mv, ml, _ = thermo.maxwell(model.eos, Tb)
+    assert abs(rl / float(ml) - 1) < 1e-3
+    assert abs(rv / float(mv) - 1) < 1e-3
+    half = rho[: ny // 2 + 1, 0]
+    ys = np.arange(len(half))
+    W = np.interp(rv + 0.95 * (rl - rv), half, ys) - np.interp(rv + 0.05 * (rl - rv), half, ys)
+    assert abs(W / 10.0 - 1) < 0.01
+    assert np.abs(uy).max() < 1e-5 * model.d.cs
+
+
+# --- mutation checks: plant mistakes in the oracle and show a pin catches each ---------------
+
+def test_mutation_sign_in_S_breaks_equivariance(model, monkeypatch):
+    orig = lbm.s_matrix
+
+    def bad(m, ux, uy):
+        S = orig(m, ux, uy)
+        S[7, 6] = -S[7, 6]
+        return S
+    monkeypatch.setattr(lbm, "s_matrix", bad)
+    st0 = _random_state(model, 14, 14, seed=5)
+    a = _rot90_state(lbm.run(model, st0, 4))
+    b = lbm.run(model, _rot90_state(st0), 4)
+    assert not np.allclose(a.f, b.f, rtol=0, atol=1e-13 * np.abs(a.f).max())
+
+
+def test_mutation_missing_Y_flips_heating(model, monkeypatch):
+    orig = lbm.y_matrix
+    monkeypatch.setattr(lbm, "y_matrix", lambda ux, uy: 0 * orig(ux, uy))
+    amps, T, k = _shear_run(model)
+    y = np.arange(len(T))
+    assert 2 * np.mean((T - T.mean()) * np.cos(2 * k * y)) < 0
+
+
+def test_mutation_transposed_inverse_breaks_equilibrium(model, monkeypatch):
+    monkeypatch.setattr(lbm, "MINV", np.ascontiguousarray(lbm.MINV.T))
+    with pytest.raises(AssertionError):
+        test_equilibrium_moments_follow_kinetic_theory(model)
+
+
+def test_mutation_missing_Qm_shifts_width(model, profile_table, monkeypatch):
+    """Without the third-order compensation S Q_m the interface is visibly off within a few
+    hundred steps (a much shorter run than the full coexistence pin)."""
+    ref = _slab_run(model, profile_table, steps=400)[0][:, 0]
+    orig = lbm.q_comp
+    monkeypatch.setattr(lbm, "q_comp", lambda m, gx, gy: 0 * orig(m, gx, gy))
+    bad = _slab_run(model, profile_table, steps=400)[0][:, 0]
+    assert np.abs(bad - ref).max() > 1e-3 * ref.max()
