@@ -1,0 +1,194 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) lattice Boltzmann update for the
+ * liquid-vapour phase transition of Huang, Wu & Adams (arXiv 2106.01557).
+ *
+ * One call of lbm_step() advances the double-distribution D2Q9 model by whole
+ * time steps: streaming Eq. (12a), the moment-space collisions Eqs. (12b)-(12c)
+ * with the matrices of SM Eqs. (2)-(6), the pairwise interaction force Eq. (13),
+ * the moment sums Eq. (14), and the closure Eqs. (15)-(17) (built-in variable
+ * eta from the dense-gas equation of state).  The lattice is periodic in x and y.
+ *
+ * Conventions shared by every call
+ *  - Every function returns int: LBM_OK (0) or a negative LBM_E* code.  Nothing
+ *    aborts or throws across the ABI.  lbm_last_error() holds a message.
+ *  - Fields are row-major [ny][nx] (x fastest), one value per node, FP64.
+ *  - Device pointers are HIP device addresses on the device that was current
+ *    when lbm_init() ran.  The library never allocates device memory: the
+ *    caller passes a workspace of at least lbm_workspace_bytes() bytes and keeps
+ *    it alive until lbm_destroy().  Host memory for the context itself is owned
+ *    by the library.
+ *  - All device work is enqueued on the stream given to lbm_init() (NULL = the
+ *    default stream) and is asynchronous unless marked "synchronising".  Device
+ *    faults surface as LBM_EHIP at the next synchronising call.
+ *  - Units are the paper's lattice units (dx = 1 by default, R = 1); the time
+ *    step dt is derived from Eq. (19) and reported by lbm_derived().
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes --------------------------------------------------------- */
+#define LBM_OK          0
+#define LBM_EINVAL     (-1)  /* bad parameter, shape or pointer                          */
+#define LBM_ESPACE     (-2)  /* workspace too small                                      */
+#define LBM_EHIP       (-3)  /* HIP runtime error (launch failure, device fault, ...)     */
+#define LBM_ENONFINITE (-4)  /* state check found NaN/Inf, rho <= 0, T <= 0 or a packing
+                                fraction >= 1                                            */
+#define LBM_ESTATE     (-5)  /* call out of order (e.g. lbm_step before lbm_set_fields,
+                                or a device call on a host-only context)                 */
+
+/* ---- equation of state kinds (p_EOS of the text after Eq. (11)) --------- */
+#define LBM_EOS_CS  0  /* Eq. (17): K[rho R T (1+t+t^2-t^3)/(1-t)^3 - a rho^2], t = b rho/4 */
+#define LBM_EOS_VDW 1  /* K[rho R T / (1 - b rho) - a rho^2]                             */
+
+/* ---- storage precision of the distributions (arithmetic is FP64 for F64 and
+ *      FP32 otherwise) ------------------------------------------------------ */
+#define LBM_F64  0
+#define LBM_F32  1
+#define LBM_F16  2  /* FP16 deviations from the rest equilibrium of (rho0, T0)      */
+#define LBM_BF16 3  /* BF16 deviations from the rest equilibrium of (rho0, T0)      */
+
+/* ---- update schemes ------------------------------------------------------- */
+#define LBM_SCHEME_AB 0  /* fused single pass, two state buffers (push streaming)      */
+#define LBM_SCHEME_AA 1  /* in-place AA pattern, one state buffer, plus a density pass */
+
+typedef struct lbm_ctx lbm_ctx;   /* opaque; owned by the library */
+
+/* Lattice: D2Q9 velocities of SM Eq. (1), periodic in both directions. */
+typedef struct {
+    int32_t nx, ny;   /* nodes, each >= 1 and nx*ny < 2^31                           */
+    double  dx;       /* lattice spacing delta_x (> 0; the paper uses 1)              */
+} lbm_lattice;
+
+/* Equation of state, Eq. (17).  For LBM_EOS_CS, a_t and b_t are a~ and b~ (Tc, pc
+ * follow from their definitions under Eq. (17)); for LBM_EOS_VDW they are a and b. */
+typedef struct {
+    int32_t kind;                    /* LBM_EOS_CS or LBM_EOS_VDW                   */
+    double  a_t, b_t, R, K_eos;      /* all > 0                                      */
+} lbm_eos;
+
+/* Model parameters (text before Eq. (20), SM Eqs. (3)-(5)).  Fields marked
+ * "reading" are not fixed by the paper; their defaults are set by
+ * lbm_default_params(). */
+typedef struct {
+    double Tr0;           /* reference reduced temperature T0/Tc: sets rho_l in Eq. (19) and
+                             the density range of the conductivity interpolation       */
+    double K_int;         /* K_INT of Eqs. (18)-(19)                                    */
+    double varpi;         /* model coefficient (SM Eq. (3), (5a)), 0 < varpi < 1/3      */
+    double gamma1, gamma2;/* model coefficients (SM Eq. (4))                            */
+    double tau_p;         /* tau_p = 1/s_p - 1/2 > 0; s_q, s_e follow from
+                             tau_p tau_q = (k+1) tau_e tau_q = 1/12 (after SM Eq. (5b)) */
+    double s_eps;         /* reading                                                    */
+    double sigma_e, sigma_eps, sigma_q, sigma_p; /* L entries (SM Eq. (5b)); reading    */
+    double tau_j_v;       /* vapour tau_j = 1/sigma_j - 1/2 (reading)                   */
+    double lambda_ratio;  /* lambda_l / lambda_v; tau_j is linear in rho between the
+                             coexistence densities at T0 and clamped outside (reading) */
+    double cv;            /* specific heat; <= 0: derived from ste and dTr_ste          */
+    double ste, dTr_ste;  /* Stefan number and T_r1 - T_r0 used to derive cv (reading) */
+    double C_ref;         /* reference volumetric heat capacity; <= 0: rho_v * cv       */
+    double accel_x, accel_y; /* external acceleration a of Eq. (14)                     */
+    double cs_override;   /* > 0: use this lattice sound speed instead of Eq. (19)      */
+    double rho_ref, T_ref;/* deviation reference for LBM_F16/LBM_BF16 storage;
+                             <= 0: rho = (rho_v + rho_l)/2 and T = T0                   */
+    int32_t precision;    /* LBM_F64, LBM_F32, LBM_F16, LBM_BF16                        */
+    int32_t scheme;       /* LBM_SCHEME_AB or LBM_SCHEME_AA                             */
+    int32_t rows_per_wave;/* rows one wavefront marches through per launch; 0 = auto    */
+    int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = auto                                 */
+} lbm_params;
+
+/* Fills *p with the paper's numerical-test parameters (varpi = 1/6, gamma1 = -2,
+ * gamma2 = 2, T_r0 = 0.8, K_INT = 2.294922, lambda_l = 10 lambda_v) and the
+ * readings listed above; precision LBM_F64, scheme LBM_SCHEME_AB.  Never fails
+ * for a non-NULL p. */
+int lbm_default_params(lbm_params* p);
+
+/* Fills *e with the paper's Carnahan-Starling set (a~ = 1, b~ = 4, R = 1,
+ * K_EOS = 0.479820), text before Eq. (20). */
+int lbm_default_eos(lbm_eos* e);
+
+/* Device workspace needed for this lattice and these parameters (state buffers,
+ * a density scratch array and reduction partials).  LBM_EINVAL on bad input. */
+int lbm_workspace_bytes(const lbm_lattice* lat, const lbm_params* p, size_t* bytes);
+
+/* Validates everything (LBM_EINVAL with a message on any bad value, before any
+ * HIP call), derives the per-run constants (Maxwell coexistence at T0, c_s of
+ * Eq. (19), dt = dx/c with c = sqrt(3) c_s, G^2 of Eq. (18), a and kappa of
+ * Eq. (16), relaxation rates, cv, C_ref) and binds the caller's workspace and
+ * stream.  workspace == NULL creates a host-only context whose constants can be
+ * queried with lbm_derived() but which refuses device calls (LBM_ESTATE).
+ * Otherwise workspace must be device memory of at least lbm_workspace_bytes()
+ * bytes, 256-byte aligned (LBM_ESPACE / LBM_EINVAL).  On success *out owns a new
+ * context; on failure *out is NULL and the message is available through
+ * lbm_last_error(NULL). */
+int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos,
+             const lbm_params* p, void* workspace, size_t workspace_bytes,
+             void* hip_stream);
+
+/* Sets the state from macroscopic fields (device FP64 arrays [ny][nx]; u is
+ * the velocity in lattice units, T the temperature): f = M^-1 m^eq and
+ * g = M^-1 n^eq of SM Eqs. (3a), (4a) with rho e_k = rho (cv T + |u|^2/2),
+ * eta and rho h_k from the closure Eq. (15) (reading: no force shift at t = 0).
+ * Resets the step counter to 0.  Asynchronous. */
+int lbm_set_fields(lbm_ctx* ctx, const double* rho, const double* ux,
+                   const double* uy, const double* T);
+
+/* Advances n >= 0 time steps.  Asynchronous; launches only (no host sync). */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Writes rho, u and T at the current time (Eq. (14); u includes the dt/2 F
+ * correction, T from rho e_k = rho cv T + rho |u|^2/2) into caller-owned device
+ * FP64 arrays [ny][nx].  Any of ux, uy, T may be NULL; rho may not (it also
+ * serves as scratch for the force stencil).  Asynchronous. */
+int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* T);
+
+/* Global diagnostics in FP64, reduced on the device in a fixed order
+ * (deterministic), then copied to host (synchronising):
+ *   out[0] mass            sum_x sum_i f_i                    (exact invariant)
+ *   out[1] momentum x      sum_x sum_i e_ix f_i               (invariant if a = 0)
+ *   out[2] momentum y
+ *   out[3] sum_g           sum_x sum_i g_i; obeys sum_g(t+dt) = sum_g(t) + out[4]
+ *   out[4] dt sum_x q      (row 0 of Eq. (12c))
+ *   out[5] E_p             -(G^2 dx^2/2) sum_x [rho^2/6 + rho/2 sum_i w_i rho(x+e_i dx)]
+ *   out[6] sum_x rho e_k
+ *   out[7] number of nodes failing the state check (NaN/Inf, rho <= 0, T <= 0,
+ *          packing fraction >= 1); when > 0 the call returns LBM_ENONFINITE.
+ * n_out must be >= 8. */
+int lbm_invariants(lbm_ctx* ctx, double* out, int n_out);
+
+/* Per-run constants, in this order (n <= 26 values are written):
+ *  0 Tc   1 pc   2 T0   3 rho_v  4 rho_l  5 p_s   6 c_s  7 c   8 dt   9 G^2
+ * 10 a   11 kappa 12 cv 13 C_ref 14 beta 15 k  16 h  17 b (SM Eq. (5a))
+ * 18 s_p 19 s_q 20 s_e 21 omega_e 22 omega_p 23 tau_j_v 24 tau_j_l 25 h_lv */
+int lbm_derived(const lbm_ctx* ctx, double* out, int n);
+
+/* Number of completed steps since lbm_set_fields(). */
+int lbm_step_count(const lbm_ctx* ctx, int64_t* steps);
+
+/* Raw state copy for checkpoint/restart: the distributions in storage
+ * precision, in the layout of the current step (scheme and parity included),
+ * to/from caller device memory of lbm_state_bytes() bytes.  Restoring a saved
+ * state and stepping is bitwise identical to never having stopped. */
+int lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
+int lbm_save_state(lbm_ctx* ctx, void* dst_device, int64_t* steps);
+int lbm_load_state(lbm_ctx* ctx, const void* src_device, int64_t steps);
+
+/* Releases the context (never the caller's workspace).  NULL is allowed. */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Static description of a code; never NULL. */
+const char* lbm_strerror(int code);
+
+/* Message of the last failing call on ctx (or of the last failed lbm_init when
+ * ctx is NULL); empty string when there is none.  Valid until the next call. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

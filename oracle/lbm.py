@@ -63,7 +63,10 @@ M = np.array([
     [0, 1, -1, 1, -1, 0, 0, 0, 0],
     [0, 0, 0, 0, 0, 1, -1, 1, -1],
 ], dtype=np.float64)
-MINV = np.linalg.inv(M)
+# M is orthogonal (SM Eq. (2)): M M^T = D = diag(9, 36, 36, 6, 12, 6, 12, 4, 4), so
+# M^-1 = M^T D^-1 exactly, with every entry a correctly rounded k/D_j.  (A numerical
+# inverse misses this by an ulp or so, enough to leak mass from the momentum rows.)
+MINV = M.T / np.diag(M @ M.T)[None, :]
 
 # --- Eq. (13): omega(|e_i dt|^2) = 1/3 on axes, 1/12 on diagonals --------------------
 OMEGA = np.array([0.0] + [1.0 / 3.0] * 4 + [1.0 / 12.0] * 4)

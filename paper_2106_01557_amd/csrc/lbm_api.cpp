@@ -1,0 +1,497 @@
+// C ABI of the liquid-vapour lattice Boltzmann library (declared in include/lbm.h).
+#include "../../include/lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm_internal.hpp"
+#include "thermo.hpp"
+
+using lbm_dev::Consts;
+
+struct lbm_ctx {
+    lbm_lattice lat;
+    lbm_eos eos;
+    lbm_params p;
+    double derived[26];
+    Consts<double> c64;
+    Consts<float> c32;
+    const void* consts;       // &c64 or &c32 depending on precision
+    bool host_only;
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    void* buf[2];
+    size_t state_bytes;
+    double* rho_scratch;
+    double* partials;
+    double* result;
+    int cur;
+    bool fields_set;
+    int64_t steps;
+    lbm_dev::LaunchShape shape;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+int fail(lbm_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_init_error = buf;
+    return code;
+}
+
+int hip_fail(lbm_ctx* ctx, hipError_t e, const char* what) {
+    return fail(ctx, LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int check_lattice(const lbm_lattice* lat) {
+    if (!lat) return fail(nullptr, LBM_EINVAL, "lattice is NULL");
+    if (lat->nx < 1 || lat->ny < 1)
+        return fail(nullptr, LBM_EINVAL, "nx and ny must be >= 1 (got %d x %d)", lat->nx, lat->ny);
+    if ((int64_t)lat->nx * lat->ny > 0x7fffffffLL)
+        return fail(nullptr, LBM_EINVAL, "nx * ny must be < 2^31 (got %lld)", (long long)lat->nx * lat->ny);
+    if (!finite_pos(lat->dx)) return fail(nullptr, LBM_EINVAL, "dx must be finite and > 0");
+    return LBM_OK;
+}
+
+int check_params(const lbm_params* p) {
+    if (!p) return fail(nullptr, LBM_EINVAL, "params is NULL");
+    if (!(p->Tr0 > 0 && p->Tr0 < 1)) return fail(nullptr, LBM_EINVAL, "Tr0 must lie in (0, 1) (got %g)", p->Tr0);
+    if (!finite_pos(p->K_int)) return fail(nullptr, LBM_EINVAL, "K_int must be > 0");
+    if (!(p->varpi > 0 && p->varpi < 1.0 / 3.0))
+        return fail(nullptr, LBM_EINVAL, "varpi must lie in (0, 1/3) (got %g)", p->varpi);
+    if (!std::isfinite(p->gamma1) || !std::isfinite(p->gamma2))
+        return fail(nullptr, LBM_EINVAL, "gamma1 and gamma2 must be finite");
+    if (!finite_pos(p->tau_p)) return fail(nullptr, LBM_EINVAL, "tau_p must be > 0 (got %g)", p->tau_p);
+    const double rates[5] = {p->s_eps, p->sigma_e, p->sigma_eps, p->sigma_q, p->sigma_p};
+    const char* names[5] = {"s_eps", "sigma_e", "sigma_eps", "sigma_q", "sigma_p"};
+    for (int i = 0; i < 5; ++i)
+        if (!(rates[i] > 0 && rates[i] < 2))
+            return fail(nullptr, LBM_EINVAL, "%s must lie in (0, 2) (got %g)", names[i], rates[i]);
+    if (!finite_pos(p->tau_j_v)) return fail(nullptr, LBM_EINVAL, "tau_j_v must be > 0");
+    if (!finite_pos(p->lambda_ratio)) return fail(nullptr, LBM_EINVAL, "lambda_ratio must be > 0");
+    if (!std::isfinite(p->cv) || !std::isfinite(p->C_ref))
+        return fail(nullptr, LBM_EINVAL, "cv and C_ref must be finite");
+    if (p->cv <= 0 && !(finite_pos(p->ste) && finite_pos(p->dTr_ste)))
+        return fail(nullptr, LBM_EINVAL, "cv <= 0 needs ste > 0 and dTr_ste > 0 to derive it");
+    if (!std::isfinite(p->accel_x) || !std::isfinite(p->accel_y))
+        return fail(nullptr, LBM_EINVAL, "acceleration must be finite");
+    if (!std::isfinite(p->cs_override) || p->cs_override < 0)
+        return fail(nullptr, LBM_EINVAL, "cs_override must be >= 0");
+    if (!std::isfinite(p->rho_ref) || !std::isfinite(p->T_ref))
+        return fail(nullptr, LBM_EINVAL, "rho_ref and T_ref must be finite");
+    if (p->precision < LBM_F64 || p->precision > LBM_BF16)
+        return fail(nullptr, LBM_EINVAL, "unknown precision %d", p->precision);
+    if (p->scheme != LBM_SCHEME_AB && p->scheme != LBM_SCHEME_AA)
+        return fail(nullptr, LBM_EINVAL, "unknown scheme %d", p->scheme);
+    if (p->rows_per_wave < 0 || p->rows_per_wave > 65536)
+        return fail(nullptr, LBM_EINVAL, "rows_per_wave must lie in [0, 65536]");
+    const int w = p->waves_per_block;
+    if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8))
+        return fail(nullptr, LBM_EINVAL, "waves_per_block must be 0, 1, 2, 4 or 8 (got %d)", w);
+    return LBM_OK;
+}
+
+int check_eos(const lbm_eos* e) {
+    if (!e) return fail(nullptr, LBM_EINVAL, "eos is NULL");
+    if (e->kind != LBM_EOS_CS && e->kind != LBM_EOS_VDW)
+        return fail(nullptr, LBM_EINVAL, "unknown EOS kind %d", e->kind);
+    if (!finite_pos(e->a_t) || !finite_pos(e->b_t) || !finite_pos(e->R) || !finite_pos(e->K_eos))
+        return fail(nullptr, LBM_EINVAL, "EOS a_t, b_t, R and K_eos must be finite and > 0");
+    return LBM_OK;
+}
+
+size_t state_buffer_bytes(const lbm_lattice* lat, const lbm_params* p) {
+    return round256((size_t)18 * lat->nx * lat->ny * lbm_dev::storage_bytes(p->precision));
+}
+
+// Rest equilibria M^-1 m^eq and M^-1 n^eq (SM Eqs. (3a), (4a) with u = 0): the
+// 16-bit storage formats keep deviations from these.
+void rest_populations(const lbm_ctx* c, double rho, double T, double* f, double* g) {
+    static const int M1[9] = {-4, -1, -1, -1, -1, 2, 2, 2, 2};
+    static const int M2[9] = {4, -2, -2, -2, -2, 1, 1, 1, 1};
+    const double cs2 = c->derived[6] * c->derived[6];
+    lbm_host::Eos e{c->eos.kind, c->eos.a_t, c->eos.b_t, c->eos.R, c->eos.K_eos};
+    const double pbe = (double)lbm_host::pressure(e, rho, T) + c->derived[10] * rho * rho;
+    const double eta = pbe / cs2 - rho, beta = c->derived[14];
+    const double m1 = -2 * rho + 2 * eta, m2 = rho + beta * eta;
+    const double rek = rho * c->derived[12] * T, cref = c->derived[13];
+    const double n1 = -4 * rek + (4 + c->p.gamma1) * cref * T, n2 = 4 * rek - (4 - c->p.gamma2) * cref * T;
+    for (int i = 0; i < 9; ++i) {
+        f[i] = rho / 9 + M1[i] * m1 / 36 + M2[i] * m2 / 36;
+        g[i] = rek / 9 + M1[i] * n1 / 36 + M2[i] * n2 / 36;
+    }
+}
+
+template <typename C>
+void fill_consts(const lbm_ctx* c, Consts<C>* k) {
+    const double* d = c->derived;
+    const double dx = c->lat.dx;
+    std::memset(k, 0, sizeof *k);
+    k->nx = c->lat.nx;
+    k->ny = c->lat.ny;
+    k->eos_kind = c->eos.kind;
+    const double G2 = d[9], cs = d[6], cc = d[7], dt = d[8];
+    k->G2dx = (C)(G2 * dx);
+    k->inv_dx = (C)(1.0 / dx);
+    k->ax = (C)c->p.accel_x;
+    k->ay = (C)c->p.accel_y;
+    k->c = (C)cc;
+    k->inv_c = (C)(1.0 / cc);
+    k->c2 = (C)(cc * cc);
+    k->dt = (C)dt;
+    k->hdt = (C)(0.5 * dt);
+    k->hdt_c = (C)(0.5 * dt / cc);
+    k->cv = (C)d[12];
+    k->inv_cv = (C)(1.0 / d[12]);
+    k->C_ref = (C)d[13];
+    k->KR = (C)(c->eos.K_eos * c->eos.R);
+    k->Ka = (C)(c->eos.K_eos * c->eos.a_t);
+    k->bq = (C)(c->eos.kind == LBM_EOS_CS ? 0.25 * c->eos.b_t : c->eos.b_t);
+    k->a_diff = (C)(d[10] - c->eos.K_eos * c->eos.a_t);
+    k->inv_cs2 = (C)(1.0 / (cs * cs));
+    k->beta = (C)d[14];
+    k->g1C = (C)((4 + c->p.gamma1) * d[13]);
+    k->g2C = (C)((4 - c->p.gamma2) * d[13]);
+    k->gamma1 = (C)c->p.gamma1;
+    k->gamma2 = (C)c->p.gamma2;
+    const double s_p = d[18], s_q = d[19], s_e = d[20], om_e = d[21], om_p = d[22];
+    k->s_e = (C)s_e;
+    k->s_eps = (C)c->p.s_eps;
+    k->s_q = (C)s_q;
+    k->s_p = (C)s_p;
+    k->ks = (C)(d[15] * c->p.s_eps * om_e);
+    k->hs = (C)(d[16] * s_q * om_e);
+    k->bs = (C)(d[17] * s_q * om_p);
+    k->sig_e = (C)c->p.sigma_e;
+    k->sig_eps = (C)c->p.sigma_eps;
+    k->sig_q = (C)c->p.sigma_q;
+    k->sig_p = (C)c->p.sigma_p;
+    k->rho_v = (C)d[3];
+    k->inv_drho = (C)(1.0 / (d[4] - d[3]));
+    k->tau_jv = (C)d[23];
+    k->dtau_j = (C)(d[24] - d[23]);
+    k->Qpre = (C)(G2 * dx * dx * dt * dt / 12.0);
+    k->Ep_pre = (C)(-0.5 * G2 * dx * dx);
+    if (c->p.precision == LBM_F16 || c->p.precision == LBM_BF16) {
+        const double rho_ref = c->p.rho_ref > 0 ? c->p.rho_ref : 0.5 * (d[3] + d[4]);
+        const double T_ref = c->p.T_ref > 0 ? c->p.T_ref : d[2];
+        double f[9], g[9];
+        rest_populations(c, rho_ref, T_ref, f, g);
+        for (int i = 0; i < 9; ++i) {
+            k->ref_f[i] = (C)f[i];
+            k->ref_g[i] = (C)g[i];
+        }
+    }
+}
+
+int derive(lbm_ctx* c) {
+    lbm_host::Eos e{c->eos.kind, c->eos.a_t, c->eos.b_t, c->eos.R, c->eos.K_eos};
+    long double Tc, pc;
+    lbm_host::critical(e, &Tc, &pc);
+    const long double T0 = (long double)c->p.Tr0 * Tc;
+    long double rv, rl, ps;
+    std::string why;
+    if (!lbm_host::coexistence(e, T0, &rv, &rl, &ps, &why))
+        return fail(nullptr, LBM_EINVAL, "coexistence at Tr0 = %g: %s", c->p.Tr0, why.c_str());
+    const long double dx = c->lat.dx;
+    const long double Kint = c->p.K_int;
+    const long double G2 = Kint * Kint * 2.0L * e.K * e.a / (dx * dx);           // Eq. (18)
+    long double cs;
+    if (c->p.cs_override > 0) {
+        cs = c->p.cs_override;
+    } else {
+        const long double arg = lbm_host::pressure_slope(e, rl, T0) + 2.0L * e.K * e.a * rl;  // Eq. (19)
+        if (!(arg > 0)) return fail(nullptr, LBM_EINVAL, "Eq. (19) gives a non-positive c_s^2");
+        cs = Kint * std::sqrt(arg);
+    }
+    const long double cc = std::sqrt(3.0L) * cs, dt = dx / cc;
+    const long double a_mf = G2 * dx * dx / 2, kappa = G2 * dx * dx * dx * dx / 4;  // Eq. (16)
+    const long double h_lv = a_mf * (rl - rv) + ps * (1.0L / rv - 1.0L / rl);
+    long double cv = c->p.cv;
+    if (!(cv > 0)) cv = (long double)c->p.ste * rl * h_lv / (rv * Tc * (long double)c->p.dTr_ste);
+    const long double Cref = c->p.C_ref > 0 ? (long double)c->p.C_ref : rv * cv;
+    const long double w = c->p.varpi;
+    const long double beta = -2.0L / (1 - w), k = 1 - w;
+    const long double h = 6 * w * (1 - w) / (1 - 3 * w), bS = (1 - w) / (1 - 3 * w);
+    const long double tau_p = c->p.tau_p;
+    const long double tau_q = 1.0L / (12.0L * tau_p);          // tau_p tau_q = 1/12
+    const long double tau_e = 1.0L / (12.0L * (k + 1) * tau_q); // (k+1) tau_e tau_q = 1/12
+    const long double s_p = 1 / (tau_p + 0.5L), s_q = 1 / (tau_q + 0.5L), s_e = 1 / (tau_e + 0.5L);
+    const long double vals[26] = {Tc, pc, T0, rv, rl, ps, cs, cc, dt, G2, a_mf, kappa, cv, Cref,
+                                  beta, k, h, bS, s_p, s_q, s_e, s_e / 2 - 1, s_p / 2 - 1,
+                                  c->p.tau_j_v, c->p.tau_j_v * c->p.lambda_ratio, h_lv};
+    for (int i = 0; i < 26; ++i) {
+        c->derived[i] = (double)vals[i];
+        if (!std::isfinite(c->derived[i])) return fail(nullptr, LBM_EINVAL, "derived constant %d is not finite", i);
+    }
+    return LBM_OK;
+}
+
+int need_device(lbm_ctx* c) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (c->host_only) return fail(c, LBM_ESTATE, "host-only context (created without a workspace)");
+    return LBM_OK;
+}
+
+int need_fields(lbm_ctx* c) {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->fields_set) return fail(c, LBM_ESTATE, "lbm_set_fields has not been called");
+    return LBM_OK;
+}
+
+int aa_parity(const lbm_ctx* c) { return c->p.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0; }
+
+const void* current_state(const lbm_ctx* c) { return c->buf[c->p.scheme == LBM_SCHEME_AA ? 0 : c->cur]; }
+
+}  // namespace
+
+extern "C" {
+
+int lbm_default_params(lbm_params* p) {
+    if (!p) return LBM_EINVAL;
+    std::memset(p, 0, sizeof *p);
+    p->Tr0 = 0.8;
+    p->K_int = 2.294922;
+    p->varpi = 1.0 / 6.0;
+    p->gamma1 = -2.0;
+    p->gamma2 = 2.0;
+    p->tau_p = 0.5;
+    p->s_eps = 1.0;
+    p->sigma_e = p->sigma_eps = p->sigma_q = p->sigma_p = 1.0;
+    p->tau_j_v = 0.1;
+    p->lambda_ratio = 10.0;
+    p->cv = 0.0;
+    p->ste = 0.005;
+    p->dTr_ste = 0.05;
+    p->C_ref = 0.0;
+    p->precision = LBM_F64;
+    p->scheme = LBM_SCHEME_AB;
+    return LBM_OK;
+}
+
+int lbm_default_eos(lbm_eos* e) {
+    if (!e) return LBM_EINVAL;
+    e->kind = LBM_EOS_CS;
+    e->a_t = 1.0;
+    e->b_t = 4.0;
+    e->R = 1.0;
+    e->K_eos = 0.479820;
+    return LBM_OK;
+}
+
+int lbm_workspace_bytes(const lbm_lattice* lat, const lbm_params* p, size_t* bytes) {
+    int r = check_lattice(lat);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
+    const size_t N = (size_t)lat->nx * lat->ny;
+    const int nbuf = p->scheme == LBM_SCHEME_AA ? 1 : 2;
+    *bytes = nbuf * state_buffer_bytes(lat, p) + round256(N * sizeof(double)) +
+             round256(lbm_dev::kMaxPartialBlocks * 8 * sizeof(double)) + 256;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lbm_params* p,
+             void* workspace, size_t workspace_bytes, void* hip_stream) {
+    g_init_error.clear();
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int r;
+    if ((r = check_lattice(lat)) || (r = check_eos(eos)) || (r = check_params(p))) return r;
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_EINVAL, "out of host memory");
+    c->lat = *lat;
+    c->eos = *eos;
+    c->p = *p;
+    if ((r = derive(c))) {
+        delete c;
+        return r;
+    }
+    fill_consts(c, &c->c64);
+    fill_consts(c, &c->c32);
+    c->consts = p->precision == LBM_F64 ? (const void*)&c->c64 : (const void*)&c->c32;
+    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : 32;
+    c->shape.waves_per_block = p->waves_per_block > 0 ? p->waves_per_block : 4;
+    c->host_only = workspace == nullptr;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (!c->host_only) {
+        size_t need = 0;
+        lbm_workspace_bytes(lat, p, &need);
+        if (workspace_bytes < need) {
+            fail(nullptr, LBM_ESPACE, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+            delete c;
+            return LBM_ESPACE;
+        }
+        if (reinterpret_cast<uintptr_t>(workspace) & 255) {
+            fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+            delete c;
+            return LBM_EINVAL;
+        }
+        char* w = static_cast<char*>(workspace);
+        const size_t sb = state_buffer_bytes(lat, p);
+        const size_t N = (size_t)lat->nx * lat->ny;
+        c->ws = workspace;
+        c->ws_bytes = workspace_bytes;
+        c->state_bytes = sb;
+        c->buf[0] = w;
+        w += sb;
+        if (p->scheme == LBM_SCHEME_AB) {
+            c->buf[1] = w;
+            w += sb;
+        } else {
+            c->buf[1] = nullptr;
+        }
+        c->rho_scratch = reinterpret_cast<double*>(w);
+        w += round256(N * sizeof(double));
+        c->partials = reinterpret_cast<double*>(w);
+        w += round256(lbm_dev::kMaxPartialBlocks * 8 * sizeof(double));
+        c->result = reinterpret_cast<double*>(w);
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_set_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T) {
+    int r = need_device(c);
+    if (r) return r;
+    if (!rho || !ux || !uy || !T) return fail(c, LBM_EINVAL, "field pointers must not be NULL");
+    c->cur = 0;
+    c->steps = 0;
+    hipError_t e = lbm_dev::launch_init(c->p.precision, c->consts, c->buf[0], rho, ux, uy, T, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "init launch");
+    c->fields_set = true;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+    int r = need_fields(c);
+    if (r) return r;
+    if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+    for (int64_t k = 0; k < n; ++k) {
+        hipError_t e;
+        if (c->p.scheme == LBM_SCHEME_AB) {
+            e = lbm_dev::launch_step_ab(c->p.precision, c->consts, c->buf[c->cur], c->buf[c->cur ^ 1], c->shape,
+                                        c->stream);
+            if (e == hipSuccess) c->cur ^= 1;
+        } else {
+            e = lbm_dev::launch_step_aa(c->p.precision, c->consts, c->buf[0], c->rho_scratch, (int)(c->steps & 1),
+                                        c->shape, c->stream);
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        ++c->steps;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* T) {
+    int r = need_fields(c);
+    if (r) return r;
+    if (!rho) return fail(c, LBM_EINVAL, "rho must not be NULL");
+    hipError_t e = lbm_dev::launch_density(c->p.precision, c->consts, current_state(c), aa_parity(c), rho, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "density launch");
+    if (ux || uy || T) {
+        e = lbm_dev::launch_moments(c->p.precision, c->consts, current_state(c), aa_parity(c), rho, ux, uy, T,
+                                    c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "moments launch");
+    }
+    return LBM_OK;
+}
+
+int lbm_invariants(lbm_ctx* c, double* out, int n_out) {
+    int r = need_fields(c);
+    if (r) return r;
+    if (!out || n_out < 8) return fail(c, LBM_EINVAL, "out must hold at least 8 doubles");
+    hipError_t e = lbm_dev::launch_density(c->p.precision, c->consts, current_state(c), aa_parity(c),
+                                           c->rho_scratch, c->stream);
+    if (e == hipSuccess)
+        e = lbm_dev::launch_invariants(c->p.precision, c->consts, current_state(c), aa_parity(c), c->rho_scratch,
+                                       c->partials, c->result, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, c->result, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "invariants");
+    if (out[7] > 0)
+        return fail(c, LBM_ENONFINITE, "state check failed at %.0f nodes after %lld steps", out[7],
+                    (long long)c->steps);
+    return LBM_OK;
+}
+
+int lbm_derived(const lbm_ctx* c, double* out, int n) {
+    if (!c || !out || n < 0) return LBM_EINVAL;
+    for (int i = 0; i < n && i < 26; ++i) out[i] = c->derived[i];
+    return LBM_OK;
+}
+
+int lbm_step_count(const lbm_ctx* c, int64_t* steps) {
+    if (!c || !steps) return LBM_EINVAL;
+    *steps = c->steps;
+    return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return LBM_EINVAL;
+    *bytes = state_buffer_bytes(&c->lat, &c->p);
+    return LBM_OK;
+}
+
+int lbm_save_state(lbm_ctx* c, void* dst, int64_t* steps) {
+    int r = need_fields(c);
+    if (r) return r;
+    if (!dst) return fail(c, LBM_EINVAL, "dst is NULL");
+    hipError_t e = hipMemcpyAsync(dst, current_state(c), c->state_bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "save copy");
+    if (steps) *steps = c->steps;
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx* c, const void* src, int64_t steps) {
+    int r = need_device(c);
+    if (r) return r;
+    if (!src || steps < 0) return fail(c, LBM_EINVAL, "src is NULL or steps < 0");
+    c->cur = 0;
+    hipError_t e = hipMemcpyAsync(c->buf[0], src, c->state_bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "load copy");
+    c->steps = steps;
+    c->fields_set = true;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+    delete c;
+    return LBM_OK;
+}
+
+const char* lbm_strerror(int code) {
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_ESPACE: return "workspace too small";
+        case LBM_EHIP: return "HIP runtime error";
+        case LBM_ENONFINITE: return "state check failed (non-finite or out-of-range values)";
+        case LBM_ESTATE: return "call out of order";
+        default: return "unknown error";
+    }
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Internal interface between the C ABI (lbm_api.cpp) and the HIP kernels
+// (lbm_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm_dev {
+
+// Per-run constants in the arithmetic type C of the kernels.  Built once on the
+// host; passed by value to every launch.
+template <typename C>
+struct Consts {
+    int32_t nx, ny;
+    int32_t eos_kind;      // 0 CS, 1 vdW
+    int32_t pad_;
+    C G2dx;                // G^2 dx: F_pair = G^2 dx rho sum_i w_i rho(x + e_i dx) e_i/c (Eq. (13))
+    C inv_dx;              // grad rho = sum_i w_i rho_i (e_i/c) / dx
+    C ax, ay;              // external acceleration
+    C c, inv_c, c2;        // lattice speed c = dx/dt
+    C dt, hdt, hdt_c;      // dt, dt/2, dt/(2c)
+    C inv_cv, cv, C_ref;
+    C KR, Ka, bq;          // K_EOS R, K_EOS a~, b~/4 (CS) or b (vdW)
+    C a_diff;              // a - K_EOS a~ with a = G^2 dx^2/2, so that p_BE = K R rho T Z + a_diff rho^2
+    C inv_cs2;
+    C beta;
+    C g1C, g2C;            // (4 + gamma1) C_ref and (4 - gamma2) C_ref (SM Eq. (4a))
+    C gamma1, gamma2;
+    C s_e, s_eps, s_q, s_p;
+    C ks;                  // k s_eps omega_e        (S(1,2))
+    C hs;                  // h s_q omega_e          (S(1,4)/u_x, S(1,6)/u_y)
+    C bs;                  // b s_q omega_p          (S(8,4)/u_y; S(7,4) = 2 bs u_x)
+    C sig_e, sig_eps, sig_q, sig_p;
+    C rho_v, inv_drho, tau_jv, dtau_j;  // tau_j(rho) interpolation
+    C Qpre;                // G^2 dx^2 dt^2 / 12 (SM Eq. (6a))
+    C Ep_pre;              // -(G^2 dx^2)/2 for the potential-energy diagnostic
+    C ref_f[9], ref_g[9];  // deviation reference for 16-bit storage (zero otherwise)
+};
+
+enum Precision { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+struct LaunchShape {
+    int rows_per_wave;     // rows a wavefront marches through
+    int waves_per_block;   // independent wavefronts per workgroup
+};
+
+// All launchers enqueue on `stream` and return the hipError_t of the launch.
+// `state` points at the 18 planes of nx*ny values (9 for f then 9 for g).
+hipError_t launch_init(int prec, const void* c, void* state, const double* rho, const double* ux,
+                       const double* uy, const double* T, hipStream_t stream);
+hipError_t launch_step_ab(int prec, const void* c, const void* in, void* out, LaunchShape shape,
+                          hipStream_t stream);
+// In-place AA pattern: `parity` 0 = even step (own-node slots), 1 = odd step.
+hipError_t launch_step_aa(int prec, const void* c, void* state, double* rho_scratch, int parity,
+                          LaunchShape shape, hipStream_t stream);
+hipError_t launch_density(int prec, const void* c, const void* state, int aa_parity, double* rho,
+                          hipStream_t stream);
+hipError_t launch_moments(int prec, const void* c, const void* state, int aa_parity, const double* rho,
+                          double* ux, double* uy, double* T, hipStream_t stream);
+// Writes 8 FP64 sums to `result` (device), using `partials` (>= kMaxPartialBlocks * 8 doubles).
+hipError_t launch_invariants(int prec, const void* c, const void* state, int aa_parity, const double* rho,
+                             double* partials, double* result, hipStream_t stream);
+
+constexpr int kMaxPartialBlocks = 1024;
+size_t consts_size(int prec);
+size_t storage_bytes(int prec);
+
+}  // namespace lbm_dev

@@ -1,0 +1,28 @@
+// Host thermodynamics of the library: equation of state, Maxwell coexistence
+// and the per-run constants of the model.  Long double throughout; results are
+// rounded to double once.
+#pragma once
+
+#include <string>
+
+namespace lbm_host {
+
+struct Eos {
+    int kind;          // 0 = Carnahan-Starling with attraction (Eq. (17)), 1 = van der Waals
+    long double a, b, R, K;
+};
+
+// Pressure p_EOS(rho, T) and its rho-derivative at fixed T.
+long double pressure(const Eos& e, long double rho, long double T);
+long double pressure_slope(const Eos& e, long double rho, long double T);
+// Chemical potential up to a function of T only.
+long double chem_potential(const Eos& e, long double rho, long double T);
+// Largest admissible density (packing fraction 1).
+long double density_limit(const Eos& e);
+// Critical temperature and pressure.
+void critical(const Eos& e, long double* Tc, long double* pc);
+// Coexisting densities and pressure at T < Tc.  Returns false (with a message) on failure.
+bool coexistence(const Eos& e, long double T, long double* rho_v, long double* rho_l,
+                 long double* p_s, std::string* err);
+
+}  // namespace lbm_host

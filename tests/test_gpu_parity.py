@@ -1,0 +1,254 @@
+"""GPU parity of the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Bars (stated with the workloads): FP64 storage and arithmetic within 1e-12 of the
+oracle after 1000 steps; FP32 within 1e-5; norms in parity_helpers.errors.
+Every case prints its name before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from paper_2106_01557_amd import inputs
+from tests.parity_helpers import (assert_close, errors, gpu_moments, gpu_solver, oracle_model,
+                                  oracle_moments, patch, say)
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def cs_model():
+    return oracle_model("cs")
+
+
+def c1_fields(d, nx=64, ny=64):
+    """Flat slab workload: rows 16-47 liquid, rest vapour (Maxwell densities at T_r0 = 0.8),
+    +-1% uniform noise on rho (PCG64 seed 0), fluid at rest, T = T0."""
+    return inputs.slab(nx, ny, d.rho_l, d.rho_v, d.T0, 16, 47, eps=0.01, seed=0)
+
+
+def test_fp64_flat_slab_1000_steps(cs_model):
+    d = cs_model.d
+    say("case: FP64 AB 64x64 slab, 1000 steps")
+    f = c1_fields(d)
+    g, s = gpu_moments(64, 64, f, 1000, params={"precision": "f64"})
+    o, ost = oracle_moments(cs_model, f, 1000)
+    assert_close(g, o, d, TOL64, "fp64 slab")
+    # invariants from the device reductions agree with the oracle's
+    inv = s.invariants()
+    from oracle import lbm as olbm
+    oinv = olbm.invariants(cs_model, ost)
+    for k in ("mass", "sum_g", "E_p", "E_kin"):
+        assert abs(inv[k] - oinv[k]) <= 1e-12 * abs(oinv[k]), (k, inv[k], oinv[k])
+    assert abs(inv["dt_sum_q"] - oinv["dt_sum_q"]) <= 1e-12 * abs(oinv["sum_g"])
+
+
+def test_fp32_droplet_1000_steps():
+    model = oracle_model("cs", {"Tr0": 0.75})
+    d = model.d
+    say("case: FP32 AB 96x80 droplet R=20 W=4, 1000 steps")
+    f = inputs.droplet(96, 80, d.rho_l, d.rho_v, d.T0, 20, 4, eps=0.005, seed=1)
+    g, _ = gpu_moments(96, 80, f, 1000, params={"precision": "f32", "Tr0": 0.75})
+    o, _ = oracle_moments(model, f, 1000)
+    assert_close(g, o, d, TOL32, "fp32 droplet")
+
+
+@pytest.mark.parametrize("shape", [(32, 4), (1, 1), (7, 2), (5, 8), (200, 4)])
+def test_fp64_ragged_tiles_and_launch_shapes(cs_model, shape):
+    """70 x 45 spans two strips (62 + 8 columns) and, for most shapes, several row chunks
+    with a ragged tail; every launch shape gives the same numbers as the oracle."""
+    d = cs_model.d
+    rows, wpb = shape
+    say(f"case: FP64 AB 70x45 random smooth, 60 steps, rows_per_wave={rows} waves_per_block={wpb}")
+    f = inputs.random_smooth(70, 45, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.4, 0.05 * d.cs, 0.05, seed=21)
+    g, _ = gpu_moments(70, 45, f, 60, params={"precision": "f64", "rows_per_wave": rows, "waves_per_block": wpb})
+    o, _ = oracle_moments(cs_model, f, 60)
+    assert_close(g, o, d, TOL64, f"shape {shape}")
+
+
+def test_launch_shapes_are_bitwise_identical(cs_model):
+    d = cs_model.d
+    say("case: FP64/FP32 AB 130x67 launch-shape bitwise identity")
+    f = inputs.droplet(130, 67, d.rho_l, d.rho_v, d.T0, 20, 5, eps=0.01, seed=4)
+    for prec in ("f64", "f32"):
+        ref = None
+        for rows, wpb in [(32, 4), (1, 8), (9, 1), (67, 2)]:
+            g, _ = gpu_moments(130, 67, f, 25, params={"precision": prec, "rows_per_wave": rows,
+                                                       "waves_per_block": wpb})
+            if ref is None:
+                ref = g
+            else:
+                for k in g:
+                    assert np.array_equal(g[k], ref[k]), (prec, rows, wpb, k)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 64), (64, 1), (2, 2), (3, 5), (62, 3), (63, 2), (124, 7), (1, 1)])
+def test_fp64_edge_shapes(cs_model, nx, ny):
+    d = cs_model.d
+    say(f"case: FP64 AB edge shape {nx}x{ny}, 40 steps")
+    f = inputs.random_smooth(nx, ny, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.5, 0.03 * d.cs, 0.03, seed=nx * 100 + ny)
+    g, _ = gpu_moments(nx, ny, f, 40, params={"precision": "f64", "rows_per_wave": 4})
+    o, _ = oracle_moments(cs_model, f, 40)
+    assert_close(g, o, d, TOL64, f"{nx}x{ny}")
+
+
+def test_fp64_vdw_droplet():
+    model = oracle_model("vdw", {"K_int": 1.0})
+    d = model.d
+    say("case: FP64 AB vdW 48x48 droplet, 300 steps")
+    f = inputs.droplet(48, 48, d.rho_l, d.rho_v, d.T0, 12, 4, eps=0.01, seed=5)
+    g, _ = gpu_moments(48, 48, f, 300, eos_kind="vdw", params={"precision": "f64", "K_int": 1.0})
+    o, _ = oracle_moments(model, f, 300)
+    assert_close(g, o, d, TOL64, "vdw")
+
+
+def test_fp64_external_acceleration(cs_model):
+    p = {"accel_x": 2e-4, "accel_y": -1e-4}
+    model = oracle_model("cs", p)
+    d = model.d
+    say("case: FP64 AB 40x36 droplet with acceleration, 200 steps")
+    f = inputs.droplet(40, 36, d.rho_l, d.rho_v, d.T0, 10, 4, eps=0.01, seed=6)
+    g, _ = gpu_moments(40, 36, f, 200, params=dict(p, precision="f64"))
+    o, _ = oracle_moments(model, f, 200)
+    assert_close(g, o, d, TOL64, "accel")
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_aa_scheme_matches_oracle_and_ab(cs_model, prec, tol):
+    d = cs_model.d
+    say(f"case: {prec} AA vs AB vs oracle 64x48 droplet, 101 steps")
+    f = inputs.droplet(64, 48, d.rho_l, d.rho_v, d.T0, 14, 5, eps=0.01, seed=7)
+    a, _ = gpu_moments(64, 48, f, 101, params={"precision": prec, "scheme": "aa"})
+    b, _ = gpu_moments(64, 48, f, 101, params={"precision": prec, "scheme": "ab"})
+    o, _ = oracle_moments(cs_model, f, 101)
+    assert_close(a, o, d, tol, f"{prec} aa")
+    e = errors(a, b, d)
+    say(f"  aa vs ab {e}")
+    assert max(e.values()) <= (1e-14 if prec == "f64" else 1e-6)
+
+
+def test_run_twice_and_checkpoint_are_bitwise(cs_model):
+    d = cs_model.d
+    say("case: FP32 AB determinism + save/load, 80x60")
+    f = inputs.droplet(80, 60, d.rho_l, d.rho_v, d.T0, 15, 4, eps=0.01, seed=8)
+    a, _ = gpu_moments(80, 60, f, 57, params={"precision": "f32"})
+    b, _ = gpu_moments(80, 60, f, 57, params={"precision": "f32"})
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+    for scheme in ("ab", "aa"):
+        s = gpu_solver(80, 60, params={"precision": "f32", "scheme": scheme})
+        s.set_fields(*f.as_tuple())
+        s.step(31)
+        blob, steps = s.save_state()
+        s.step(26)
+        want = s.moments_numpy()
+        s2 = gpu_solver(80, 60, params={"precision": "f32", "scheme": scheme})
+        s2.load_state(blob, steps)
+        s2.step(26)
+        got = s2.moments_numpy()
+        for k in got:
+            assert np.array_equal(got[k], want[k]), (scheme, k)
+
+
+def test_gpu_conservation_over_many_steps(cs_model):
+    d = cs_model.d
+    say("case: FP64 AB conservation 96x96 droplet, 500 steps")
+    f = inputs.droplet(96, 96, d.rho_l, d.rho_v, d.T0, 24, 5, eps=0.01, seed=9)
+    s = gpu_solver(96, 96, params={"precision": "f64"})
+    s.set_fields(*f.as_tuple())
+    i0 = s.invariants()
+    for _ in range(5):
+        before = s.invariants()
+        s.step(1)
+        after = s.invariants()
+        assert abs(after["sum_g"] - before["sum_g"] - before["dt_sum_q"]) <= 1e-13 * abs(before["sum_g"])
+        s.step(99)
+    i1 = s.invariants()
+    assert abs(i1["mass"] / i0["mass"] - 1) < 1e-13
+    scale = d.c * i0["mass"]
+    assert abs(i1["mom_x"]) < 1e-13 * scale and abs(i1["mom_y"]) < 1e-13 * scale
+
+
+def test_state_check_flags_bad_state(cs_model):
+    from paper_2106_01557_amd import lbm
+    d = cs_model.d
+    say("case: state check on a negative-temperature node")
+    f = inputs.uniform(16, 16, d.rho_v, d.T0)
+    f.T[3, 4] = -d.T0
+    s = gpu_solver(16, 16, params={"precision": "f64"})
+    s.set_fields(*f.as_tuple())
+    with pytest.raises(lbm.LbmError) as ei:
+        s.invariants()
+    assert ei.value.code == lbm.LBM_ENONFINITE
+    inv = s.invariants(raise_on_bad=False)
+    assert inv["bad_nodes"] == 1.0
+
+
+def test_call_order_and_workspace_errors():
+    import ctypes
+    import torch
+    from paper_2106_01557_amd import lbm
+    say("case: ABI call-order and workspace errors on the device")
+    s = gpu_solver(16, 16)
+    with pytest.raises(lbm.LbmError) as ei:
+        s.step(1)
+    assert ei.value.code == lbm.LBM_ESTATE
+    lib = lbm.library()
+    lat = lbm._Lattice(16, 16, 1.0)
+    eos = lbm.Eos()._c()
+    p = lbm._params_c({})
+    need = lbm.workspace_bytes(16, 16)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ctx = ctypes.c_void_p()
+    code = lib.lbm_init(ctypes.byref(ctx), ctypes.byref(lat), ctypes.byref(eos), ctypes.byref(p),
+                        ctypes.c_void_p(ws.data_ptr()), need - 1, None)
+    assert code == lbm.LBM_ESPACE and not ctx.value
+    assert b"workspace" in lib.lbm_last_error(None)
+
+
+# ---- full size, in the launch configuration the benchmark times ---------------------------
+
+def _sampled_full_size(prec, tol, steps=8, n=4096):
+    """Droplet workload at full size (n x n, R = 512, W = 4, T_r 0.75, +-0.5% noise, seed 1):
+    the GPU runs `steps` steps over the whole domain; the oracle runs the same steps on
+    periodic patches of the same initial fields around sampled nodes (the update has a
+    dependency radius of 2 nodes per step, so a patch's centre is exact)."""
+    import torch
+    model = oracle_model("cs", {"Tr0": 0.75})
+    d = model.d
+    say(f"case: {prec} AB full size {n}x{n} droplet, {steps} steps, sampled patches")
+    f = inputs.droplet(n, n, d.rho_l, d.rho_v, d.T0, 512, 4, eps=0.005, seed=1)
+    s = gpu_solver(n, n, params={"precision": prec, "Tr0": 0.75})
+    s.set_fields(*f.as_tuple())
+    s.step(steps)
+    mom = s.moments()
+    s.stream.synchronize()
+    half = 2 * steps + 8
+    margin = 2 * steps + 2
+    c = n // 2
+    centres = [(c, c), (c + 512, c), (c, c - 512), (c + 362, c + 362), (0, 0), (n - 1, 5), (17, n - 3),
+               (c - 400, c + 300), (1234, 3001), (c + 511, c + 3)]
+    worst = {}
+    for cy, cx in centres:
+        sub = inputs.Fields(*[np.ascontiguousarray(patch(a, cy, cx, half)) for a in f.as_tuple()])
+        o, _ = oracle_moments(model, sub, steps)
+        ys = (torch.arange(cy - half, cy + half) % n).to(mom["rho"].device)
+        xs = (torch.arange(cx - half, cx + half) % n).to(mom["rho"].device)
+        g = {k: v[ys][:, xs].cpu().numpy() for k, v in mom.items()}
+        inner = (slice(margin, 2 * half - margin), slice(margin, 2 * half - margin))
+        e = errors({k: v[inner] for k, v in g.items()}, {k: v[inner] for k, v in o.items()}, d)
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    say(f"  worst sampled errors {worst}")
+    assert max(worst.values()) <= tol
+    inv = s.invariants()
+    assert inv["bad_nodes"] == 0
+
+
+def test_fp32_full_size_sampled():
+    _sampled_full_size("f32", TOL32)
+
+
+def test_fp64_full_size_sampled():
+    _sampled_full_size("f64", TOL64)

@@ -51,6 +51,16 @@ def test_moment_matrix_is_lallemand_luo_polynomials():
     assert np.array_equal(G, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]).astype(float))
 
 
+def test_inverse_moment_matrix_conserves_exactly():
+    """M^-1 is exactly M^T D^-1: M M^-1 = I to rounding, and the population sum of M^-1 m
+    depends on m_0 alone (columns 1..8 of M^-1 sum to exactly zero, column 0 to one), so
+    the inverse transform cannot create mass from the other moments."""
+    assert np.allclose(lbm.M @ lbm.MINV, np.eye(9), rtol=0, atol=1e-15)
+    import math
+    sums = [math.fsum(lbm.MINV[:, j]) for j in range(9)]   # exact sums of the stored entries
+    assert sums[0] == 1.0 and all(v == 0.0 for v in sums[1:]), sums
+
+
 def test_stencil_isotropy():
     """Eq. (13) weights: sum w e = 0, sum w e e = I, third moment 0 -> isotropic gradient."""
     w, E = lbm.OMEGA, lbm.EF
