@@ -39,9 +39,9 @@ def kernel_sha() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(tag: str):
+def measured_traffic(tag: str, shape: tuple):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was taken on
-    the current kernel source (else None)."""
+    the current kernel source in the same launch shape (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{tag}.txt")
     if not os.path.exists(path):
         return None
@@ -51,6 +51,8 @@ def measured_traffic(tag: str):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha") != kernel_sha():
+        return None
+    if kv.get("launch_shape") != f"{shape[0]}x{shape[1]}":
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -82,6 +84,23 @@ def cpu_baseline(seconds: float) -> dict:
                       f"single thread (numpy einsum/roll loops, no BLAS)"}
 
 
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
+    """A plain device copy of known size: read nbytes + write nbytes per launch.  Profiling
+    it with the same HBM counters gives the factor that turns counter readings into bytes."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+                      "ms": round(dt * 1e3, 4), "GB_s_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,7 +113,11 @@ def main() -> int:
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the update would shard by slabs with halo exchange, which is not built)", file=sys.stderr)
@@ -142,7 +165,8 @@ def main() -> int:
     kernel_ms = ev_ms / args.steps / launches_per_step if args.scheme == "ab" else ev_ms / args.steps
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
     tag = f"step_{args.scheme}_{args.precision}_{n}"
-    traffic = measured_traffic(tag)
+    shape = solver.launch_shape()
+    traffic = measured_traffic(tag, shape)
     out = {
         "metric": "MLUPS & % HBM roofline",
         "value": round(mlups, 1),
@@ -161,6 +185,7 @@ def main() -> int:
                         f"K_EOS=0.479820, K_INT=2.294922), T/Tc=0.75, +-0.5% noise seed 1",
             "nx": n, "ny": n, "precision": args.precision, "scheme": args.scheme,
             "bytes_per_node_step": 36 * STORAGE_BYTES[args.precision],
+            "launch_shape": f"{shape[0]} rows/wave x {shape[1]} waves/block",
         },
         "roofline": {
             "bound": "hbm",

@@ -167,6 +167,11 @@ int lbm_invariants(lbm_ctx* ctx, double* out, int n_out);
  * 18 s_p 19 s_q 20 s_e 21 omega_e 22 omega_p 23 tau_j_v 24 tau_j_l 25 h_lv */
 int lbm_derived(const lbm_ctx* ctx, double* out, int n);
 
+/* Effective launch shape of the fused two-buffer kernel (after resolving the
+ * 0 = auto values of lbm_params): rows each wavefront marches through and
+ * wavefronts per workgroup.  Host-only; never fails for a valid context. */
+int lbm_launch_shape(const lbm_ctx* ctx, int32_t* rows_per_wave, int32_t* waves_per_block);
+
 /* Number of completed steps since lbm_set_fields(). */
 int lbm_step_count(const lbm_ctx* ctx, int64_t* steps);
 

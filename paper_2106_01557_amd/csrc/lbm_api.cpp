@@ -330,7 +330,7 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     fill_consts(c, &c->c64);
     fill_consts(c, &c->c32);
     c->consts = p->precision == LBM_F64 ? (const void*)&c->c64 : (const void*)&c->c32;
-    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : 32;
+    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : 8;
     c->shape.waves_per_block = p->waves_per_block > 0 ? p->waves_per_block : 4;
     c->host_only = workspace == nullptr;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -438,6 +438,13 @@ int lbm_invariants(lbm_ctx* c, double* out, int n_out) {
 int lbm_derived(const lbm_ctx* c, double* out, int n) {
     if (!c || !out || n < 0) return LBM_EINVAL;
     for (int i = 0; i < n && i < 26; ++i) out[i] = c->derived[i];
+    return LBM_OK;
+}
+
+int lbm_launch_shape(const lbm_ctx* c, int32_t* rows_per_wave, int32_t* waves_per_block) {
+    if (!c || !rows_per_wave || !waves_per_block) return LBM_EINVAL;
+    *rows_per_wave = c->shape.rows_per_wave;
+    *waves_per_block = c->shape.waves_per_block;
     return LBM_OK;
 }
 

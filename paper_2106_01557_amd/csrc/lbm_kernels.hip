@@ -114,9 +114,10 @@ __device__ inline void to_moments(const C* f, C* m) {
 }
 
 // Inverse transform f = M^T D^-1 m with D = diag(9, 36, 36, 6, 12, 6, 12, 4, 4).
-// Row 0 of M is all ones, so f_0 = m_0 - sum_{i>0} f_i exactly; taking f_0 that way
-// keeps the sum of the populations equal to m_0 up to one summation rounding
-// (1/9 is inexact in binary and would otherwise bias the mass every step).
+// Row 0 of M is all ones, so f_0 = m_0 - sum_{i>0} f_i, and the axis and diagonal
+// populations sum to 4 ba and 4 bd; taking f_0 = m_0 - 4 (ba + bd) keeps the sum of
+// the populations equal to m_0 up to unbiased rounding (1/9 is inexact in binary
+// and would otherwise bias the mass in the same direction every step).
 template <typename C>
 __device__ inline void from_moments(const C* m, C* f) {
     const C a0 = m[0] * (C(1) / C(9)), a1 = m[1] * (C(1) / C(36)), a2 = m[2] * (C(1) / C(36));
@@ -135,7 +136,7 @@ __device__ inline void from_moments(const C* m, C* f) {
     f[6] = bd - dx + dy - a8;
     f[7] = bd - dx - dy + a8;
     f[8] = bd + dx - dy - a8;
-    f[0] = m[0] - ((f[1] + f[2]) + (f[3] + f[4])) - ((f[5] + f[6]) + (f[7] + f[8]));
+    f[0] = m[0] - C(4) * (ba + bd);
 }
 
 // Macroscopic quantities at time t (Eq. (14)) from rho, the first moments of f
@@ -380,14 +381,17 @@ struct StripGeom {
     __device__ unsigned off(int y, unsigned x) const { return (unsigned)y * rowb + x * esz; }
 };
 
-template <bool kPre, typename S, typename C, bool kBuf>
+// One row of the marching update.  kStage = 2: issue the loads two rows ahead
+// (g of row y+2, f of row y+3), collide row y, rotate the register ring; kStage = 1:
+// collide and rotate without new loads; kStage = 0: collide only (last row).
+template <int kStage, typename S, typename C, bool kBuf>
 __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
-                                       const StripGeom& G, int y, C (&fA)[9], C (&fB)[9], C (&gA)[9], C& rm,
-                                       C& rc, C& rp) {
-    C fN[9], gN[9];
-    if (kPre) {
-        load_row9<S, C, kBuf>(in, 9, G.off(y + 1, G.xc), P.ref_g, gN);
-        load_row9<S, C, kBuf>(in, 0, G.off(wrap(y + 2, G.ny), G.xc), P.ref_f, fN);
+                                       const StripGeom& G, int y, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&gA)[9],
+                                       C (&gB)[9], C& rm, C& rc, C& rp) {
+    C fD[9], gC[9];
+    if (kStage == 2) {
+        load_row9<S, C, kBuf>(in, 9, G.off(wrap(y + 2, G.ny), G.xc), P.ref_g, gC);
+        load_row9<S, C, kBuf>(in, 0, G.off(wrap(y + 3, G.ny), G.xc), P.ref_f, fD);
     }
     // neighbour densities: lane L-1 is x-1 (west), lane L+1 is x+1 (east)
     const C rW = __shfl_up(rc, 1), rE = __shfl_down(rc, 1);
@@ -409,15 +413,19 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
     };
     if (kBuf) body();          // every lane runs the row; halo lanes' stores are dropped
     else if (G.owner) body();
-    if (kPre) {
+    if (kStage >= 1) {
         rm = rc;
         rc = rp;
-        rp = sum9(fN);
+        rp = sum9(fC);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             fA[i] = fB[i];
-            fB[i] = fN[i];
-            gA[i] = gN[i];
+            fB[i] = fC[i];
+            gA[i] = gB[i];
+            if (kStage == 2) {
+                fC[i] = fD[i];
+                gB[i] = gC[i];
+            }
         }
     }
 }
@@ -449,7 +457,8 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
     const Planes<S, kBuf> Pout(out, pb);
     const int y0 = chunk * rows, y1 = min(ny, y0 + rows);
 
-    C fA[9], fB[9], gA[9];
+    // register ring: f of rows y, y+1, y+2 and g of rows y, y+1; densities of rows y-1..y+1
+    C fA[9], fB[9], fC[9], gA[9], gB[9];
     C rm, rc, rp;
     {
         C t[9];
@@ -459,15 +468,19 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
     load_row9<S, C, kBuf>(Pin, 0, G.off(y0, G.xc), P.ref_f, fA);
     load_row9<S, C, kBuf>(Pin, 0, G.off(wrap(y0 + 1, ny), G.xc), P.ref_f, fB);
     load_row9<S, C, kBuf>(Pin, 9, G.off(y0, G.xc), P.ref_g, gA);
+    load_row9<S, C, kBuf>(Pin, 9, G.off(wrap(y0 + 1, ny), G.xc), P.ref_g, gB);
+    load_row9<S, C, kBuf>(Pin, 0, G.off(wrap(y0 + 2, ny), G.xc), P.ref_f, fC);
     rc = sum9(fA);
     rp = sum9(fB);
     // Let the prologue's loads land before the loop: the loop header then sees only
     // the pipelined state, and the memory-counter waits inside the loop cover just the
-    // loads issued one row earlier (not the stores of the previous row).
+    // loads issued in earlier rows (not the stores of the previous row).
 #pragma unroll
-    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(gA[i]));
-    for (int y = y0; y < y1 - 1; ++y) ab_row<true, S, C, kBuf>(P, Pin, Pout, G, y, fA, fB, gA, rm, rc, rp);
-    ab_row<false, S, C, kBuf>(P, Pin, Pout, G, y1 - 1, fA, fB, gA, rm, rc, rp);
+    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(gA[i]), "v"(gB[i]), "v"(fC[i]));
+    int y = y0;
+    for (; y < y1 - 2; ++y) ab_row<2, S, C, kBuf>(P, Pin, Pout, G, y, fA, fB, fC, gA, gB, rm, rc, rp);
+    if (y < y1 - 1) ab_row<1, S, C, kBuf>(P, Pin, Pout, G, y++, fA, fB, fC, gA, gB, rm, rc, rp);
+    ab_row<0, S, C, kBuf>(P, Pin, Pout, G, y, fA, fB, fC, gA, gB, rm, rc, rp);
 }
 
 // ---------------------------------------------------------------------------

@@ -51,7 +51,8 @@ class _Params(ctypes.Structure):
 
 
 EXPORTED = ["lbm_default_params", "lbm_default_eos", "lbm_workspace_bytes", "lbm_init", "lbm_set_fields",
-            "lbm_step", "lbm_moments", "lbm_invariants", "lbm_derived", "lbm_step_count", "lbm_state_bytes",
+            "lbm_step", "lbm_moments", "lbm_invariants", "lbm_derived", "lbm_launch_shape", "lbm_step_count",
+            "lbm_state_bytes",
             "lbm_save_state", "lbm_load_state", "lbm_destroy", "lbm_strerror", "lbm_last_error"]
 
 
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_moments.argtypes = [V, V, V, V, V]
     lib.lbm_invariants.argtypes = [V, P(D), I]
     lib.lbm_derived.argtypes = [V, P(D), I]
+    lib.lbm_launch_shape.argtypes = [V, P(ctypes.c_int32), P(ctypes.c_int32)]
     lib.lbm_step_count.argtypes = [V, P(ctypes.c_int64)]
     lib.lbm_state_bytes.argtypes = [V, P(S)]
     lib.lbm_save_state.argtypes = [V, V, P(ctypes.c_int64)]
@@ -255,6 +257,11 @@ class Solver:
         buf = (ctypes.c_double * 26)()
         _check(_lib.lbm_derived(self._ctx, buf, 26))
         return dict(zip(DERIVED_NAMES, list(buf)))
+
+    def launch_shape(self) -> tuple:
+        r, w = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.lbm_launch_shape(self._ctx, ctypes.byref(r), ctypes.byref(w)))
+        return r.value, w.value
 
     @property
     def steps(self) -> int:
