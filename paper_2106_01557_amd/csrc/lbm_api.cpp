@@ -259,7 +259,10 @@ int need_fields(lbm_ctx* c) {
     return LBM_OK;
 }
 
-int aa_parity(const lbm_ctx* c) { return c->p.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0; }
+// Layout of the current state for the diagnostic kernels: the two-buffer scheme keeps
+// post-collision populations at their source node (pull convention, 2); the AA
+// scheme alternates between own-node (0) and shifted, swapped slots (1).
+int aa_parity(const lbm_ctx* c) { return c->p.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 2; }
 
 const void* current_state(const lbm_ctx* c) { return c->buf[c->p.scheme == LBM_SCHEME_AA ? 0 : c->cur]; }
 
@@ -320,6 +323,12 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     if ((r = check_lattice(lat)) || (r = check_eos(eos)) || (r = check_params(p))) return r;
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_EINVAL, "out of host memory");
+    if ((size_t)lat->nx * lat->ny * lbm_dev::storage_bytes(p->precision) >= ((size_t)1 << 32)) {
+        fail(nullptr, LBM_EINVAL, "one population plane must stay below 4 GiB (32-bit offsets); got %d x %d",
+             lat->nx, lat->ny);
+        delete c;
+        return LBM_EINVAL;
+    }
     c->lat = *lat;
     c->eos = *eos;
     c->p = *p;
@@ -377,7 +386,8 @@ int lbm_set_fields(lbm_ctx* c, const double* rho, const double* ux, const double
     if (!rho || !ux || !uy || !T) return fail(c, LBM_EINVAL, "field pointers must not be NULL");
     c->cur = 0;
     c->steps = 0;
-    hipError_t e = lbm_dev::launch_init(c->p.precision, c->consts, c->buf[0], rho, ux, uy, T, c->stream);
+    hipError_t e = lbm_dev::launch_init(c->p.precision, c->consts, c->buf[0], rho, ux, uy, T,
+                                        c->p.scheme == LBM_SCHEME_AA ? 0 : 2, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init launch");
     c->fields_set = true;
     return LBM_OK;

@@ -48,19 +48,20 @@ struct LaunchShape {
 
 // All launchers enqueue on `stream` and return the hipError_t of the launch.
 // `state` points at the 18 planes of nx*ny values (9 for f then 9 for g).
+// layout of the state (see load_node): 0 AA even parity, 1 AA odd parity, 2 two-buffer pull
 hipError_t launch_init(int prec, const void* c, void* state, const double* rho, const double* ux,
-                       const double* uy, const double* T, hipStream_t stream);
+                       const double* uy, const double* T, int layout, hipStream_t stream);
 hipError_t launch_step_ab(int prec, const void* c, const void* in, void* out, LaunchShape shape,
                           hipStream_t stream);
 // In-place AA pattern: `parity` 0 = even step (own-node slots), 1 = odd step.
 hipError_t launch_step_aa(int prec, const void* c, void* state, double* rho_scratch, int parity,
                           LaunchShape shape, hipStream_t stream);
-hipError_t launch_density(int prec, const void* c, const void* state, int aa_parity, double* rho,
+hipError_t launch_density(int prec, const void* c, const void* state, int layout, double* rho,
                           hipStream_t stream);
-hipError_t launch_moments(int prec, const void* c, const void* state, int aa_parity, const double* rho,
+hipError_t launch_moments(int prec, const void* c, const void* state, int layout, const double* rho,
                           double* ux, double* uy, double* T, hipStream_t stream);
 // Writes 8 FP64 sums to `result` (device), using `partials` (>= kMaxPartialBlocks * 8 doubles).
-hipError_t launch_invariants(int prec, const void* c, const void* state, int aa_parity, const double* rho,
+hipError_t launch_invariants(int prec, const void* c, const void* state, int layout, const double* rho,
                              double* partials, double* result, hipStream_t stream);
 
 constexpr int kMaxPartialBlocks = 1024;

@@ -254,35 +254,73 @@ __device__ inline void collide(const Consts<C>& P, const C* f, const C* g, C rho
     from_moments(nb, go);
 }
 
-// Velocity components per population (integer lattice vectors).
+// ---------------------------------------------------------------------------
+// fused two-buffer step (pull streaming, 64-column aligned strips)
+// ---------------------------------------------------------------------------
+// State convention of the two-buffer scheme: a buffer holds the post-collision
+// populations at the node where they were computed, not yet streamed; step t
+// reads f_i(x, t) = f_bar_i(x - e_i, t - dt) (Eq. (12a) applied on read) and
+// writes f_bar(x, t) at x.
+//
+// A wavefront owns 64 aligned columns x0..x0+63 of a strip and marches through
+// `rows` rows.  For the populations of target row y it loads, for each i, the
+// aligned row y - e_iy of plane i (one full 256-byte segment per instruction) and
+// moves the values e_ix columns across lanes with a wave-wide DPP shift.  The one
+// value per shifted population that comes from outside the strip (for lane 0 or
+// the last owned lane) and the populations of the two halo columns (whose
+// densities the force stencil needs) arrive through one gather load per row in
+// which each of 18 lanes fetches one value.  Stores are aligned, at the node.
+// Densities of the rows y-1, y, y+1 live in registers; their x-neighbours come
+// from DPP shifts as well.  Every population is read from HBM once per step.
+
 __device__ constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
-// ---------------------------------------------------------------------------
-// fused two-buffer step (push streaming)
-// ---------------------------------------------------------------------------
-// A wavefront owns a strip of 62 columns and marches through `rows` rows.  Lane
-// L holds column x0 - 1 + L (lanes 0 and 63 are halo columns that only supply
-// rho).  Each row's density is computed once from the 9 f values the lane
-// loads anyway; neighbour densities in x come from the adjacent lanes (wave
-// shuffles), in y from the rows kept in registers, so every f value is read
-// from HBM once per step (plus two halo rows per strip of `rows`).
-//
-// Software pipeline: while row y is collided, the g values of row y+1 and the f
-// values of row y+2 are already in flight (vector memory returns in order, so the
-// loads for later rows are issued before the registers of earlier rows are used).
-// The last row of a strip is peeled so the pipelined rows need no selects.
-//
+__device__ inline float dpp_from_west(float v) {  // lane L receives lane L-1
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ inline float dpp_from_east(float v) {  // lane L receives lane L+1
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+__device__ inline double dpp_from_west(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double dpp_from_east(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline float lane_value(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ inline double lane_value(double v, int l) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Index modulo n (for uniform values; the division only runs when v is outside [0, n)).
+__device__ inline int wrap_row(int v, int n) {
+    if (v < 0 || v >= n) v = ((v % n) + n) % n;
+    return v;
+}
+
 // Addressing: with kBuf every access is a raw buffer instruction on one resource
-// per state buffer whose record count covers all 18 planes; the plane offset goes
-// in the scalar offset, the lane's row/column byte offset in the vector offset.  A
-// lane that must not store (halo columns) gets the vector offset
+// per state buffer whose record count covers all 18 planes; for row accesses the
+// plane offset goes in the scalar offset and the lane's row/column byte offset in
+// the vector offset, for the gather the whole offset is per lane.  A lane that
+// must not store, or whose gather slot is unused, gets the vector offset
 // drop = 2^32 - 1 - 17 * plane_bytes: for every plane the total offset then lies at
 // or past the record count without leaving 32 bits, so the hardware drops the
-// store whether or not it counts the scalar offset in its range check.  That needs
-// 35 * plane_bytes < 2^32, which the launcher checks; larger lattices use 64-bit
-// plane addresses and branch around the halo stores.
+// store (or returns zero) whether or not it counts the scalar offset in its range
+// check.  That needs 35 * plane_bytes < 2^32, which the launcher checks; larger
+// lattices use 64-bit plane addresses and branches instead.
 template <typename S>
 struct Bits;
 template <>
@@ -340,6 +378,12 @@ struct Planes<S, true> {
         const S v = Bits<S>::ld(r, off, pb * (unsigned)i);
         return Io<S, C>::ld(&v, 0, ref);
     }
+    // per-lane plane; an unused slot reads zero
+    template <typename C>
+    __device__ C gather(unsigned plane, unsigned off, bool on, C ref) const {
+        const S v = Bits<S>::ld(r, on ? pb * plane + off : drop, 0u);
+        return Io<S, C>::ld(&v, 0, ref);
+    }
     template <typename C>
     __device__ void st(int i, unsigned off, C v, C ref, bool valid) const {
         S t;
@@ -358,74 +402,195 @@ struct Planes<S, false> {
         return Io<S, C>::ld(reinterpret_cast<const S*>(base + pb * i + off), 0, ref);
     }
     template <typename C>
+    __device__ C gather(unsigned plane, unsigned off, bool on, C ref) const {
+        // unused slots read plane 0 at offset 0 (a valid address) and are ignored
+        return on ? Io<S, C>::ld(reinterpret_cast<const S*>(base + pb * plane + off), 0, ref) : C(0);
+    }
+    template <typename C>
     __device__ void st(int i, unsigned off, C v, C ref, bool valid) const {
         if (valid) Io<S, C>::st(reinterpret_cast<S*>(base + pb * i + off), 0, v, ref);
     }
 };
-
-template <typename S, typename C, bool kBuf>
-__device__ inline void load_row9(const Planes<S, kBuf>& B, int first, unsigned off, const C* ref, C* v) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) v[i] = B.template ld<C>(first + i, off, ref[i]);
-}
 
 template <typename C>
 __device__ inline C sum9(const C* f) {
     return f[0] + ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
 }
 
-struct StripGeom {
+// Geometry of one strip, per lane.  The gather slot of a lane (18 for f, 6 for g)
+// names a population, a column and the row offset -e_y of that population.
+struct Strip {
     int nx, ny;
-    unsigned xc, xe, xw, rowb, esz;
-    bool owner;
+    unsigned rowb, esz;
+    unsigned xc;          // the lane's column (clamped to a valid column past the strip end)
+    bool owner;           // the lane holds an owned column
+    int last;             // last owned lane
+    // gather slots
+    bool fon, gon;
+    unsigned fplane, gplane, fcol, gcol;
+    int fdy, gdy;
     __device__ unsigned off(int y, unsigned x) const { return (unsigned)y * rowb + x * esz; }
 };
 
-// One row of the marching update.  kStage = 2: issue the loads two rows ahead
-// (g of row y+2, f of row y+3), collide row y, rotate the register ring; kStage = 1:
-// collide and rotate without new loads; kStage = 0: collide only (last row).
+// Raw loads for one target row: plane i at source row y - e_iy, aligned, and the
+// gather.  up/mid/dn are the byte offsets of source rows y+1, y, y-1 (periodic).
+template <typename S, typename C, bool kBuf>
+__device__ inline void load_target_row(const Planes<S, kBuf>& B, int first, const Strip& G, unsigned up,
+                                       unsigned mid, unsigned dn, bool is_f, const C* ref, C* raw, C& gth) {
+    const unsigned xo = G.xc * G.esz;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const unsigned r = kEy[i] < 0 ? up : (kEy[i] > 0 ? dn : mid);
+        raw[i] = B.template ld<C>(first + i, r + xo, ref[i]);
+    }
+    const unsigned plane = is_f ? G.fplane : G.gplane;
+    const unsigned col = is_f ? G.fcol : G.gcol;
+    const int dy = is_f ? G.fdy : G.gdy;  // -e_y of the slot's population
+    const bool on = is_f ? G.fon : G.gon;
+    const unsigned r = dy > 0 ? up : (dy < 0 ? dn : mid);
+    // the gather's reference is the plane's own (it differs per lane)
+    gth = B.template gather<C>(first + plane, r + col * G.esz, on, ref[plane]);
+}
+
+// Byte offset of the next row, periodic in y: one conditional subtraction is exact
+// because the offset is always below the plane size.
+__device__ inline unsigned next_row(unsigned o, unsigned rowb, unsigned pb) {
+    o += rowb;
+    return o >= pb ? o - pb : o;
+}
+
+// Streamed populations of the target row from its raw loads (DPP shifts plus the
+// edge values from the gather) and the densities of the row's lanes and of its two
+// halo columns.  Gather slots for f: 0-2 pops 0,2,4 at x0-1; 3-5 pops 1,5,8 at x0-2;
+// 6-8 pops 1,5,8 at x0-1; 9-11 pops 0,2,4 at x0+n; 12-14 pops 3,6,7 at x0+n+1;
+// 15-17 pops 3,6,7 at x0+n (n = owned columns).  For g: 0-2 pops 1,5,8 at x0-1;
+// 3-5 pops 3,6,7 at x0+n.
+// DPP reads a source lane only if that lane is active, so every shift below runs
+// with the whole wavefront active: shifts and lane reads are computed unconditionally
+// and pinned (empty asm) before the per-lane selects, which the compiler must not
+// turn into branches around the shifts.
+template <typename C>
+__device__ inline void pin(C& v) {
+    asm volatile("" : "+v"(v));
+}
+
+template <typename C>
+__device__ inline void finish_f(const Strip& G, const C* raw, C gth, C* f, C& rho, C& rhoL, C& rhoR) {
+    const int lane = threadIdx.x & 63;
+    C w1 = dpp_from_west(raw[1]), w5 = dpp_from_west(raw[5]), w8 = dpp_from_west(raw[8]);
+    C e3 = dpp_from_east(raw[3]), e6 = dpp_from_east(raw[6]), e7 = dpp_from_east(raw[7]);
+    pin(w1), pin(w5), pin(w8), pin(e3), pin(e6), pin(e7);
+    const C g6 = lane_value(gth, 6), g7 = lane_value(gth, 7), g8 = lane_value(gth, 8);
+    const C g15 = lane_value(gth, 15), g16 = lane_value(gth, 16), g17 = lane_value(gth, 17);
+    const bool first = lane == 0, lastl = lane == G.last;
+    f[0] = raw[0];
+    f[2] = raw[2];
+    f[4] = raw[4];
+    f[1] = first ? g6 : w1;
+    f[5] = first ? g7 : w5;
+    f[8] = first ? g8 : w8;
+    f[3] = lastl ? g15 : e3;
+    f[6] = lastl ? g16 : e6;
+    f[7] = lastl ? g17 : e7;
+    rho = sum9(f);
+    C h[9];
+    h[0] = lane_value(gth, 0);
+    h[2] = lane_value(gth, 1);
+    h[4] = lane_value(gth, 2);
+    h[1] = lane_value(gth, 3);
+    h[5] = lane_value(gth, 4);
+    h[8] = lane_value(gth, 5);
+    h[3] = lane_value(raw[3], 0);
+    h[6] = lane_value(raw[6], 0);
+    h[7] = lane_value(raw[7], 0);
+    rhoL = sum9(h);
+    h[0] = lane_value(gth, 9);
+    h[2] = lane_value(gth, 10);
+    h[4] = lane_value(gth, 11);
+    h[3] = lane_value(gth, 12);
+    h[6] = lane_value(gth, 13);
+    h[7] = lane_value(gth, 14);
+    h[1] = lane_value(raw[1], G.last);
+    h[5] = lane_value(raw[5], G.last);
+    h[8] = lane_value(raw[8], G.last);
+    rhoR = sum9(h);
+}
+
+template <typename C>
+__device__ inline void finish_g(const Strip& G, const C* raw, C gth, C* g) {
+    const int lane = threadIdx.x & 63;
+    C w1 = dpp_from_west(raw[1]), w5 = dpp_from_west(raw[5]), w8 = dpp_from_west(raw[8]);
+    C e3 = dpp_from_east(raw[3]), e6 = dpp_from_east(raw[6]), e7 = dpp_from_east(raw[7]);
+    pin(w1), pin(w5), pin(w8), pin(e3), pin(e6), pin(e7);
+    const C g0 = lane_value(gth, 0), g1 = lane_value(gth, 1), g2 = lane_value(gth, 2);
+    const C g3 = lane_value(gth, 3), g4 = lane_value(gth, 4), g5 = lane_value(gth, 5);
+    const bool first = lane == 0, lastl = lane == G.last;
+    g[0] = raw[0];
+    g[2] = raw[2];
+    g[4] = raw[4];
+    g[1] = first ? g0 : w1;
+    g[5] = first ? g1 : w5;
+    g[8] = first ? g2 : w8;
+    g[3] = lastl ? g3 : e3;
+    g[6] = lastl ? g4 : e6;
+    g[7] = lastl ? g5 : e7;
+}
+
+template <typename C>
+struct Dens {
+    C v, L, R;  // the lane's density and the two halo columns' densities (uniform)
+};
+
+// One row of the marching update.  kStage = 2: issue the loads for later rows
+// (g of row y+2, f of row y+3), collide row y, finish and rotate; kStage = 1: collide,
+// finish and rotate without new loads; kStage = 0: collide only (last row).
+// R[0..3] hold the byte offsets of rows y+1 .. y+4 (periodic); yo that of row y.
 template <int kStage, typename S, typename C, bool kBuf>
 __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
-                                       const StripGeom& G, int y, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&gA)[9],
-                                       C (&gB)[9], C& rm, C& rc, C& rp) {
-    C fD[9], gC[9];
+                                       const Strip& G, unsigned yo, unsigned (&R)[4], C (&fA)[9], C (&fB)[9],
+                                       C (&rC)[9], C& hC, C (&gA)[9], C (&rgB)[9], C& hgB, Dens<C>& dm,
+                                       Dens<C>& dc, Dens<C>& dp) {
+    const int lane = threadIdx.x & 63;
+    C rD[9], hD, rgC[9], hgC;
     if (kStage == 2) {
-        load_row9<S, C, kBuf>(in, 9, G.off(wrap(y + 2, G.ny), G.xc), P.ref_g, gC);
-        load_row9<S, C, kBuf>(in, 0, G.off(wrap(y + 3, G.ny), G.xc), P.ref_f, fD);
+        load_target_row<S, C, kBuf>(in, 9, G, R[2], R[1], R[0], false, P.ref_g, rgC, hgC);
+        load_target_row<S, C, kBuf>(in, 0, G, R[3], R[2], R[1], true, P.ref_f, rD, hD);
     }
-    // neighbour densities: lane L-1 is x-1 (west), lane L+1 is x+1 (east)
-    const C rW = __shfl_up(rc, 1), rE = __shfl_down(rc, 1);
-    const C rSW = __shfl_up(rm, 1), rSE = __shfl_down(rm, 1);
-    const C rNW = __shfl_up(rp, 1), rNE = __shfl_down(rp, 1);
-    auto body = [&]() {
-        C sx, sy;
-        stencil(rE, rp, rW, rm, rNE, rNW, rSW, rSE, sx, sy);
-        C fo[9], go[9];
-        collide(P, fA, gA, rc, sx, sy, fo, go);
-        const int yn = y + 1 == G.ny ? 0 : y + 1, ys = y == 0 ? G.ny - 1 : y - 1;
-        const unsigned dst[9] = {G.off(y, G.xc), G.off(y, G.xe), G.off(yn, G.xc), G.off(y, G.xw), G.off(ys, G.xc),
-                                 G.off(yn, G.xe), G.off(yn, G.xw), G.off(ys, G.xw), G.off(ys, G.xe)};
+    // neighbour densities: lane L-1 is x-1 (west), lane L+1 is x+1 (east); the
+    // shifts run on the whole wavefront before the halo lanes are patched
+    C wc = dpp_from_west(dc.v), ec = dpp_from_east(dc.v);
+    C wm = dpp_from_west(dm.v), em = dpp_from_east(dm.v);
+    C wp = dpp_from_west(dp.v), ep = dpp_from_east(dp.v);
+    pin(wc), pin(ec), pin(wm), pin(em), pin(wp), pin(ep);
+    const bool first = lane == 0, lastl = lane == G.last;
+    const C rW = first ? dc.L : wc, rE = lastl ? dc.R : ec;
+    const C rSW = first ? dm.L : wm, rSE = lastl ? dm.R : em;
+    const C rNW = first ? dp.L : wp, rNE = lastl ? dp.R : ep;
+    C sx, sy;
+    stencil(rE, dp.v, rW, dm.v, rNE, rNW, rSW, rSE, sx, sy);
+    C fo[9], go[9];
+    collide(P, fA, gA, dc.v, sx, sy, fo, go);
+    const unsigned o = yo + G.xc * G.esz;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            out.template st<C>(i, dst[i], fo[i], P.ref_f[i], G.owner);
-            out.template st<C>(9 + i, dst[i], go[i], P.ref_g[i], G.owner);
-        }
-    };
-    if (kBuf) body();          // every lane runs the row; halo lanes' stores are dropped
-    else if (G.owner) body();
+    for (int i = 0; i < 9; ++i) {
+        out.template st<C>(i, o, fo[i], P.ref_f[i], G.owner);
+        out.template st<C>(9 + i, o, go[i], P.ref_g[i], G.owner);
+    }
     if (kStage >= 1) {
-        rm = rc;
-        rc = rp;
-        rp = sum9(fC);
+        dm = dc;
+        dc = dp;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            fA[i] = fB[i];
-            fB[i] = fC[i];
-            gA[i] = gB[i];
-            if (kStage == 2) {
-                fC[i] = fD[i];
-                gB[i] = gC[i];
+        for (int i = 0; i < 9; ++i) fA[i] = fB[i];
+        finish_f(G, rC, hC, fB, dp.v, dp.L, dp.R);
+        finish_g(G, rgB, hgB, gA);
+        if (kStage == 2) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                rC[i] = rD[i];
+                rgB[i] = rgC[i];
             }
+            hC = hD;
+            hgB = hgC;
         }
     }
 }
@@ -435,52 +600,98 @@ __global__ void __launch_bounds__(64 * WPB)
 k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, const int nstrips,
           const int rows, const int nitems) {
     const int lane = threadIdx.x & 63;
-    const int w = remap_xcd(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6);
+    // the wavefront's work item is uniform across its lanes; saying so keeps the strip
+    // geometry, the row loop and the halo columns on the scalar unit (and the loop free
+    // of exec masking, which the DPP shifts rely on)
+    const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
     if (w >= nitems) return;
     const int strip = w % nstrips, chunk = w / nstrips;
     const int nx = P.nx, ny = P.ny;
-    const int x0 = strip * 62;
-    const int owned = min(62, nx - x0);
-    const bool active = lane <= owned + 1;
-    StripGeom G;
+    const int x0 = strip * 64;
+    const int owned = min(64, nx - x0);
+    Strip G;
     G.nx = nx;
     G.ny = ny;
-    G.owner = lane >= 1 && lane <= owned;
-    // inactive lanes read column 0 (a valid address) and never store
-    G.xc = active ? (unsigned)wrap(x0 - 1 + lane, nx) : 0u;
-    G.xe = G.xc + 1 == (unsigned)nx ? 0u : G.xc + 1;
-    G.xw = G.xc == 0 ? (unsigned)nx - 1 : G.xc - 1;
     G.rowb = (unsigned)nx * sizeof(S);
     G.esz = sizeof(S);
+    G.owner = lane < owned;
+    G.xc = (unsigned)(G.owner ? x0 + lane : nx - 1);
+    G.last = __builtin_amdgcn_readfirstlane(owned - 1);  // a lane index for v_readlane: must be uniform
+    {
+        // halo columns (uniform): x0-1, x0-2, x0+n, x0+n+1 modulo nx
+        const unsigned l1 = __builtin_amdgcn_readfirstlane(wrap_row(x0 - 1, nx));
+        const unsigned l2 = __builtin_amdgcn_readfirstlane(wrap_row(x0 - 2, nx));
+        const unsigned r1 = __builtin_amdgcn_readfirstlane(wrap_row(x0 + owned, nx));
+        const unsigned r2 = __builtin_amdgcn_readfirstlane(wrap_row(x0 + owned + 1, nx));
+        // f slots (lane: population, column): 0-2 axis pops {0,2,4} at l1; 3-5 east pops
+        // {1,5,8} at l2; 6-8 east pops at l1; 9-11 axis pops at r1; 12-14 west pops
+        // {3,6,7} at r2; 15-17 west pops at r1.  g slots: 0-2 east pops at l1; 3-5 west
+        // pops at r1.  Branch-free selects keep the setup free of divergent control flow.
+        const int k = lane % 3, grp = lane / 3;
+        const int axis0 = k == 0 ? 0 : (k == 1 ? 2 : 4);
+        const int east = k == 0 ? 1 : (k == 1 ? 5 : 8);
+        const int west = k == 0 ? 3 : (k == 1 ? 6 : 7);
+        const int pf = (grp == 0 || grp == 3) ? axis0 : ((grp == 1 || grp == 2) ? east : west);
+        const unsigned cf = grp == 1 ? l2 : (grp == 4 ? r2 : ((grp == 0 || grp == 2) ? l1 : r1));
+        G.fon = lane < 18;
+        G.fplane = (unsigned)pf;
+        G.fcol = cf;
+        G.fdy = pf == 2 || pf == 5 || pf == 6 ? -1 : (pf == 4 || pf == 7 || pf == 8 ? 1 : 0);  // -e_y
+        const int pg = grp == 0 ? east : west;
+        G.gon = lane < 6;
+        G.gplane = (unsigned)pg;
+        G.gcol = grp == 0 ? l1 : r1;
+        G.gdy = pg == 5 || pg == 6 ? -1 : (pg == 7 || pg == 8 ? 1 : 0);
+    }
     const size_t pb = (size_t)nx * ny * sizeof(S);
     const Planes<S, kBuf> Pin(in, pb);
     const Planes<S, kBuf> Pout(out, pb);
     const int y0 = chunk * rows, y1 = min(ny, y0 + rows);
+    const unsigned pbu = (unsigned)pb;  // only used when the byte offsets fit in 32 bits
 
-    // register ring: f of rows y, y+1, y+2 and g of rows y, y+1; densities of rows y-1..y+1
-    C fA[9], fB[9], fC[9], gA[9], gB[9];
-    C rm, rc, rp;
+    // register ring: streamed f of rows y, y+1 and raw loads of row y+2; streamed g of
+    // row y and raw loads of row y+1; densities of rows y-1, y, y+1
+    C fA[9], fB[9], rC[9], hC, gA[9], rgB[9], hgB;
+    Dens<C> dm, dc, dp;
+    // byte offsets of rows y0-2 .. y0+3 (periodic)
+    unsigned ro[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ro[k] = __builtin_amdgcn_readfirstlane((unsigned)wrap_row(y0 - 2 + k, ny) * G.rowb);
     {
-        C t[9];
-        load_row9<S, C, kBuf>(Pin, 0, G.off(wrap(y0 - 1, ny), G.xc), P.ref_f, t);
-        rm = sum9(t);
+        C r[9], h, t[9];
+        load_target_row<S, C, kBuf>(Pin, 0, G, ro[2], ro[1], ro[0], true, P.ref_f, r, h);
+        finish_f(G, r, h, t, dm.v, dm.L, dm.R);
+        load_target_row<S, C, kBuf>(Pin, 0, G, ro[3], ro[2], ro[1], true, P.ref_f, r, h);
+        finish_f(G, r, h, fA, dc.v, dc.L, dc.R);
+        load_target_row<S, C, kBuf>(Pin, 0, G, ro[4], ro[3], ro[2], true, P.ref_f, r, h);
+        finish_f(G, r, h, fB, dp.v, dp.L, dp.R);
+        load_target_row<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, r, h);
+        finish_g(G, r, h, gA);
     }
-    load_row9<S, C, kBuf>(Pin, 0, G.off(y0, G.xc), P.ref_f, fA);
-    load_row9<S, C, kBuf>(Pin, 0, G.off(wrap(y0 + 1, ny), G.xc), P.ref_f, fB);
-    load_row9<S, C, kBuf>(Pin, 9, G.off(y0, G.xc), P.ref_g, gA);
-    load_row9<S, C, kBuf>(Pin, 9, G.off(wrap(y0 + 1, ny), G.xc), P.ref_g, gB);
-    load_row9<S, C, kBuf>(Pin, 0, G.off(wrap(y0 + 2, ny), G.xc), P.ref_f, fC);
-    rc = sum9(fA);
-    rp = sum9(fB);
+    load_target_row<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rgB, hgB);
+    load_target_row<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rC, hC);
     // Let the prologue's loads land before the loop: the loop header then sees only
     // the pipelined state, and the memory-counter waits inside the loop cover just the
     // loads issued in earlier rows (not the stores of the previous row).
 #pragma unroll
-    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(gA[i]), "v"(gB[i]), "v"(fC[i]));
+    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(rgB[i]), "v"(rC[i]));
+    asm volatile("" ::"v"(hgB), "v"(hC));
+    unsigned R[4] = {ro[3], ro[4], ro[5], next_row(ro[5], G.rowb, pbu)};  // rows y+1 .. y+4
+    unsigned yo = ro[2];
     int y = y0;
-    for (; y < y1 - 2; ++y) ab_row<2, S, C, kBuf>(P, Pin, Pout, G, y, fA, fB, fC, gA, gB, rm, rc, rp);
-    if (y < y1 - 1) ab_row<1, S, C, kBuf>(P, Pin, Pout, G, y++, fA, fB, fC, gA, gB, rm, rc, rp);
-    ab_row<0, S, C, kBuf>(P, Pin, Pout, G, y, fA, fB, fC, gA, gB, rm, rc, rp);
+    for (; y < y1 - 2; ++y) {
+        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
+        yo = R[0];
+        R[0] = R[1];
+        R[1] = R[2];
+        R[2] = R[3];
+        R[3] = next_row(R[3], G.rowb, pbu);
+    }
+    if (y < y1 - 1) {
+        ab_row<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
+        yo = R[0];
+    }
+    ab_row<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
 }
 
 // ---------------------------------------------------------------------------
@@ -540,17 +751,18 @@ k_step_aa(S* __restrict__ st, const double* __restrict__ rho_arr, const Consts<C
     }
 }
 
-// Populations of node (x, y) at the current time, for either scheme: AA parity
-// 0 is also the layout of the two-buffer scheme.
+// Populations of node (x, y) at the current time.  layout 0: AA even parity (slot i
+// at x); 1: AA odd parity (slot opp(i) at x - e_i); 2: the two-buffer scheme's pull
+// convention (slot i at x - e_i).
 template <typename S, typename C>
-__device__ inline void load_node(const S* st, const Consts<C>& P, int parity, int x, int y, C* f, C* g) {
+__device__ inline void load_node(const S* st, const Consts<C>& P, int layout, int x, int y, C* f, C* g) {
     using IO = Io<S, C>;
     const int nx = P.nx, ny = P.ny, N = nx * ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int slot = i, off = y * nx + x;
-        if (parity) {
-            slot = kOpp[i];
+        if (layout != 0) {
+            slot = layout == 1 ? kOpp[i] : i;
             off = wrap(y - kEy[i], ny) * nx + wrap(x - kEx[i], nx);
         }
         f[i] = IO::ld(st + (size_t)slot * N, off, P.ref_f[i]);
@@ -558,10 +770,13 @@ __device__ inline void load_node(const S* st, const Consts<C>& P, int parity, in
     }
 }
 
+// Equilibrium state from macroscopic fields.  layout 0 (AA even parity) stores f_i(x)
+// in slot i at x; layout 2 (two-buffer pull convention) stores it at x - e_i, where
+// the first step's pull read finds it.
 template <typename S, typename C>
 __global__ void __launch_bounds__(256)
 k_init(S* __restrict__ st, const double* __restrict__ rho_in, const double* __restrict__ ux_in,
-       const double* __restrict__ uy_in, const double* __restrict__ T_in, const Consts<C> P) {
+       const double* __restrict__ uy_in, const double* __restrict__ T_in, const Consts<C> P, const int layout) {
     using IO = Io<S, C>;
     const int N = P.nx * P.ny;
     const int k = blockIdx.x * 256 + threadIdx.x;
@@ -595,10 +810,12 @@ k_init(S* __restrict__ st, const double* __restrict__ rho_in, const double* __re
     n[7] = C(0);
     n[8] = C(0);
     from_moments(n, g);
+    const int y = k / P.nx, x = k - y * P.nx;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        IO::st(st + (size_t)i * N, k, f[i], P.ref_f[i]);
-        IO::st(st + (size_t)(9 + i) * N, k, g[i], P.ref_g[i]);
+        const int o = layout == 2 ? wrap(y - kEy[i], P.ny) * P.nx + wrap(x - kEx[i], P.nx) : k;
+        IO::st(st + (size_t)i * N, o, f[i], P.ref_f[i]);
+        IO::st(st + (size_t)(9 + i) * N, o, g[i], P.ref_g[i]);
     }
 }
 
@@ -722,11 +939,11 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double* __restric
 template <typename S, typename C>
 struct Launch {
     static hipError_t init(const void* cv, void* st, const double* r, const double* u, const double* v,
-                           const double* T, hipStream_t s) {
+                           const double* T, int layout, hipStream_t s) {
         const Consts<C>& P = *static_cast<const Consts<C>*>(cv);
         const int N = P.nx * P.ny;
         hipLaunchKernelGGL((k_init<S, C>), dim3((N + 255) / 256), dim3(256), 0, s, static_cast<S*>(st), r,
-                           u, v, T, P);
+                           u, v, T, P, layout);
         return hipGetLastError();
     }
     template <bool kBuf>
@@ -743,7 +960,7 @@ struct Launch {
     }
     static hipError_t step_ab(const void* cv, const void* in, void* out, LaunchShape sh, hipStream_t s) {
         const Consts<C>& P = *static_cast<const Consts<C>*>(cv);
-        const int nstrips = (P.nx + 61) / 62;
+        const int nstrips = (P.nx + 63) / 64;
         const int rows = sh.rows_per_wave;
         const int nchunks = (P.ny + rows - 1) / rows;
         const int nitems = nstrips * nchunks;
@@ -809,8 +1026,8 @@ struct Launch {
     }
 
 hipError_t launch_init(int prec, const void* c, void* state, const double* rho, const double* ux,
-                       const double* uy, const double* T, hipStream_t stream) {
-    LBM_DISPATCH(prec, init(c, state, rho, ux, uy, T, stream));
+                       const double* uy, const double* T, int layout, hipStream_t stream) {
+    LBM_DISPATCH(prec, init(c, state, rho, ux, uy, T, layout, stream));
 }
 hipError_t launch_step_ab(int prec, const void* c, const void* in, void* out, LaunchShape shape,
                           hipStream_t stream) {
