@@ -55,7 +55,7 @@ extern "C" {
 #define LBM_BF16 3  /* BF16 deviations from the rest equilibrium of (rho0, T0)      */
 
 /* ---- update schemes ------------------------------------------------------- */
-#define LBM_SCHEME_AB 0  /* fused single pass, two state buffers (push streaming)      */
+#define LBM_SCHEME_AB 0  /* fused single pass, two state buffers (pull streaming)      */
 #define LBM_SCHEME_AA 1  /* in-place AA pattern, one state buffer, plus a density pass */
 
 typedef struct lbm_ctx lbm_ctx;   /* opaque; owned by the library */

@@ -339,7 +339,7 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     fill_consts(c, &c->c64);
     fill_consts(c, &c->c32);
     c->consts = p->precision == LBM_F64 ? (const void*)&c->c64 : (const void*)&c->c32;
-    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : 8;
+    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : 128;
     c->shape.waves_per_block = p->waves_per_block > 0 ? p->waves_per_block : 4;
     c->host_only = workspace == nullptr;
     c->stream = static_cast<hipStream_t>(hip_stream);

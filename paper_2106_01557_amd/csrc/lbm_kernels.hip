@@ -595,16 +595,12 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
     }
 }
 
-template <typename S, typename C, int WPB, bool kBuf>
-__global__ void __launch_bounds__(64 * WPB)
-k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, const int nstrips,
-          const int rows, const int nitems) {
+// Update of one work item (a strip of up to 64 columns times `rows` rows) of one
+// lattice.  `w` must be uniform across the wavefront.
+template <typename S, typename C, bool kBuf>
+__device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict__ out, const Consts<C>& P,
+                                         const int w, const int nstrips, const int rows) {
     const int lane = threadIdx.x & 63;
-    // the wavefront's work item is uniform across its lanes; saying so keeps the strip
-    // geometry, the row loop and the halo columns on the scalar unit (and the loop free
-    // of exec masking, which the DPP shifts rely on)
-    const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
-    if (w >= nitems) return;
     const int strip = w % nstrips, chunk = w / nstrips;
     const int nx = P.nx, ny = P.ny;
     const int x0 = strip * 64;
@@ -692,6 +688,55 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
         yo = R[0];
     }
     ab_row<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
+}
+
+template <typename S, typename C, int WPB, bool kBuf>
+__global__ void __launch_bounds__(64 * WPB)
+k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, const int nstrips,
+          const int rows, const int nitems) {
+    // the wavefront's work item is uniform across its lanes; saying so keeps the strip
+    // geometry, the row loop and the halo columns on the scalar unit (and the loop free
+    // of exec masking, which the DPP shifts rely on)
+    const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
+    if (w >= nitems) return;
+    ab_strip<S, C, kBuf>(in, out, P, w, nstrips, rows);
+}
+
+// ---------------------------------------------------------------------------
+// batched form: many independent lattices, one launch per step
+// ---------------------------------------------------------------------------
+// Work items of all lattices are numbered consecutively (lattice b owns items
+// [first[b], first[b+1])).  A persistent grid of wavefronts walks the item range
+// with a stride of the grid's wavefront count; each wavefront finds its lattice by
+// a uniform binary search and reads that lattice's constants and buffers from the
+// descriptor table in device memory (scalar loads).
+template <typename C>
+struct BatchDesc {
+    Consts<C> P;
+    void* buf[2];
+    int nstrips, rows, first, pad_;
+};
+
+template <typename S, typename C, int WPB>
+__global__ void __launch_bounds__(64 * WPB)
+k_step_ab_batch(const BatchDesc<C>* __restrict__ desc, const int nlat, const int nitems, const int parity) {
+    const int nw = gridDim.x * WPB;
+    for (int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
+         w < nitems; w += nw) {
+        int lo = 0, hi = nlat - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (desc[mid].first <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = __builtin_amdgcn_readfirstlane(lo);
+        const BatchDesc<C>& D = desc[b];
+        const S* in = static_cast<const S*>(D.buf[parity]);
+        S* out = static_cast<S*>(D.buf[parity ^ 1]);
+        const bool kbuf = (size_t)35 * D.P.nx * D.P.ny * sizeof(S) < ((size_t)1 << 32);
+        if (kbuf) ab_strip<S, C, true>(in, out, D.P, w - D.first, D.nstrips, D.rows);
+        else ab_strip<S, C, false>(in, out, D.P, w - D.first, D.nstrips, D.rows);
+    }
 }
 
 // ---------------------------------------------------------------------------
