@@ -2,6 +2,7 @@
 
     python bench.py [--steps K] [--warmup W] [--precision f32|f64|f16|bf16] [--scheme ab|aa]
                     [--n 4096] [--no-cpu-baseline] [--gpus 1]
+    python bench.py --workload batch64 [--steps K] [--coexistence STEPS]
 
 Workload: a static droplet on a periodic 4096 x 4096 D2Q9 lattice, radius 512 at
 the domain centre, tanh interface of width 4 nodes, Carnahan-Starling EOS with the
@@ -84,6 +85,167 @@ def cpu_baseline(seconds: float) -> dict:
                       f"single thread (numpy einsum/roll loops, no BLAS)"}
 
 
+def batch_members(seed: int = 2, count: int = 64):
+    """The batched workload: `count` periodic domains with side U{128, 256, 512, 1024},
+    a droplet (R = side/4) or a slab (middle half liquid) with equal odds, T/Tc in
+    U[0.60, 0.95], tanh interface width 4, +-0.5 % density noise; all from PCG64(seed)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(count):
+        side = int(rng.choice([128, 256, 512, 1024]))
+        kind = "droplet" if rng.random() < 0.5 else "slab"
+        tr = float(rng.uniform(0.60, 0.95))
+        out.append({"side": side, "kind": kind, "Tr0": tr, "seed": seed * 1000 + k})
+    return out
+
+
+def _bulk_samples(m, kind, side):
+    """Liquid and vapour sample regions (5 x 5 node means): droplet centre and the
+    far corner; slab centre row and the row half a period away (5 rows each)."""
+    import torch
+    rho, T = m["rho"], m["T"]
+    c = side // 2
+    if kind == "droplet":
+        liq = (slice(c - 2, c + 3), slice(c - 2, c + 3))
+        vap = (slice(0, 5), slice(0, 5))
+    else:
+        liq = (slice(c - 2, c + 3), slice(None))
+        vap = (slice(0, 5), slice(None))
+    vals = torch.stack([rho[liq].mean(), rho[vap].mean(), T[liq].mean(), T[vap].mean()])
+    return vals
+
+
+def run_batch(args) -> dict:
+    import torch
+    from paper_2106_01557_amd import inputs, lbm
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    spec = batch_members()
+    sols = []
+    for m in spec:
+        s = lbm.Solver(m["side"], m["side"], params={"Tr0": m["Tr0"], "precision": args.precision},
+                       stream=stream)
+        d = s.derived()
+        n = m["side"]
+        if m["kind"] == "droplet":
+            f = inputs.droplet(n, n, d["rho_l"], d["rho_v"], d["T0"], n / 4, 4, eps=0.005, seed=m["seed"])
+        else:
+            f = inputs.slab(n, n, d["rho_l"], d["rho_v"], d["T0"], n // 4, n - n // 4 - 1, width=4, eps=0.005,
+                            seed=m["seed"])
+        s.set_fields(*f.as_tuple())
+        sols.append(s)
+    b = lbm.Batch(sols)
+    items, nodes = b.size()
+    print(f"# batch ready: {len(sols)} domains, {nodes} nodes", file=sys.stderr, flush=True)
+    shape, tuned_ms = b.autotune(args.autotune_steps)
+    print(f"# autotuned shape {shape}: {tuned_ms:.4f} ms/step", file=sys.stderr, flush=True)
+    b.set_graph(args.graph_steps)
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    b.step(args.steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = start.elapsed_time(stop) / args.steps
+    mlups = nodes * args.steps / wall / 1e6
+    b_alg = 36 * STORAGE_BYTES[args.precision] * nodes
+    achieved = b_alg / (kernel_ms * 1e-3) / 1e9
+    bad_each = [s.invariants(raise_on_bad=False)["bad_nodes"] for s in sols]
+    bad = sum(bad_each)
+    out = {
+        "metric": "MLUPS & % HBM roofline (batched)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32"}[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": "64 periodic domains, side U{128,256,512,1024}, droplet (R=side/4) or slab (middle half), "
+                        "T/Tc U[0.60,0.95], CS EOS paper set, tanh W=4, +-0.5% noise, PCG64 seed 2",
+            "nodes": nodes, "work_items": items, "precision": args.precision,
+            "launch_shape": shape, "graph_steps": args.graph_steps,
+            "autotune_ms_per_step": round(tuned_ms, 5),
+        },
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "k_step_ab_batch", "kernel_ms": round(kernel_ms, 5)},
+        "checks": {"bad_nodes": bad,
+                   "failed_domains": [(m["side"], m["kind"], round(m["Tr0"], 4))
+                                      for m, x in zip(spec, bad_each) if x > 0]},
+    }
+    if args.coexistence > 0:
+        out["coexistence"] = batch_coexistence(b, sols, spec, args.coexistence, args.check_every,
+                                               wall * 1e3 / args.steps)
+    return out
+
+
+def batch_coexistence(b, sols, spec, steps, every, ms_per_step) -> dict:
+    """Runs the batch `steps` more steps, sampling bulk densities every `every` steps.
+    Time to coexistence of a domain: the first sample after which both bulk densities
+    stay within 1e-3 (relative) of their final values.  The final values are compared
+    with Maxwell's construction at the measured bulk temperature."""
+    import numpy as np
+    import torch
+    from paper_2106_01557_amd import lbm
+
+    hist = []
+    done = 0
+    t0 = time.perf_counter()
+    stream = sols[0].stream
+    while done < steps:
+        n = min(every, steps - done)
+        b.step(n)
+        done += n
+        # the moments are written on the solvers' stream: sample them on that stream too
+        with torch.cuda.stream(stream):
+            row = torch.stack([_bulk_samples(s.moments(("rho", "T")), m["kind"], m["side"])
+                               for s, m in zip(sols, spec)]).cpu().numpy()
+        hist.append((done, row))
+        if len(hist) % 10 == 0:
+            print(f"# coexistence run: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
+    final = hist[-1][1]
+    per = []
+    for i, (s, m) in enumerate(zip(sols, spec)):
+        rl, rv, Tl, Tv = (float(v) for v in final[i])
+        t_first = None
+        for k in range(len(hist)):
+            ok = all(abs(h[1][i][0] - rl) <= 1e-3 * rl and abs(h[1][i][1] - rv) <= 1e-3 * rv for h in hist[k:])
+            if ok:
+                t_first = hist[k][0]
+                break
+        Tb = 0.5 * (Tl + Tv)
+        bad = s.invariants(raise_on_bad=False)["bad_nodes"]
+        try:
+            mx = lbm.maxwell(Tb / s.derived()["Tc"])
+        except lbm.LbmError:
+            mx = {"rho_l": float("nan"), "rho_v": float("nan")}
+        per.append({"bad_nodes": bad, "side": m["side"], "kind": m["kind"], "Tr0": round(m["Tr0"], 4),
+                    "rho_l": rl, "rho_v": rv, "T_bulk_over_Tc": Tb / s.derived()["Tc"],
+                    "rel_dev_rho_l": (rl - mx["rho_l"]) / mx["rho_l"], "rel_dev_rho_v": (rv - mx["rho_v"]) / mx["rho_v"],
+                    "steps_to_coexistence": t_first, "finite": bool(np.isfinite(final[i]).all())})
+    ttc = [p["steps_to_coexistence"] for p in per if p["steps_to_coexistence"] is not None and p["bad_nodes"] == 0]
+    slabs = [p for p in per if p["kind"] == "slab"]
+    return {
+        "steps": steps, "check_every": every,
+        "converged_domains": len(ttc), "domains": len(per),
+        "failed_domains": [(p["side"], p["kind"], p["Tr0"]) for p in per if p["bad_nodes"] > 0],
+        "steps_to_coexistence_median": float(np.median(ttc)) if ttc else None,
+        "steps_to_coexistence_max": max(ttc) if ttc else None,
+        "seconds_to_coexistence_all": (max(ttc) * ms_per_step / 1e3) if len(ttc) == len(per) else None,
+        "slab_max_rel_dev_vs_maxwell": max(max(abs(p["rel_dev_rho_l"]), abs(p["rel_dev_rho_v"])) for p in slabs)
+        if slabs else None,
+        "per_domain": per,
+    }
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
     """A plain device copy of known size: read nbytes + write nbytes per launch.  Profiling
     it with the same HBM counters gives the factor that turns counter readings into bytes."""
@@ -104,6 +266,12 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="droplet4096", choices=["droplet4096", "batch64"])
+    ap.add_argument("--autotune-steps", type=int, default=5)
+    ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--coexistence", type=int, default=0,
+                    help="batch64: steps of the coexistence run after the timed steps (0 = skip)")
+    ap.add_argument("--check-every", type=int, default=500)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="f32", choices=list(STORAGE_BYTES))
@@ -122,6 +290,10 @@ def main() -> int:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the update would shard by slabs with halo exchange, which is not built)", file=sys.stderr)
         return 2
+
+    if args.workload == "batch64":
+        print(json.dumps(run_batch(args)), flush=True)
+        return 0
 
     import torch
     from paper_2106_01557_amd import inputs, lbm

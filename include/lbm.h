@@ -186,6 +186,79 @@ int lbm_load_state(lbm_ctx* ctx, const void* src_device, int64_t steps);
 /* Releases the context (never the caller's workspace).  NULL is allowed. */
 int lbm_destroy(lbm_ctx* ctx);
 
+/* Coexisting densities of the equation of state alone (Maxwell equal-area
+ * construction on p_EOS of Eq. (17); the pressure at coexistence is p_s) at the
+ * reduced temperature Tr = T/Tc, 0 < Tr < 1.  Host-only: out[0] rho_v,
+ * out[1] rho_l, out[2] p_s, out[3] Tc.  LBM_EINVAL on bad input or when no
+ * coexistence is found. */
+int lbm_maxwell(const lbm_eos* eos, double Tr, double out[4]);
+
+/* ---- batched form -----------------------------------------------------------
+ * Many independent lattices (each its own size, EOS, temperature and constants,
+ * created by lbm_init with the two-buffer scheme) advanced together by one kernel
+ * launch per time step.  Each step of a member is bitwise identical to what
+ * lbm_step on that member alone computes.  The members stay usable through the
+ * single-lattice calls (moments, invariants, save/load, even lbm_step); the
+ * batch notices a member stepped alone and re-reads its buffers.  Members must
+ * outlive the batch and share one precision and one stream, and each must keep
+ * 35 population planes below 4 GiB (32-bit buffer offsets). */
+typedef struct lbm_batch lbm_batch;  /* opaque; owned by the library */
+
+/* Work distribution of a batched launch. */
+typedef struct {
+    int32_t rows_per_wave;   /* rows of one work item (>= 1)                          */
+    int32_t waves_per_block; /* 1, 2 or 4                                              */
+    int32_t queue;           /* 0: one wavefront per work item (grid sized to the work);
+                                1: persistent grid of resident wavefronts taking work
+                                items from per-XCD atomic tile queues                   */
+    int32_t blocks;          /* queue mode: grid size; 0 = CUs x resident blocks per CU */
+} lbm_batch_shape;
+
+/* Device workspace of a batch of n members in this precision (descriptor table,
+ * item offsets, queue counters). */
+int lbm_batch_workspace_bytes(int32_t n, int32_t precision, size_t* bytes);
+
+/* Groups n >= 1 distinct device contexts.  workspace: device memory of at least
+ * lbm_batch_workspace_bytes() bytes, 256-byte aligned.  Synchronises the stream
+ * once (descriptor upload).  Default shape: 32 rows per wave, 4 waves per block,
+ * grid mode.  On failure *out is NULL and lbm_batch_last_error(NULL) explains. */
+int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* workspace,
+                     size_t workspace_bytes);
+
+/* Sets / reads the launch shape (LBM_EINVAL for values outside the ranges above). */
+int lbm_batch_set_shape(lbm_batch* b, const lbm_batch_shape* shape);
+int lbm_batch_get_shape(const lbm_batch* b, lbm_batch_shape* shape);
+
+/* Replays captured HIP graphs of steps_per_graph launches (even, >= 2) for the
+ * bulk of lbm_batch_step; 0 launches every step directly.  The graph is captured
+ * on the members' stream at the next step call and again after a shape change.
+ * The stream must be a created stream (LBM_EINVAL for the null stream). */
+int lbm_batch_set_graph(lbm_batch* b, int32_t steps_per_graph);
+
+/* Advances every member n >= 0 time steps.  Asynchronous (a descriptor re-upload,
+ * needed only after a member was stepped or reset alone, synchronises). */
+int lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Times every candidate shape (rows 16/32/64/128 x 1/2/4 waves per block x grid
+ * and queue mode) over steps_per_candidate >= 1 steps after 2 warm-up steps, and
+ * keeps the fastest.  The timed steps are real steps: every member advances
+ * 24 x (steps_per_candidate + 2) steps, bitwise as it would under any fixed
+ * shape.  Writes the chosen shape and its milliseconds per step (either pointer
+ * may be NULL).  Synchronising. */
+int lbm_batch_autotune(lbm_batch* b, int32_t steps_per_candidate, lbm_batch_shape* best,
+                       double* ms_per_step);
+
+/* Work items of one launch under the current shape, and total nodes. */
+int lbm_batch_size(const lbm_batch* b, int64_t* items, int64_t* nodes);
+
+/* Releases the batch (never the members or the workspace).  NULL is allowed. */
+int lbm_batch_destroy(lbm_batch* b);
+
+/* Message of the last failing call on b (or of the last failed create when b is
+ * NULL). */
+const char* lbm_batch_last_error(const lbm_batch* b);
+
+
 /* Static description of a code; never NULL. */
 const char* lbm_strerror(int code);
 

@@ -10,34 +10,11 @@
 #include <new>
 #include <string>
 
-#include "lbm_internal.hpp"
+#include "lbm_ctx.hpp"
 #include "thermo.hpp"
 
 using lbm_dev::Consts;
 
-struct lbm_ctx {
-    lbm_lattice lat;
-    lbm_eos eos;
-    lbm_params p;
-    double derived[26];
-    Consts<double> c64;
-    Consts<float> c32;
-    const void* consts;       // &c64 or &c32 depending on precision
-    bool host_only;
-    void* ws;
-    size_t ws_bytes;
-    hipStream_t stream;
-    void* buf[2];
-    size_t state_bytes;
-    double* rho_scratch;
-    double* partials;
-    double* result;
-    int cur;
-    bool fields_set;
-    int64_t steps;
-    lbm_dev::LaunchShape shape;
-    std::string err;
-};
 
 namespace {
 

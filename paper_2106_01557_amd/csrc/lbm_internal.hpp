@@ -65,6 +65,37 @@ hipError_t launch_invariants(int prec, const void* c, const void* state, int lay
                              double* partials, double* result, hipStream_t stream);
 
 constexpr int kMaxPartialBlocks = 1024;
+
+// ---- batched form: many independent lattices advanced by one launch per step ----
+// One descriptor per lattice, in device memory.  The work items of lattice b (strips of
+// 64 columns times `rows` rows, strip-major within each row chunk) are numbered
+// starts[b] .. starts[b+1]-1 in one global range.  A launch of parity p reads buf[p]
+// and writes buf[p ^ 1].
+template <typename C>
+struct BatchDesc {
+    Consts<C> P;
+    const void* buf[2];
+    int32_t nstrips;
+    int32_t rows;
+    int32_t pad_[2];
+};
+
+// Work distribution of a batched launch.
+struct BatchLaunch {
+    int waves_per_block;
+    int blocks;            // grid size
+    int queue;             // 0: one wavefront per work item; 1: persistent grid on per-XCD tile queues
+    int groups;            // queue mode: number of queues (min(8, blocks))
+};
+
+// `queue` holds 2 x 8 unsigned counters (zero before the first launch).  A queue-mode
+// launch of parity p takes items from counters [p*8, p*8+8) and clears the other eight
+// for the next launch.
+hipError_t launch_step_ab_batch(int prec, const void* desc, const int32_t* starts, unsigned* queue, int nlat,
+                                int nitems, int parity, BatchLaunch bl, hipStream_t stream);
+// Resident blocks per CU of the batched kernel for the given precision and block size.
+int batch_blocks_per_cu(int prec, int waves_per_block, int queue);
+size_t batch_desc_size(int prec);
 size_t consts_size(int prec);
 size_t storage_bytes(int prec);
 

@@ -705,37 +705,53 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
 // ---------------------------------------------------------------------------
 // batched form: many independent lattices, one launch per step
 // ---------------------------------------------------------------------------
-// Work items of all lattices are numbered consecutively (lattice b owns items
-// [first[b], first[b+1])).  A persistent grid of wavefronts walks the item range
-// with a stride of the grid's wavefront count; each wavefront finds its lattice by
-// a uniform binary search and reads that lattice's constants and buffers from the
-// descriptor table in device memory (scalar loads).
-template <typename C>
-struct BatchDesc {
-    Consts<C> P;
-    void* buf[2];
-    int nstrips, rows, first, pad_;
-};
+// The lattice owning global item w is found by a binary search over `starts` (uniform,
+// so it runs on the scalar unit); its constants and buffers come from its descriptor.
+// Grid mode: one wavefront per item, XCD-remapped as in the single-lattice kernel.
+// Queue mode: a persistent grid; the item range is cut into `groups` contiguous
+// ranges, one per XCD (a block's XCD is its index modulo 8), and the wavefronts of
+// an XCD take items of its range from an atomic counter until it is exhausted.
+// Every lattice must satisfy the 32-bit buffer-offset bound (35 planes < 4 GiB).
+template <typename S, typename C>
+__device__ __forceinline__ void batch_item(const BatchDesc<C>* __restrict__ desc, const int32_t* __restrict__ starts,
+                                           const int nlat, const int w, const int parity) {
+    int lo = 0, hi = nlat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const int b = __builtin_amdgcn_readfirstlane(lo);
+    const BatchDesc<C>* D = desc + b;
+    const S* in = static_cast<const S*>(D->buf[parity]);
+    S* out = const_cast<S*>(static_cast<const S*>(D->buf[parity ^ 1]));
+    ab_strip<S, C, true>(in, out, D->P, __builtin_amdgcn_readfirstlane(w - starts[b]), D->nstrips, D->rows);
+}
 
-template <typename S, typename C, int WPB>
+template <typename S, typename C, int WPB, bool kQueue>
 __global__ void __launch_bounds__(64 * WPB)
-k_step_ab_batch(const BatchDesc<C>* __restrict__ desc, const int nlat, const int nitems, const int parity) {
-    const int nw = gridDim.x * WPB;
-    for (int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
-         w < nitems; w += nw) {
-        int lo = 0, hi = nlat - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (desc[mid].first <= w) lo = mid;
-            else hi = mid - 1;
-        }
-        const int b = __builtin_amdgcn_readfirstlane(lo);
-        const BatchDesc<C>& D = desc[b];
-        const S* in = static_cast<const S*>(D.buf[parity]);
-        S* out = static_cast<S*>(D.buf[parity ^ 1]);
-        const bool kbuf = (size_t)35 * D.P.nx * D.P.ny * sizeof(S) < ((size_t)1 << 32);
-        if (kbuf) ab_strip<S, C, true>(in, out, D.P, w - D.first, D.nstrips, D.rows);
-        else ab_strip<S, C, false>(in, out, D.P, w - D.first, D.nstrips, D.rows);
+k_step_ab_batch(const BatchDesc<C>* __restrict__ desc, const int32_t* __restrict__ starts,
+                unsigned* __restrict__ queue, const int nlat, const int nitems, const int parity, const int groups) {
+    if (!kQueue) {
+        const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
+        if (w >= nitems) return;
+        batch_item<S, C>(desc, starts, nlat, w, parity);
+        return;
+    }
+    // counters of the other parity were used by the previous launch (complete by stream
+    // order) and are next used by the following launch (after this one completes)
+    if (blockIdx.x == 0 && threadIdx.x < 8) queue[(parity ^ 1) * 8 + threadIdx.x] = 0u;
+    const int g = (int)(blockIdx.x % (unsigned)groups);
+    const int lo = (int)(((long long)nitems * g) / groups);
+    const int hi = (int)(((long long)nitems * (g + 1)) / groups);
+    unsigned* ctr = queue + parity * 8 + g;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(ctr, 1u);
+        const int w = lo + (int)__builtin_amdgcn_readfirstlane(t);
+        if (w >= hi) break;
+        batch_item<S, C>(desc, starts, nlat, w, parity);
     }
 }
 
@@ -1018,6 +1034,44 @@ struct Launch {
         if (kBuf) return step_ab_wpb<true>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
         return step_ab_wpb<false>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
     }
+    template <int WPB>
+    static hipError_t batch_wpb(const void* d, const int32_t* st, unsigned* q, int nlat, int nitems, int parity,
+                                BatchLaunch bl, hipStream_t s) {
+        const BatchDesc<C>* desc = static_cast<const BatchDesc<C>*>(d);
+        if (bl.queue)
+            hipLaunchKernelGGL((k_step_ab_batch<S, C, WPB, true>), dim3(bl.blocks), dim3(64 * WPB), 0, s, desc, st, q,
+                               nlat, nitems, parity, bl.groups);
+        else
+            hipLaunchKernelGGL((k_step_ab_batch<S, C, WPB, false>), dim3(bl.blocks), dim3(64 * WPB), 0, s, desc, st,
+                               q, nlat, nitems, parity, bl.groups);
+        return hipGetLastError();
+    }
+    static hipError_t step_ab_batch(const void* d, const int32_t* st, unsigned* q, int nlat, int nitems, int parity,
+                                    BatchLaunch bl, hipStream_t s) {
+        switch (bl.waves_per_block) {
+            case 1: return batch_wpb<1>(d, st, q, nlat, nitems, parity, bl, s);
+            case 2: return batch_wpb<2>(d, st, q, nlat, nitems, parity, bl, s);
+            case 4: return batch_wpb<4>(d, st, q, nlat, nitems, parity, bl, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    template <int WPB>
+    static int occ_wpb(int queue) {
+        int n = 0;
+        hipError_t e = queue ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &n, reinterpret_cast<const void*>(&k_step_ab_batch<S, C, WPB, true>), 64 * WPB, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &n, reinterpret_cast<const void*>(&k_step_ab_batch<S, C, WPB, false>), 64 * WPB, 0);
+        return e == hipSuccess ? n : 0;
+    }
+    static int batch_occupancy(int wpb, int queue) {
+        switch (wpb) {
+            case 1: return occ_wpb<1>(queue);
+            case 2: return occ_wpb<2>(queue);
+            case 4: return occ_wpb<4>(queue);
+            default: return 0;
+        }
+    }
     static hipError_t step_aa(const void* cv, void* st, double* rho, int parity, LaunchShape, hipStream_t s) {
         const Consts<C>& P = *static_cast<const Consts<C>*>(cv);
         const int N = P.nx * P.ny;
@@ -1094,6 +1148,21 @@ hipError_t launch_invariants(int prec, const void* c, const void* state, int aa_
                              double* partials, double* result, hipStream_t stream) {
     LBM_DISPATCH(prec, invariants(c, state, aa_parity, rho, partials, result, stream));
 }
+
+hipError_t launch_step_ab_batch(int prec, const void* desc, const int32_t* starts, unsigned* queue, int nlat,
+                                int nitems, int parity, BatchLaunch bl, hipStream_t stream) {
+    LBM_DISPATCH(prec, step_ab_batch(desc, starts, queue, nlat, nitems, parity, bl, stream));
+}
+int batch_blocks_per_cu(int prec, int waves_per_block, int queue) {
+    switch (prec) {
+        case kF64: return Launch<double, double>::batch_occupancy(waves_per_block, queue);
+        case kF32: return Launch<float, float>::batch_occupancy(waves_per_block, queue);
+        case kF16: return Launch<__half, float>::batch_occupancy(waves_per_block, queue);
+        case kBF16: return Launch<__hip_bfloat16, float>::batch_occupancy(waves_per_block, queue);
+        default: return 0;
+    }
+}
+size_t batch_desc_size(int prec) { return prec == kF64 ? sizeof(BatchDesc<double>) : sizeof(BatchDesc<float>); }
 
 size_t consts_size(int prec) { return prec == kF64 ? sizeof(Consts<double>) : sizeof(Consts<float>); }
 size_t storage_bytes(int prec) { return prec == kF64 ? 8 : (prec == kF32 ? 4 : 2); }

@@ -53,7 +53,15 @@ class _Params(ctypes.Structure):
 EXPORTED = ["lbm_default_params", "lbm_default_eos", "lbm_workspace_bytes", "lbm_init", "lbm_set_fields",
             "lbm_step", "lbm_moments", "lbm_invariants", "lbm_derived", "lbm_launch_shape", "lbm_step_count",
             "lbm_state_bytes",
-            "lbm_save_state", "lbm_load_state", "lbm_destroy", "lbm_strerror", "lbm_last_error"]
+            "lbm_save_state", "lbm_load_state", "lbm_destroy", "lbm_strerror", "lbm_last_error",
+            "lbm_maxwell", "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set_shape",
+            "lbm_batch_get_shape", "lbm_batch_set_graph", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_size",
+            "lbm_batch_destroy", "lbm_batch_last_error"]
+
+
+class _BatchShape(ctypes.Structure):
+    _fields_ = [("rows_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("queue", ctypes.c_int32), ("blocks", ctypes.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -81,8 +89,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_strerror.restype = ctypes.c_char_p
     lib.lbm_last_error.argtypes = [V]
     lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_maxwell.argtypes = [P(_Eos), D, P(D)]
+    lib.lbm_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, P(S)]
+    lib.lbm_batch_create.argtypes = [P(V), P(V), ctypes.c_int32, V, S]
+    lib.lbm_batch_set_shape.argtypes = [V, P(_BatchShape)]
+    lib.lbm_batch_get_shape.argtypes = [V, P(_BatchShape)]
+    lib.lbm_batch_set_graph.argtypes = [V, ctypes.c_int32]
+    lib.lbm_batch_step.argtypes = [V, ctypes.c_int64]
+    lib.lbm_batch_autotune.argtypes = [V, ctypes.c_int32, P(_BatchShape), P(D)]
+    lib.lbm_batch_size.argtypes = [V, P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.lbm_batch_destroy.argtypes = [V]
+    lib.lbm_batch_last_error.argtypes = [V]
+    lib.lbm_batch_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("lbm_strerror", "lbm_last_error"):
+        if name not in ("lbm_strerror", "lbm_last_error", "lbm_batch_last_error"):
             getattr(lib, name).restype = I
     return lib
 
@@ -136,6 +156,16 @@ def _params_c(overrides: dict | None) -> _Params:
             raise LbmError(LBM_EINVAL, f"unknown parameter {k!r}")
         setattr(p, k, v)
     return p
+
+
+def maxwell(Tr: float, eos: Eos | None = None) -> dict:
+    """Coexistence of the EOS alone at T/Tc = Tr (host thermodynamics of the library)."""
+    out = (ctypes.c_double * 4)()
+    e = (eos or Eos())._c()
+    code = _lib.lbm_maxwell(ctypes.byref(e), float(Tr), out)
+    if code != LBM_OK:
+        raise LbmError(code, f"no coexistence at Tr = {Tr}")
+    return {"rho_v": out[0], "rho_l": out[1], "p_s": out[2], "Tc": out[3]}
 
 
 def _check(code: int, ctx=None):
@@ -287,6 +317,78 @@ class Solver:
         if self._ctx:
             _lib.lbm_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent Solvers (two-buffer scheme, one precision, one stream) advanced
+    together by one launch per step.  The member Solvers stay usable on their own."""
+
+    def __init__(self, members):
+        import torch
+        self.members = list(members)
+        if not self.members:
+            raise LbmError(LBM_EINVAL, "a batch needs at least one member")
+        m0 = self.members[0]
+        self.stream, self.device = m0.stream, m0.device
+        nbytes = ctypes.c_size_t()
+        p = int(m0._p.precision)
+        code = _lib.lbm_batch_workspace_bytes(len(self.members), p, ctypes.byref(nbytes))
+        if code != LBM_OK:
+            raise LbmError(code, _lib.lbm_batch_last_error(None).decode())
+        with torch.cuda.device(self.device):
+            raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.workspace = raw[off:off + nbytes.value]
+        arr = (ctypes.c_void_p * len(self.members))(*[m._ctx.value for m in self.members])
+        self._b = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            code = _lib.lbm_batch_create(ctypes.byref(self._b), arr, len(self.members),
+                                         ctypes.c_void_p(self.workspace.data_ptr()), nbytes.value)
+        if code != LBM_OK:
+            raise LbmError(code, _lib.lbm_batch_last_error(None).decode() or _lib.lbm_strerror(code).decode())
+
+    def _check(self, code):
+        if code != LBM_OK:
+            raise LbmError(code, _lib.lbm_batch_last_error(self._b).decode() or _lib.lbm_strerror(code).decode())
+
+    def step(self, n: int = 1):
+        self._check(_lib.lbm_batch_step(self._b, int(n)))
+
+    def set_shape(self, rows_per_wave: int = 32, waves_per_block: int = 4, queue: bool = False, blocks: int = 0):
+        s = _BatchShape(int(rows_per_wave), int(waves_per_block), int(bool(queue)), int(blocks))
+        self._check(_lib.lbm_batch_set_shape(self._b, ctypes.byref(s)))
+
+    def shape(self) -> dict:
+        s = _BatchShape()
+        self._check(_lib.lbm_batch_get_shape(self._b, ctypes.byref(s)))
+        return {"rows_per_wave": s.rows_per_wave, "waves_per_block": s.waves_per_block,
+                "queue": bool(s.queue), "blocks": s.blocks}
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(_lib.lbm_batch_set_graph(self._b, int(steps_per_graph)))
+
+    def autotune(self, steps_per_candidate: int = 10) -> tuple:
+        s, ms = _BatchShape(), ctypes.c_double()
+        self._check(_lib.lbm_batch_autotune(self._b, int(steps_per_candidate), ctypes.byref(s), ctypes.byref(ms)))
+        return ({"rows_per_wave": s.rows_per_wave, "waves_per_block": s.waves_per_block,
+                 "queue": bool(s.queue), "blocks": s.blocks}, ms.value)
+
+    def size(self) -> tuple:
+        items, nodes = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.lbm_batch_size(self._b, ctypes.byref(items), ctypes.byref(nodes)))
+        return items.value, nodes.value
+
+    def close(self):
+        if self._b:
+            _lib.lbm_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -99,3 +99,45 @@ def test_strerror_covers_codes(lbm):
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.lbm_strerror(code).decode() not in ("", "unknown error")
     assert lib.lbm_strerror(-99).decode() == "unknown error"
+
+
+@pytest.mark.parametrize("eos_kind", ["cs", "vdw"])
+@pytest.mark.parametrize("Tr", [0.6, 0.75, 0.8, 0.95])
+def test_maxwell_query_matches_oracle(lbm, eos_kind, Tr):
+    """lbm_maxwell (long-double host thermodynamics) against the 40-digit oracle."""
+    eos = lbm.Eos() if eos_kind == "cs" else lbm.vdw_eos()
+    e = thermo.paper_cs_eos() if eos_kind == "cs" else thermo.vdw_eos()
+    got = lbm.maxwell(Tr, eos)
+    Tc = float(thermo.critical_point(e)[0])
+    rv, rl = (float(v) for v in thermo.maxwell(e, Tr * thermo.critical_point(e)[0])[:2])
+    assert got["Tc"] == pytest.approx(Tc, rel=1e-14)
+    assert got["rho_v"] == pytest.approx(rv, rel=1e-12)
+    assert got["rho_l"] == pytest.approx(rl, rel=1e-12)
+
+
+def test_maxwell_query_rejects_bad_input(lbm):
+    for Tr in (0.0, 1.0, 1.2, -0.5, float("nan")):
+        with pytest.raises(lbm.LbmError):
+            lbm.maxwell(Tr)
+
+
+def test_batch_validation_before_any_device_call(lbm):
+    lib = lbm.library()
+    out = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_batch_workspace_bytes(0, 1, ctypes.byref(nbytes)) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_workspace_bytes(4, 9, ctypes.byref(nbytes)) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_workspace_bytes(64, 1, ctypes.byref(nbytes)) == lbm.LBM_OK
+    small = nbytes.value
+    assert lib.lbm_batch_workspace_bytes(64, 0, ctypes.byref(nbytes)) == lbm.LBM_OK
+    assert nbytes.value > small  # FP64 descriptors hold FP64 constants
+    s = lbm.Solver(8, 8, host_only=True)
+    arr = (ctypes.c_void_p * 1)(s._ctx.value)
+    code = lib.lbm_batch_create(ctypes.byref(out), arr, 1, ctypes.c_void_p(1 << 20), 1 << 20)
+    assert code == lbm.LBM_ESTATE and not out.value
+    assert "host-only" in lib.lbm_batch_last_error(None).decode()
+    assert lib.lbm_batch_create(ctypes.byref(out), arr, 0, ctypes.c_void_p(1 << 20), 1 << 20) == lbm.LBM_EINVAL
+    null = (ctypes.c_void_p * 1)(None)
+    assert lib.lbm_batch_create(ctypes.byref(out), null, 1, ctypes.c_void_p(1 << 20), 1 << 20) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_destroy(None) == lbm.LBM_OK
+    s.close()
