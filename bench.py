@@ -139,8 +139,12 @@ def run_batch(args) -> dict:
     b = lbm.Batch(sols)
     items, nodes = b.size()
     print(f"# batch ready: {len(sols)} domains, {nodes} nodes", file=sys.stderr, flush=True)
-    shape, tuned_ms = b.autotune(args.autotune_steps)
-    print(f"# autotuned shape {shape}: {tuned_ms:.4f} ms/step", file=sys.stderr, flush=True)
+    if args.autotune_steps > 0:
+        shape, tuned_ms = b.autotune(args.autotune_steps)
+        print(f"# autotuned shape {shape}: {tuned_ms:.4f} ms/step", file=sys.stderr, flush=True)
+    else:  # fixed shape (grid mode), e.g. for profiling one kernel configuration
+        b.set_shape(args.rows_per_wave or 64, args.waves_per_block or 4, queue=False)
+        shape, tuned_ms = b.shape(), 0.0
     b.set_graph(args.graph_steps)
     b.step(args.warmup)
     torch.cuda.synchronize()
