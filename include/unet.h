@@ -1,0 +1,125 @@
+/* unet.h -- C ABI of the learned warm start's network kernels (gfx950).
+ *
+ * A U-Net on periodic lattice fields predicts a later density field from an initial
+ * one; the lattice solver (lbm.h) starts from the prediction.  These calls are the
+ * network's building blocks: 3x3 convolutions on bfloat16 activations with FP32
+ * accumulation on the matrix cores, their two gradients, 2x2 max pooling, nearest
+ * 2x upsampling, the 1x1 output head with the mean-squared-error loss, and the Adam
+ * update (Kingma & Ba, 2015).
+ *
+ * Conventions shared by every call:
+ *  - Activations are NHWC, bfloat16 (raw 16-bit patterns, round to nearest even),
+ *    unless a call says FP32.  A tensor argument comes with `ld` (elements between
+ *    consecutive pixels, >= its channel count) and `off` (channel offset), so one
+ *    buffer can hold the channel concatenation of two tensors.  ld and off must be
+ *    multiples of 8 and the base pointer 16-byte aligned (16-bit tensors).
+ *  - H and W are powers of two (>= 2; the pooled and upsampled sizes follow); the
+ *    3x3 convolutions wrap around (periodic padding), matching the lattice.
+ *  - 3x3 weights are [C_out][3][3][C_in] (tap (ky, kx) reads offset (ky-1, kx-1)).
+ *  - Every pointer is device memory owned by the caller; nothing is allocated.
+ *    Calls are asynchronous on `stream` (a hipStream_t; NULL = null stream).
+ *  - Returns 0 on success, UNET_EINVAL (-1) for a bad argument (checked before any
+ *    launch), UNET_EHIP (-3) when a launch fails; unet_last_error() explains.
+ */
+#ifndef UNET_H
+#define UNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UNET_OK 0
+#define UNET_EINVAL (-1)
+#define UNET_EHIP (-3)
+
+/* y = epilogue(conv3x3(x, w) + bias): y[n,p,o] = bias[o] + sum_{t,i} w[o,t,i] x[n,p+off_t,i].
+ * flags: UNET_RELU applies max(., 0); UNET_OUT_F32 stores FP32 (else bfloat16).
+ * mask (nullable, bfloat16, [N,H,W] x C_out with its own ld/off): the result is
+ * zeroed where mask <= 0 (the ReLU gradient gate of a backward pass).
+ * bias may be NULL (no bias).  C_in % 8 == 0, C_out % 16 == 0. */
+#define UNET_RELU 1
+#define UNET_OUT_F32 2
+int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, const float* bias,
+                     void* y, int32_t ldy, int32_t offy, const void* mask, int32_t ldm, int32_t offm,
+                     int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, int32_t flags,
+                     void* stream);
+
+/* wf[i][t][o] = w[o][8-t][i]: the weights of the input-gradient convolution
+ * (dx = conv3x3_fwd(g, wf) with C_in and C_out exchanged). */
+int unet_flip_weights(const void* w, void* wf, int32_t C_out, int32_t C_in, void* stream);
+
+/* Weight and bias gradients: dw[o,t,i] = sum_{n,p} g[n,p,o] x[n,p+off_t,i] and
+ * db[o] = sum g[n,p,o] (FP32, overwritten).  The pixel sum is split over slabs whose
+ * FP32 partial sums go to `partials` and are then added in a fixed order
+ * (deterministic).  unet_wgrad_partial_bytes() gives the partials size. */
+int unet_wgrad_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, size_t* bytes);
+int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg,
+                       float* dw, float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H,
+                       int32_t W, int32_t C_in, int32_t C_out, void* stream);
+
+/* 2x2 max pooling with stride 2: y[n,Y,X,c] = max of x over rows 2Y..2Y+1, cols 2X..2X+1. */
+int unet_maxpool2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t ldy, int32_t offy,
+                      int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
+
+/* Pooling gradient: dx = route(dy) + add, gated by x > 0 when gate_relu != 0, where
+ * route sends each window's dy to its first maximum in row-major window order.
+ * add (nullable) is a full-size tensor.  H, W are the input (unpooled) sizes. */
+int unet_maxpool2_bwd(const void* x, int32_t ldx, int32_t offx, const void* dy, int32_t lddy, int32_t offdy,
+                      const void* add, int32_t lda, int32_t offa, void* dx, int32_t lddx, int32_t offdx,
+                      int32_t gate_relu, int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
+
+/* Nearest 2x upsampling: y[n,2Y+a,2X+b,c] = x[n,Y,X,c].  H, W are the input sizes. */
+int unet_upsample2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t ldy, int32_t offy,
+                       int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
+
+/* Upsampling gradient: dx[n,Y,X,c] = sum over the 2x2 block of dy, zeroed where
+ * gate <= 0 (gate nullable, same shape as dx).  H, W are the output (small) sizes. */
+int unet_upsample2_bwd(const void* dy, int32_t lddy, int32_t offdy, const void* gate, int32_t ldgt,
+                       int32_t offgt, void* dx, int32_t lddx, int32_t offdx, int32_t N, int32_t H, int32_t W,
+                       int32_t C, void* stream);
+
+/* Network input from density fields: x[n,p,0] = (rho - rho_v[n]) / (rho_l[n] - rho_v[n]),
+ * x[n,p,1] = cond[n], channels 2..7 zero (x is [N,H,W,8] bfloat16); rin (FP32)
+ * receives channel 0 unrounded.  rho is FP64 [N,H,W]; x or rin may be NULL, not both. */
+int unet_prepare_input(const double* rho, const double* rho_v, const double* rho_l, const double* cond,
+                       void* x, float* rin, int32_t N, int32_t H, int32_t W, void* stream);
+
+/* Density from the normalised prediction: rho[n,p] = rho_v[n] + (rho_l[n] - rho_v[n]) out[n,p]
+ * (out FP32, rho FP64, both [N,H,W]). */
+int unet_output_density(const float* out, const double* rho_v, const double* rho_l, double* rho,
+                        int32_t N, int32_t H, int32_t W, void* stream);
+
+/* Output head: out[n,p] = sum_c hw[c] d[n,p,c] + hb + rin[n,p] (FP32).  With target
+ * (nullable) also the loss: dout = 2 (out - target) / (N H W) and the mean squared
+ * error is written to loss[0] (both FP32; the sum uses per-block partials in
+ * `partials`, >= unet_head_partial_bytes(), added in a fixed order). */
+int unet_head_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C, size_t* bytes);
+int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, const float* rin,
+                  const float* target, float* out, float* dout, float* loss, void* partials,
+                  size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
+
+/* Head gradient: g[n,p,c] = dout[n,p] hw[c] (gated by d > 0), dhw[c] = sum dout d[.,c],
+ * dhb = sum dout (FP32, deterministic block partials). */
+int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout, void* g, float* dhw,
+                  float* dhb, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W,
+                  int32_t C, void* stream);
+
+/* Adam step t >= 1 on n FP32 parameters: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).  p16 (nullable) receives the
+ * bfloat16 rounding of the updated p. */
+int unet_adam(float* p, const float* g, float* m, float* v, void* p16, size_t n, float lr, float b1,
+              float b2, float eps, int32_t t, void* stream);
+
+/* bfloat16 <-> FP32 copies of n values (round to nearest even). */
+int unet_to_bf16(const float* src, void* dst, size_t n, void* stream);
+int unet_to_f32(const void* src, float* dst, size_t n, void* stream);
+
+const char* unet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UNET_H */

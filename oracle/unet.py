@@ -158,16 +158,24 @@ def init_params(arch: Arch, seed: int):
     return p
 
 
-def forward(arch: Arch, p: dict, x):
+def _exact(a):
+    return a
+
+
+def forward(arch: Arch, p: dict, x, store=_exact, rin=None):
     """x: [N, H, W, in_channels]; channel 0 is the normalised input density.  Returns the
-    prediction [N, H, W] and the activations the backward pass needs."""
+    prediction [N, H, W] and the activations the backward pass needs.
+
+    store: applied to every convolution output (identity by default; bf16_round
+    models an implementation that keeps activations in bfloat16).  rin: the density
+    the head adds (default x[..., 0])."""
     cache = {"x": x}
     h = x
     skips = []
     L = len(arch.widths)
     for lvl in range(L):
-        a = relu(conv3x3(h, p[f"e{lvl}a.w"], p[f"e{lvl}a.b"]))
-        bb = relu(conv3x3(a, p[f"e{lvl}b.w"], p[f"e{lvl}b.b"]))
+        a = store(relu(conv3x3(h, p[f"e{lvl}a.w"], p[f"e{lvl}a.b"])))
+        bb = store(relu(conv3x3(a, p[f"e{lvl}b.w"], p[f"e{lvl}b.b"])))
         cache[f"e{lvl}_in"], cache[f"e{lvl}a"], cache[f"e{lvl}b"] = h, a, bb
         if lvl < L - 1:
             skips.append(bb)
@@ -176,16 +184,20 @@ def forward(arch: Arch, p: dict, x):
             h = bb
     for lvl in range(L - 2, -1, -1):
         cat = np.concatenate([upsample2(h), skips[lvl]], axis=3)
-        a = relu(conv3x3(cat, p[f"d{lvl}a.w"], p[f"d{lvl}a.b"]))
-        bb = relu(conv3x3(a, p[f"d{lvl}b.w"], p[f"d{lvl}b.b"]))
+        a = store(relu(conv3x3(cat, p[f"d{lvl}a.w"], p[f"d{lvl}a.b"])))
+        bb = store(relu(conv3x3(a, p[f"d{lvl}b.w"], p[f"d{lvl}b.b"])))
         cache[f"d{lvl}_in"], cache[f"d{lvl}a"], cache[f"d{lvl}b"] = cat, a, bb
         h = bb
-    out = head(h, p["head.w"], p["head.b"][0], x[..., 0])
+    out = head(h, p["head.w"], p["head.b"][0], x[..., 0] if rin is None else rin)
     return out, cache
 
 
-def backward(arch: Arch, p: dict, cache: dict, dout):
-    """Gradients of every parameter and of the input for dL/dout = dout."""
+def backward(arch: Arch, p: dict, cache: dict, dout, store=_exact):
+    """Gradients of every parameter and of the input for dL/dout = dout.
+
+    store: applied to every activation-gradient tensor an implementation would keep
+    (ReLU-gated gradients of convolution outputs, input gradients of convolutions,
+    the pooled-path gradients); identity by default."""
     gr = {}
     L = len(arch.widths)
     top = cache["d0b"]
@@ -195,11 +207,11 @@ def backward(arch: Arch, p: dict, cache: dict, dout):
     dskip = {}
     # decoder levels ran L-2, ..., 0; their backward runs 0, ..., L-2
     for lvl in range(0, L - 1):
-        gb = relu_grad(dh, cache[f"d{lvl}b"])
+        gb = store(relu_grad(dh, cache[f"d{lvl}b"]))
         gr[f"d{lvl}b.w"], gr[f"d{lvl}b.b"] = conv3x3_grad_weight(cache[f"d{lvl}a"], gb)
-        ga = relu_grad(conv3x3_grad_input(gb, p[f"d{lvl}b.w"]), cache[f"d{lvl}a"])
+        ga = store(relu_grad(conv3x3_grad_input(gb, p[f"d{lvl}b.w"]), cache[f"d{lvl}a"]))
         gr[f"d{lvl}a.w"], gr[f"d{lvl}a.b"] = conv3x3_grad_weight(cache[f"d{lvl}_in"], ga)
-        dcat = conv3x3_grad_input(ga, p[f"d{lvl}a.w"])
+        dcat = store(conv3x3_grad_input(ga, p[f"d{lvl}a.w"]))
         cu = dcat.shape[3] - arch.widths[lvl]
         dskip[lvl] = dcat[..., cu:]
         dh = upsample2_grad(dcat[..., :cu])
@@ -207,11 +219,13 @@ def backward(arch: Arch, p: dict, cache: dict, dout):
     for lvl in range(L - 1, -1, -1):
         if lvl < L - 1:
             dh = maxpool2_grad(cache[f"e{lvl}b"], dh) + dskip[lvl]
-        gb = relu_grad(dh, cache[f"e{lvl}b"])
+        gb = store(relu_grad(dh, cache[f"e{lvl}b"]))
         gr[f"e{lvl}b.w"], gr[f"e{lvl}b.b"] = conv3x3_grad_weight(cache[f"e{lvl}a"], gb)
-        ga = relu_grad(conv3x3_grad_input(gb, p[f"e{lvl}b.w"]), cache[f"e{lvl}a"])
+        ga = store(relu_grad(conv3x3_grad_input(gb, p[f"e{lvl}b.w"]), cache[f"e{lvl}a"]))
         gr[f"e{lvl}a.w"], gr[f"e{lvl}a.b"] = conv3x3_grad_weight(cache[f"e{lvl}_in"], ga)
         dh = conv3x3_grad_input(ga, p[f"e{lvl}a.w"])
+        if lvl > 0:
+            dh = store(dh)
     dx = dh.copy()
     dx[..., 0] += dout
     return gr, dx

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
 ARCH = "gfx950"
 
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "lbm_batch.cpp", "thermo.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "lbm_batch.cpp", "thermo.cpp", "unet_kernels.hip"]
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

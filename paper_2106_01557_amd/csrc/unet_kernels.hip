@@ -1,0 +1,883 @@
+// Kernels and C ABI of the learned warm start's U-Net (declared in include/unet.h).
+//
+// Activations are NHWC bfloat16 (raw 16-bit patterns).  The 3x3 convolutions are
+// implicit GEMMs on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16: FP32
+// accumulation of bfloat16 products): rows are pixels, columns output channels,
+// the reduction runs over (tap, input channel).  Operand layout of that instruction
+// for lane l of a wavefront: A row l%16, reduction indices 8(l/16)..8(l/16)+7; B
+// column l%16, the same reduction indices; result rows 4(l/16)..4(l/16)+3, column
+// l%16.  With channels innermost, each lane's 8 reduction values are 8 consecutive
+// channels of one pixel: one 16-byte load.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/unet.h"
+
+namespace unet_dev {
+namespace {
+
+typedef uint16_t bf16_t;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+
+// round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint32_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ uint4 ld16(const bf16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ void st16(bf16_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
+
+__device__ __forceinline__ float lo(uint32_t w) { return bf2f(w & 0xffffu); }
+__device__ __forceinline__ float hi(uint32_t w) { return bf2f(w >> 16); }
+__device__ __forceinline__ uint32_t pack(float a, float b) { return f2bf(a) | (f2bf(b) << 16); }
+
+__device__ __forceinline__ void unpack8(uint4 v, float* f) {
+    f[0] = lo(v.x); f[1] = hi(v.x); f[2] = lo(v.y); f[3] = hi(v.y);
+    f[4] = lo(v.z); f[5] = hi(v.z); f[6] = lo(v.w); f[7] = hi(v.w);
+}
+__device__ __forceinline__ uint4 pack8(const float* f) {
+    return make_uint4(pack(f[0], f[1]), pack(f[2], f[3]), pack(f[4], f[5]), pack(f[6], f[7]));
+}
+
+__device__ __forceinline__ bf16x8 as_frag(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ uint4 sel(bool keep, uint4 v) {
+    return keep ? v : make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution (forward; also the input gradient with flipped weights)
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+    const bf16_t* x;      // offset applied
+    const bf16_t* w;      // [C_out][9 C_in]
+    const float* bias;    // nullable
+    void* y;              // offset applied (elements of the output type)
+    const bf16_t* mask;   // nullable, offset applied
+    int ldx, ldy, ldm;
+    int lh, lw;           // log2 H, log2 W
+    int P;                // N H W
+    int Cin, Cout, relu;
+};
+
+// A wavefront computes (16 MT) pixels x (16 NT) output channels; a workgroup of four
+// wavefronts covers 64 MT consecutive pixels.  kTapOuter (C_in % 32 == 0): each
+// 32-wide reduction chunk lies inside one tap, so the tap loop is outside and the
+// per-lane pixel addresses are computed once per tap.  Out-of-range pixels and
+// channels load from a valid address and are zeroed by a select (no branches around
+// the loads).
+template <int MT, int NT, bool kTapOuter, bool kF32>
+__global__ void __launch_bounds__(256) k_conv3x3(const ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    const int p0 = (blockIdx.x * 4 + wave) * (16 * MT);
+    const int co0 = blockIdx.y * (16 * NT);
+    const int Hm = (1 << a.lh) - 1, Wm = (1 << a.lw) - 1;
+    const int K = 9 * a.Cin;
+    int pimg[MT], py[MT], px[MT];
+    bool pv[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        int p = p0 + 16 * m + row;
+        pv[m] = p < a.P;
+        if (!pv[m]) p = 0;
+        px[m] = p & Wm;
+        py[m] = (p >> a.lw) & Hm;
+        pimg[m] = (p >> (a.lw + a.lh)) << (a.lw + a.lh);
+    }
+    const bf16_t* wrow[NT];
+    bool cv[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = co0 + 16 * n + row;
+        cv[n] = co < a.Cout;
+        wrow[n] = a.w + (size_t)(cv[n] ? co : 0) * K;
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    if (kTapOuter) {
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
+            const bf16_t* xa[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int ys = (py[m] + dy) & Hm, xs = (px[m] + dx) & Wm;
+                xa[m] = a.x + (size_t)(pimg[m] + (ys << a.lw) + xs) * a.ldx + 8 * grp;
+            }
+            const int kb = tap * a.Cin + 8 * grp;
+            for (int c = 0; c < a.Cin; c += 32) {
+                uint4 A[MT], B[NT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) A[m] = ld16(xa[m] + c);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) B[n] = ld16(wrow[n] + kb + c);
+#pragma unroll
+                for (int m = 0; m < MT; ++m) A[m] = sel(pv[m], A[m]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) B[n] = sel(cv[n], B[n]);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]),
+                                                                            acc[m][n], 0, 0, 0);
+            }
+        }
+    } else {
+        for (int kc = 0; kc < K; kc += 32) {
+            const int k0 = kc + 8 * grp;
+            const bool kv = k0 < K;
+            const int tap = kv ? k0 / a.Cin : 0;
+            const int ci = kv ? k0 - tap * a.Cin : 0;
+            const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
+            uint4 A[MT], B[NT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int ys = (py[m] + dy) & Hm, xs = (px[m] + dx) & Wm;
+                A[m] = ld16(a.x + (size_t)(pimg[m] + (ys << a.lw) + xs) * a.ldx + ci);
+            }
+#pragma unroll
+            for (int n = 0; n < NT; ++n) B[n] = ld16(wrow[n] + (kv ? k0 : 0));
+#pragma unroll
+            for (int m = 0; m < MT; ++m) A[m] = sel(pv[m] && kv, A[m]);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) B[n] = sel(cv[n] && kv, B[n]);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]), acc[m][n],
+                                                                        0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = co0 + 16 * n + row;
+        if (co >= a.Cout) continue;
+        const float b = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = p0 + 16 * m + 4 * grp + r;
+                if (p >= a.P) continue;
+                float v = acc[m][n][r] + b;
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.mask && !(bf2f(a.mask[(size_t)p * a.ldm + co]) > 0.f)) v = 0.f;
+                if (kF32) static_cast<float*>(a.y)[(size_t)p * a.ldy + co] = v;
+                else static_cast<bf16_t*>(a.y)[(size_t)p * a.ldy + co] = (bf16_t)f2bf(v);
+            }
+        }
+    }
+}
+
+// wf[i][t][o] = w[o][8-t][i]
+__global__ void k_flip(const bf16_t* __restrict__ w, bf16_t* __restrict__ wf, int Cout, int Cin) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = Cout * 9 * Cin;
+    if (idx >= n) return;
+    const int o = idx % Cout, t = (idx / Cout) % 9, i = idx / (9 * Cout);
+    wf[idx] = w[((size_t)o * 9 + (8 - t)) * Cin + i];
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: dw[o][k] = sum_p g[p][o] X[p][k], X[p][k] = x[p + off_tap(k)][ci(k)]
+// ---------------------------------------------------------------------------
+// MFMA with rows = k (im2col column), columns = output channel, reduction = pixels.
+// The reduction runs over pixels, which are not contiguous in NHWC, so each
+// 32-pixel chunk of X and g is staged through LDS transposed ([k][pixel],
+// [o][pixel]).  Column K of X is the constant 1, which turns the same product
+// into the bias gradient.  Workgroup tile: 64 k x CT output channels; the pixel
+// range is split into slabs (grid z) whose partial sums are stored separately.
+struct WgArgs {
+    const bf16_t* x;
+    const bf16_t* g;
+    float* part;          // [slabs][Cout][Kt]
+    int ldx, ldg;
+    int lh, lw, P, Cin, Cout, K, Kt, slab;
+};
+
+constexpr int kLdsPad = 40;  // 32 pixels + 8: rows stay 16-byte aligned
+
+template <int CT>
+__global__ void __launch_bounds__(256) k_wgrad(const WgArgs a) {
+    __shared__ __attribute__((aligned(16))) bf16_t Xs[64][kLdsPad];
+    __shared__ __attribute__((aligned(16))) bf16_t Gs[CT][kLdsPad];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int kb = blockIdx.x * 64, cb = blockIdx.y * CT;
+    const int pbeg = blockIdx.z * a.slab;
+    const int pend = min(a.P, pbeg + a.slab);
+    const int Hm = (1 << a.lh) - 1, Wm = (1 << a.lw) - 1;
+    // loader roles: vector lg (8 consecutive k or channels) of pixel lp of the chunk
+    const int lg = t & 7, lp = t >> 3;
+    const int kx = kb + 8 * lg;
+    const int mode = kx < a.K ? 0 : (kx == a.K ? 1 : 2);  // data, bias column, zero
+    const int tap = mode == 0 ? kx / a.Cin : 0;
+    const int ci = mode == 0 ? kx - tap * a.Cin : 0;
+    const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
+    const int cg = cb + 8 * lg;  // first output channel of this thread's g vector
+    const bool gload = (CT == 64 || lg < 4) && cg < a.Cout;
+    // MFMA roles: CT = 64: 2 x 2 wavefronts of 32 k x 32 channels; CT = 32: 4 x 1 of 16 k x 32
+    constexpr int MI = CT == 64 ? 2 : 1;
+    const int wk = CT == 64 ? (wave & 1) * 32 : wave * 16;
+    const int wc = CT == 64 ? (wave >> 1) * 32 : 0;
+    f32x4 acc[MI][2];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int p = pbeg; p < pend; p += 32) {
+        const int pp = p + lp;
+        const bool ok = pp < pend;
+        const int q = ok ? pp : pbeg;
+        uint4 xv = make_uint4(0u, 0u, 0u, 0u), gv = make_uint4(0u, 0u, 0u, 0u);
+        if (mode == 0) {
+            const int base = (q >> (a.lw + a.lh)) << (a.lw + a.lh);
+            const int ys = ((q >> a.lw) + dy) & Hm, xs = ((q & Wm) + dx) & Wm;
+            xv = ld16(a.x + (size_t)(base + (ys << a.lw) + xs) * a.ldx + ci);
+        } else if (mode == 1) {
+            xv.x = 0x3f80u;  // bfloat16 1.0 in element 0 (k == K), zeros after it
+        }
+        if (gload) gv = ld16(a.g + (size_t)q * a.ldg + cg);
+        xv = sel(ok, xv);
+        gv = sel(ok, gv);
+        __syncthreads();  // the previous chunk's fragments have been read
+        const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w};
+        const uint32_t gw[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Xs[8 * lg + 2 * j][lp] = (bf16_t)(xw[j] & 0xffffu);
+            Xs[8 * lg + 2 * j + 1][lp] = (bf16_t)(xw[j] >> 16);
+        }
+        if (CT == 64 || lg < 4) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                Gs[8 * lg + 2 * j][lp] = (bf16_t)(gw[j] & 0xffffu);
+                Gs[8 * lg + 2 * j + 1][lp] = (bf16_t)(gw[j] >> 16);
+            }
+        }
+        __syncthreads();
+        const int r16 = lane & 15, k8 = 8 * (lane >> 4);
+        uint4 A[MI], B[2];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) A[i] = *reinterpret_cast<const uint4*>(&Xs[wk + 16 * i + r16][k8]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) B[j] = *reinterpret_cast<const uint4*>(&Gs[wc + 16 * j + r16][k8]);
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[i]), as_frag(B[j]), acc[i][j], 0, 0, 0);
+    }
+    float* part = a.part + (size_t)blockIdx.z * a.Cout * a.Kt;
+    const int r16 = lane & 15, g4 = 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int co = cb + wc + 16 * j + r16;
+        if (co >= a.Cout) continue;
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[(size_t)co * a.Kt + kb + wk + 16 * i + g4 + r] = acc[i][j][r];
+    }
+}
+
+// dw[o][k] = sum_s part[s][o][k] (k < K), db[o] = sum_s part[s][o][K]; slabs in order
+__global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, float* __restrict__ db,
+                               int slabs, int Cout, int K, int Kt) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Cout * (K + 1)) return;
+    const int o = idx / (K + 1), k = idx - o * (K + 1);
+    float s = 0.f;
+    for (int z = 0; z < slabs; ++z) s += part[((size_t)z * Cout + o) * Kt + k];
+    if (k < K) dw[(size_t)o * K + k] = s;
+    else if (db) db[o] = s;
+}
+
+// ---------------------------------------------------------------------------
+// pooling, upsampling (16-byte vectors of 8 channels)
+// ---------------------------------------------------------------------------
+struct Geo {
+    int N, lh, lw, C;  // lh, lw: log2 of the larger (unpooled) size
+};
+
+__device__ __forceinline__ void small_pixel(int idx, const Geo& g, int& cg, int& n, int& Y, int& X) {
+    const int cgs = g.C >> 3;
+    cg = idx % cgs;
+    int r = idx / cgs;
+    X = r & ((1 << (g.lw - 1)) - 1);
+    r >>= g.lw - 1;
+    Y = r & ((1 << (g.lh - 1)) - 1);
+    n = r >> (g.lh - 1);
+}
+
+__global__ void k_pool_fwd(const bf16_t* x, int ldx, bf16_t* y, int ldy, Geo g, int total) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int cg, n, Y, X;
+    small_pixel(idx, g, cg, n, Y, X);
+    const int W = 1 << g.lw, H = 1 << g.lh;
+    const size_t p00 = ((size_t)n * H + 2 * Y) * W + 2 * X;
+    float m[8], v[8];
+    unpack8(ld16(x + p00 * ldx + 8 * cg), m);
+    const size_t ps[3] = {p00 + 1, p00 + W, p00 + W + 1};
+    for (int k = 0; k < 3; ++k) {
+        unpack8(ld16(x + ps[k] * ldx + 8 * cg), v);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) m[c] = v[c] > m[c] ? v[c] : m[c];
+    }
+    const size_t q = ((size_t)n * (H >> 1) + Y) * (W >> 1) + X;
+    st16(y + q * ldy + 8 * cg, pack8(m));
+}
+
+__global__ void k_pool_bwd(const bf16_t* x, int ldx, const bf16_t* dy, int lddy, const bf16_t* add, int lda,
+                           bf16_t* dx, int lddx, int gate, Geo g, int total) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int cg, n, Y, X;
+    small_pixel(idx, g, cg, n, Y, X);
+    const int W = 1 << g.lw, H = 1 << g.lh;
+    const size_t p00 = ((size_t)n * H + 2 * Y) * W + 2 * X;
+    const size_t ps[4] = {p00, p00 + 1, p00 + W, p00 + W + 1};
+    float xv[4][8], d[8];
+    for (int k = 0; k < 4; ++k) unpack8(ld16(x + ps[k] * ldx + 8 * cg), xv[k]);
+    const size_t q = ((size_t)n * (H >> 1) + Y) * (W >> 1) + X;
+    unpack8(ld16(dy + q * lddy + 8 * cg), d);
+    int arg[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        int best = 0;
+        for (int k = 1; k < 4; ++k)
+            if (xv[k][c] > xv[best][c]) best = k;
+        arg[c] = best;
+    }
+    for (int k = 0; k < 4; ++k) {
+        float o[8], ad[8];
+        if (add) unpack8(ld16(add + ps[k] * lda + 8 * cg), ad);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float v = arg[c] == k ? d[c] : 0.f;
+            if (add) v += ad[c];
+            if (gate && !(xv[k][c] > 0.f)) v = 0.f;
+            o[c] = v;
+        }
+        st16(dx + ps[k] * lddx + 8 * cg, pack8(o));
+    }
+}
+
+// g describes the large (output) size
+__global__ void k_up_fwd(const bf16_t* x, int ldx, bf16_t* y, int ldy, Geo g, int total) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int cg, n, Y, X;
+    small_pixel(idx, g, cg, n, Y, X);
+    const int W = 1 << g.lw, H = 1 << g.lh;
+    const size_t q = ((size_t)n * (H >> 1) + Y) * (W >> 1) + X;
+    const uint4 v = ld16(x + q * ldx + 8 * cg);
+    const size_t p00 = ((size_t)n * H + 2 * Y) * W + 2 * X;
+    st16(y + p00 * ldy + 8 * cg, v);
+    st16(y + (p00 + 1) * ldy + 8 * cg, v);
+    st16(y + (p00 + W) * ldy + 8 * cg, v);
+    st16(y + (p00 + W + 1) * ldy + 8 * cg, v);
+}
+
+__global__ void k_up_bwd(const bf16_t* dy, int lddy, const bf16_t* gate, int ldgt, bf16_t* dx, int lddx, Geo g,
+                         int total) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int cg, n, Y, X;
+    small_pixel(idx, g, cg, n, Y, X);
+    const int W = 1 << g.lw, H = 1 << g.lh;
+    const size_t p00 = ((size_t)n * H + 2 * Y) * W + 2 * X;
+    const size_t ps[4] = {p00, p00 + 1, p00 + W, p00 + W + 1};
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, v[8];
+    for (int k = 0; k < 4; ++k) {
+        unpack8(ld16(dy + ps[k] * lddy + 8 * cg), v);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s[c] += v[c];
+    }
+    const size_t q = ((size_t)n * (H >> 1) + Y) * (W >> 1) + X;
+    if (gate) {
+        float gt[8];
+        unpack8(ld16(gate + q * ldgt + 8 * cg), gt);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (!(gt[c] > 0.f)) s[c] = 0.f;
+    }
+    st16(dx + q * lddx + 8 * cg, pack8(s));
+}
+
+// ---------------------------------------------------------------------------
+// input, head and loss, optimizer
+// ---------------------------------------------------------------------------
+__global__ void k_prepare(const double* rho, const double* rv, const double* rl, const double* cond, bf16_t* x,
+                          float* rin, int lhw, int total) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int n = idx >> lhw;
+    const float v = (float)((rho[idx] - rv[n]) / (rl[n] - rv[n]));
+    if (rin) rin[idx] = v;
+    if (x) st16(x + (size_t)idx * 8, make_uint4(f2bf(v) | (f2bf((float)cond[n]) << 16), 0u, 0u, 0u));
+}
+
+__global__ void k_output(const float* out, const double* rv, const double* rl, double* rho, int lhw, int total) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int n = idx >> lhw;
+    rho[idx] = rv[n] + (rl[n] - rv[n]) * (double)out[idx];
+}
+
+constexpr int kHeadBlock = 256;
+
+// block sum of one float per thread (fixed tree order)
+__device__ __forceinline__ float block_sum(float v, float* sm) {
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kHeadBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    const float r = sm[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kHeadBlock) k_head_fwd(const bf16_t* d, int ldd, const float* hw, const float* hb,
+                                                         const float* rin, const float* target, float* out,
+                                                         float* dout, float* part, int C, int P) {
+    __shared__ float sm[kHeadBlock];
+    const int p = blockIdx.x * kHeadBlock + threadIdx.x;
+    float r2 = 0.f;
+    if (p < P) {
+        float s = hb[0] + rin[p];
+        for (int c = 0; c < C; c += 8) {
+            float v[8];
+            unpack8(ld16(d + (size_t)p * ldd + c), v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += hw[c + j] * v[j];
+        }
+        out[p] = s;
+        if (target) {
+            const float r = s - target[p];
+            dout[p] = 2.f * r / (float)P;
+            r2 = r * r;
+        }
+    }
+    if (target) {
+        const float b = block_sum(r2, sm);
+        if (threadIdx.x == 0) part[blockIdx.x] = b;
+    }
+}
+
+// part: [blocks][C + 1]: per-block sums of dout d[., c] and of dout
+__global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ldd, const float* hw,
+                                                         const float* dout, bf16_t* g, float* part, int C, int P) {
+    __shared__ float sm[kHeadBlock];
+    const int p = blockIdx.x * kHeadBlock + threadIdx.x;
+    const float dp = p < P ? dout[p] : 0.f;
+    for (int c = 0; c < C; c += 8) {
+        float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, o[8];
+        if (p < P) unpack8(ld16(d + (size_t)p * ldd + c), v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = v[j] > 0.f ? dp * hw[c + j] : 0.f;
+        if (p < P) st16(g + (size_t)p * C + c, pack8(o));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float b = block_sum(dp * v[j], sm);
+            if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 1) + c + j] = b;
+        }
+    }
+    const float b = block_sum(dp, sm);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 1) + C] = b;
+}
+
+// out[j] = sum over blocks of part[b][j] (j < m), in block order; scaled
+__global__ void k_sum_partials(const float* part, int blocks, int m, float scale, float* out0, float* out1) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += part[(size_t)b * m + j];
+    const float v = (float)(s * scale);
+    if (out1 && j == m - 1) out1[0] = v;
+    else out0[j] = v;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, bf16_t* p16, size_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (p16) p16[i] = (bf16_t)f2bf(pi);
+}
+
+__global__ void k_to_bf16(const float* s, bf16_t* d, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (bf16_t)f2bf(s[i]);
+}
+__global__ void k_to_f32(const bf16_t* s, float* d, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = bf2f(s[i]);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int launched(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(UNET_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return UNET_OK;
+}
+
+int log2_exact(int v) {
+    if (v < 2 || (v & (v - 1))) return -1;
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// tensor argument checks shared by every call: 16-byte aligned vectors of 8 channels
+int check_tensor(const char* name, const void* p, int ld, int off, int C, bool nullable) {
+    if (!p) return nullable ? UNET_OK : fail(UNET_EINVAL, "%s is NULL", name);
+    if (!aligned16(p)) return fail(UNET_EINVAL, "%s must be 16-byte aligned", name);
+    if (ld % 8 || off % 8 || off < 0 || ld < off + C)
+        return fail(UNET_EINVAL, "%s: ld (%d) and off (%d) must be multiples of 8 with ld >= off + C (%d)", name, ld,
+                    off, C);
+    return UNET_OK;
+}
+
+int check_geo(int N, int H, int W, int* lh, int* lw) {
+    *lh = log2_exact(H);
+    *lw = log2_exact(W);
+    if (N < 1 || *lh < 0 || *lw < 0) return fail(UNET_EINVAL, "N >= 1 and H, W powers of two >= 2 (got %d, %d, %d)", N, H, W);
+    if ((int64_t)N * H * W >= ((int64_t)1 << 31)) return fail(UNET_EINVAL, "N H W must stay below 2^31");
+    return UNET_OK;
+}
+
+template <int MT, int NT>
+void launch_conv(const ConvArgs& a, bool tap_outer, bool f32, hipStream_t s) {
+    const dim3 grid((a.P + 64 * MT - 1) / (64 * MT), (a.Cout + 16 * NT - 1) / (16 * NT));
+    if (tap_outer) {
+        if (f32) hipLaunchKernelGGL((k_conv3x3<MT, NT, true, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<MT, NT, true, false>), grid, dim3(256), 0, s, a);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_conv3x3<MT, NT, false, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<MT, NT, false, false>), grid, dim3(256), 0, s, a);
+    }
+}
+
+struct WgPlan {
+    int ktiles, ctiles, CT, slabs, slab, Kt;
+};
+
+WgPlan wgrad_plan(int P, int Cin, int Cout) {
+    WgPlan w;
+    const int K = 9 * Cin;
+    w.ktiles = (K + 1 + 63) / 64;
+    w.Kt = 64 * w.ktiles;
+    w.CT = Cout % 64 == 0 ? 64 : 32;
+    w.ctiles = (Cout + w.CT - 1) / w.CT;
+    const int want = 4096;  // workgroups to aim for
+    int slabs = (want + w.ktiles * w.ctiles - 1) / (w.ktiles * w.ctiles);
+    const int max_slabs = (P + 255) / 256;  // at least 256 pixels per slab
+    if (slabs > max_slabs) slabs = max_slabs;
+    if (slabs < 1) slabs = 1;
+    w.slab = ((P + slabs - 1) / slabs + 31) / 32 * 32;
+    w.slabs = (P + w.slab - 1) / w.slab;
+    return w;
+}
+
+}  // namespace
+}  // namespace unet_dev
+
+using namespace unet_dev;
+
+extern "C" {
+
+int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, const float* bias, void* y,
+                     int32_t ldy, int32_t offy, const void* mask, int32_t ldm, int32_t offm, int32_t N, int32_t H,
+                     int32_t W, int32_t C_in, int32_t C_out, int32_t flags, void* stream) {
+    int lh, lw, r;
+    if ((r = check_geo(N, H, W, &lh, &lw))) return r;
+    if (C_in < 8 || C_in % 8 || C_out < 16 || C_out % 16)
+        return fail(UNET_EINVAL, "C_in must be a multiple of 8 and C_out of 16 (got %d, %d)", C_in, C_out);
+    if (flags & ~(UNET_RELU | UNET_OUT_F32)) return fail(UNET_EINVAL, "unknown flags %d", flags);
+    if ((r = check_tensor("x", x, ldx, offx, C_in, false))) return r;
+    if ((r = check_tensor("mask", mask, ldm, offm, C_out, true))) return r;
+    if (!w || !aligned16(w)) return fail(UNET_EINVAL, "w must be non-NULL and 16-byte aligned");
+    if (!y || ldy < offy + C_out || offy < 0) return fail(UNET_EINVAL, "y: need ld >= off + C_out");
+    const bool f32 = flags & UNET_OUT_F32;
+    ConvArgs a;
+    a.x = static_cast<const bf16_t*>(x) + offx;
+    a.w = static_cast<const bf16_t*>(w);
+    a.bias = bias;
+    a.y = f32 ? (void*)(static_cast<float*>(y) + offy) : (void*)(static_cast<bf16_t*>(y) + offy);
+    a.mask = mask ? static_cast<const bf16_t*>(mask) + offm : nullptr;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.ldm = ldm;
+    a.lh = lh;
+    a.lw = lw;
+    a.P = N * H * W;
+    a.Cin = C_in;
+    a.Cout = C_out;
+    a.relu = (flags & UNET_RELU) ? 1 : 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool tap_outer = C_in % 32 == 0;
+    if (C_out % 64 == 0) launch_conv<2, 4>(a, tap_outer, f32, s);
+    else launch_conv<4, 2>(a, tap_outer, f32, s);
+    return launched("conv3x3 launch");
+}
+
+int unet_flip_weights(const void* w, void* wf, int32_t C_out, int32_t C_in, void* stream) {
+    if (!w || !wf || C_out < 1 || C_in < 1) return fail(UNET_EINVAL, "flip: bad arguments");
+    const int n = C_out * 9 * C_in;
+    hipLaunchKernelGGL(k_flip, dim3((n + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16_t*>(w), static_cast<bf16_t*>(wf), C_out, C_in);
+    return launched("flip launch");
+}
+
+int unet_wgrad_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, size_t* bytes) {
+    int lh, lw, r;
+    if ((r = check_geo(N, H, W, &lh, &lw))) return r;
+    if (!bytes || C_in < 8 || C_in % 8 || C_out < 16 || C_out % 16) return fail(UNET_EINVAL, "wgrad: bad channels");
+    const WgPlan p = wgrad_plan(N * H * W, C_in, C_out);
+    *bytes = (size_t)p.slabs * C_out * p.Kt * sizeof(float);
+    return UNET_OK;
+}
+
+int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, float* dw,
+                       float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C_in,
+                       int32_t C_out, void* stream) {
+    size_t need = 0;
+    int r;
+    if ((r = unet_wgrad_partial_bytes(N, H, W, C_in, C_out, &need))) return r;
+    if ((r = check_tensor("x", x, ldx, offx, C_in, false))) return r;
+    if ((r = check_tensor("g", g, ldg, offg, C_out, false))) return r;
+    if (!dw) return fail(UNET_EINVAL, "dw is NULL");
+    if (!partials || partial_bytes < need) return fail(UNET_EINVAL, "partials: %zu bytes needed", need);
+    int lh, lw;
+    check_geo(N, H, W, &lh, &lw);
+    const WgPlan p = wgrad_plan(N * H * W, C_in, C_out);
+    WgArgs a;
+    a.x = static_cast<const bf16_t*>(x) + offx;
+    a.g = static_cast<const bf16_t*>(g) + offg;
+    a.part = static_cast<float*>(partials);
+    a.ldx = ldx;
+    a.ldg = ldg;
+    a.lh = lh;
+    a.lw = lw;
+    a.P = N * H * W;
+    a.Cin = C_in;
+    a.Cout = C_out;
+    a.K = 9 * C_in;
+    a.Kt = p.Kt;
+    a.slab = p.slab;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid(p.ktiles, p.ctiles, p.slabs);
+    if (p.CT == 64) hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_wgrad<32>), grid, dim3(256), 0, s, a);
+    if ((r = launched("wgrad launch"))) return r;
+    const int n = C_out * (a.K + 1);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, a.part, dw, db, p.slabs, C_out, a.K,
+                       p.Kt);
+    return launched("wgrad reduce launch");
+}
+
+int unet_maxpool2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t ldy, int32_t offy, int32_t N,
+                      int32_t H, int32_t W, int32_t C, void* stream) {
+    int lh, lw, r;
+    if ((r = check_geo(N, H, W, &lh, &lw))) return r;
+    if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_tensor("x", x, ldx, offx, C, false)) || (r = check_tensor("y", y, ldy, offy, C, false))) return r;
+    const Geo g{N, lh, lw, C};
+    const int total = N * (H / 2) * (W / 2) * (C / 8);
+    hipLaunchKernelGGL(k_pool_fwd, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16_t*>(x) + offx, ldx, static_cast<bf16_t*>(y) + offy, ldy, g, total);
+    return launched("maxpool launch");
+}
+
+int unet_maxpool2_bwd(const void* x, int32_t ldx, int32_t offx, const void* dy, int32_t lddy, int32_t offdy,
+                      const void* add, int32_t lda, int32_t offa, void* dx, int32_t lddx, int32_t offdx,
+                      int32_t gate_relu, int32_t N, int32_t H, int32_t W, int32_t C, void* stream) {
+    int lh, lw, r;
+    if ((r = check_geo(N, H, W, &lh, &lw))) return r;
+    if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_tensor("x", x, ldx, offx, C, false)) || (r = check_tensor("dy", dy, lddy, offdy, C, false)) ||
+        (r = check_tensor("add", add, lda, offa, C, true)) || (r = check_tensor("dx", dx, lddx, offdx, C, false)))
+        return r;
+    const Geo g{N, lh, lw, C};
+    const int total = N * (H / 2) * (W / 2) * (C / 8);
+    hipLaunchKernelGGL(k_pool_bwd, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16_t*>(x) + offx, ldx, static_cast<const bf16_t*>(dy) + offdy, lddy,
+                       add ? static_cast<const bf16_t*>(add) + offa : nullptr, lda,
+                       static_cast<bf16_t*>(dx) + offdx, lddx, gate_relu ? 1 : 0, g, total);
+    return launched("maxpool bwd launch");
+}
+
+int unet_upsample2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t ldy, int32_t offy, int32_t N,
+                       int32_t H, int32_t W, int32_t C, void* stream) {
+    int lh, lw, r;
+    if ((r = check_geo(N, 2 * H, 2 * W, &lh, &lw))) return r;
+    if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_tensor("x", x, ldx, offx, C, false)) || (r = check_tensor("y", y, ldy, offy, C, false))) return r;
+    const Geo g{N, lh, lw, C};
+    const int total = N * H * W * (C / 8);
+    hipLaunchKernelGGL(k_up_fwd, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16_t*>(x) + offx, ldx, static_cast<bf16_t*>(y) + offy, ldy, g, total);
+    return launched("upsample launch");
+}
+
+int unet_upsample2_bwd(const void* dy, int32_t lddy, int32_t offdy, const void* gate, int32_t ldgt, int32_t offgt,
+                       void* dx, int32_t lddx, int32_t offdx, int32_t N, int32_t H, int32_t W, int32_t C,
+                       void* stream) {
+    int lh, lw, r;
+    if ((r = check_geo(N, 2 * H, 2 * W, &lh, &lw))) return r;
+    if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_tensor("dy", dy, lddy, offdy, C, false)) || (r = check_tensor("gate", gate, ldgt, offgt, C, true)) ||
+        (r = check_tensor("dx", dx, lddx, offdx, C, false)))
+        return r;
+    const Geo g{N, lh, lw, C};
+    const int total = N * H * W * (C / 8);
+    hipLaunchKernelGGL(k_up_bwd, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16_t*>(dy) + offdy, lddy,
+                       gate ? static_cast<const bf16_t*>(gate) + offgt : nullptr, ldgt,
+                       static_cast<bf16_t*>(dx) + offdx, lddx, g, total);
+    return launched("upsample bwd launch");
+}
+
+int unet_prepare_input(const double* rho, const double* rho_v, const double* rho_l, const double* cond, void* x,
+                       float* rin, int32_t N, int32_t H, int32_t W, void* stream) {
+    int lh, lw, r;
+    if ((r = check_geo(N, H, W, &lh, &lw))) return r;
+    if (!rho || !rho_v || !rho_l || !cond || (!x && !rin) || (x && !aligned16(x)))
+        return fail(UNET_EINVAL, "prepare: bad pointers");
+    const int total = N * H * W;
+    hipLaunchKernelGGL(k_prepare, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), rho,
+                       rho_v, rho_l, cond, static_cast<bf16_t*>(x), rin, lh + lw, total);
+    return launched("prepare launch");
+}
+
+int unet_output_density(const float* out, const double* rho_v, const double* rho_l, double* rho, int32_t N, int32_t H,
+                        int32_t W, void* stream) {
+    int lh, lw, r;
+    if ((r = check_geo(N, H, W, &lh, &lw))) return r;
+    if (!out || !rho_v || !rho_l || !rho) return fail(UNET_EINVAL, "output: bad pointers");
+    const int total = N * H * W;
+    hipLaunchKernelGGL(k_output, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), out, rho_v,
+                       rho_l, rho, lh + lw, total);
+    return launched("output launch");
+}
+
+int unet_head_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C, size_t* bytes) {
+    int lh, lw, r;
+    if ((r = check_geo(N, H, W, &lh, &lw))) return r;
+    if (!bytes || C < 8 || C % 8) return fail(UNET_EINVAL, "head: bad channels");
+    const size_t blocks = ((size_t)N * H * W + kHeadBlock - 1) / kHeadBlock;
+    *bytes = blocks * (C + 1) * sizeof(float);
+    return UNET_OK;
+}
+
+int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, const float* rin, const float* target,
+                  float* out, float* dout, float* loss, void* partials, size_t partial_bytes, int32_t N, int32_t H,
+                  int32_t W, int32_t C, void* stream) {
+    size_t need = 0;
+    int r;
+    if ((r = unet_head_partial_bytes(N, H, W, C, &need))) return r;
+    if ((r = check_tensor("d", d, ldd, 0, C, false))) return r;
+    if (!hw || !hb || !rin || !out) return fail(UNET_EINVAL, "head: NULL argument");
+    if (target && (!dout || !loss || !partials || partial_bytes < need))
+        return fail(UNET_EINVAL, "head with a target needs dout, loss and %zu bytes of partials", need);
+    const int P = N * H * W, blocks = (P + kHeadBlock - 1) / kHeadBlock;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_head_fwd, dim3(blocks), dim3(kHeadBlock), 0, s, static_cast<const bf16_t*>(d), ldd, hw, hb,
+                       rin, target, out, dout, static_cast<float*>(partials), C, P);
+    if ((r = launched("head launch"))) return r;
+    if (target) {
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, static_cast<const float*>(partials), blocks, 1,
+                           1.0f / (float)P, loss, (float*)nullptr);
+        return launched("loss reduce launch");
+    }
+    return UNET_OK;
+}
+
+int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout, void* g, float* dhw, float* dhb,
+                  void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, void* stream) {
+    size_t need = 0;
+    int r;
+    if ((r = unet_head_partial_bytes(N, H, W, C, &need))) return r;
+    if ((r = check_tensor("d", d, ldd, 0, C, false)) || (r = check_tensor("g", g, C, 0, C, false))) return r;
+    if (!hw || !dout || !dhw || !dhb || !partials || partial_bytes < need)
+        return fail(UNET_EINVAL, "head bwd: NULL argument or partials below %zu bytes", need);
+    const int P = N * H * W, blocks = (P + kHeadBlock - 1) / kHeadBlock;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(kHeadBlock), 0, s, static_cast<const bf16_t*>(d), ldd, hw, dout,
+                       static_cast<bf16_t*>(g), static_cast<float*>(partials), C, P);
+    if ((r = launched("head bwd launch"))) return r;
+    hipLaunchKernelGGL(k_sum_partials, dim3((C + 1 + 63) / 64), dim3(64), 0, s, static_cast<const float*>(partials),
+                       blocks, C + 1, 1.0f, dhw, dhb);
+    return launched("head reduce launch");
+}
+
+int unet_adam(float* p, const float* g, float* m, float* v, void* p16, size_t n, float lr, float b1, float b2,
+              float eps, int32_t t, void* stream) {
+    if (!p || !g || !m || !v || t < 1 || !(lr >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return fail(UNET_EINVAL, "adam: bad arguments");
+    if (n == 0) return UNET_OK;
+    const float c1 = (float)(1.0 - std::pow((double)b1, t)), c2 = (float)(1.0 - std::pow((double)b2, t));
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), p, g,
+                       m, v, static_cast<bf16_t*>(p16), n, lr, b1, b2, eps, c1, c2);
+    return launched("adam launch");
+}
+
+int unet_to_bf16(const float* src, void* dst, size_t n, void* stream) {
+    if (!src || !dst) return fail(UNET_EINVAL, "to_bf16: NULL");
+    if (n == 0) return UNET_OK;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), src,
+                       static_cast<bf16_t*>(dst), n);
+    return launched("to_bf16 launch");
+}
+
+int unet_to_f32(const void* src, float* dst, size_t n, void* stream) {
+    if (!src || !dst) return fail(UNET_EINVAL, "to_f32: NULL");
+    if (n == 0) return UNET_OK;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16_t*>(src), dst, n);
+    return launched("to_f32 launch");
+}
+
+const char* unet_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,324 @@
+"""Learned warm start: a U-Net that maps an initial density field to a later one,
+built on the network kernels of include/unet.h (bfloat16 activations, FP32
+accumulation on the matrix cores, FP32 master weights and Adam).
+
+Marshalling only: every arithmetic step of the forward pass, the backward pass and
+the optimizer runs in the library's kernels; torch provides device memory and the
+stream.  The architecture: encoder levels of widths (32, 64, 128, 256), each two
+3x3 convolutions with ReLU followed by 2x2 max pooling (none after the last, the
+bottleneck); decoder levels upsample 2x, concatenate the encoder level's output
+and apply two 3x3 convolutions with ReLU; a 1x1 head adds its output to the input
+density channel.  Convolutions wrap around (the lattice is periodic).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import lbm as _lbm
+
+_lib = _lbm.library()
+_P, _I, _F, _V, _S = ctypes.POINTER, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
+
+EXPORTED = ["unet_conv3x3_fwd", "unet_flip_weights", "unet_wgrad_partial_bytes", "unet_conv3x3_wgrad",
+            "unet_maxpool2_fwd", "unet_maxpool2_bwd", "unet_upsample2_fwd", "unet_upsample2_bwd",
+            "unet_prepare_input", "unet_output_density", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd", "unet_adam",
+            "unet_to_bf16", "unet_to_f32", "unet_last_error"]
+
+RELU, OUT_F32 = 1, 2
+
+_lib.unet_conv3x3_fwd.argtypes = [_V, _I, _I, _V, _V, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_flip_weights.argtypes = [_V, _V, _I, _I, _V]
+_lib.unet_wgrad_partial_bytes.argtypes = [_I, _I, _I, _I, _I, _P(_S)]
+_lib.unet_conv3x3_wgrad.argtypes = [_V, _I, _I, _V, _I, _I, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
+_lib.unet_maxpool2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_maxpool2_bwd.argtypes = [_V, _I, _I, _V, _I, _I, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_upsample2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_upsample2_bwd.argtypes = [_V, _I, _I, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_prepare_input.argtypes = [_V, _V, _V, _V, _V, _V, _I, _I, _I, _V]
+_lib.unet_output_density.argtypes = [_V, _V, _V, _V, _I, _I, _I, _V]
+_lib.unet_head_partial_bytes.argtypes = [_I, _I, _I, _I, _P(_S)]
+_lib.unet_head_fwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _V]
+_lib.unet_head_bwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _V]
+_lib.unet_adam.argtypes = [_V, _V, _V, _V, _V, _S, _F, _F, _F, _F, _I, _V]
+_lib.unet_to_bf16.argtypes = [_V, _V, _S, _V]
+_lib.unet_to_f32.argtypes = [_V, _V, _S, _V]
+_lib.unet_last_error.argtypes = []
+_lib.unet_last_error.restype = ctypes.c_char_p
+for _n in EXPORTED:
+    if _n != "unet_last_error":
+        getattr(_lib, _n).restype = ctypes.c_int
+
+
+class UnetError(RuntimeError):
+    pass
+
+
+def _ck(code):
+    if code != 0:
+        raise UnetError(f"{code}: {_lib.unet_last_error().decode()}")
+
+
+def ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def library():
+    return _lib
+
+
+def conv_layers(widths, in_channels):
+    """(name, C_in, C_out) of the 3x3 convolutions: two per encoder level, then two per
+    decoder level from the bottom up (the first reads the concatenation of the
+    upsampled lower level and the encoder level's output)."""
+    layers, cin = [], in_channels
+    for lvl, c in enumerate(widths):
+        layers.append((f"e{lvl}a", cin, c))
+        layers.append((f"e{lvl}b", c, c))
+        cin = c
+    for lvl in reversed(range(len(widths) - 1)):
+        layers.append((f"d{lvl}a", widths[lvl + 1] + widths[lvl], widths[lvl]))
+        layers.append((f"d{lvl}b", widths[lvl], widths[lvl]))
+    return layers
+
+
+class UNet:
+    """Parameters (FP32 masters, bfloat16 copies and flipped copies for the input
+    gradient) and per-batch-shape activation buffers on one device."""
+
+    def __init__(self, widths=(32, 64, 128, 256), in_channels=8, seed=0, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.widths = tuple(int(w) for w in widths)
+        self.in_channels = int(in_channels)
+        self.layers = conv_layers(self.widths, self.in_channels)
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.s = ctypes.c_void_p(self.stream.cuda_stream)
+        self.t = 0
+        rng = np.random.Generator(np.random.PCG64(seed))
+        p = {}
+        for name, ci, co in self.layers:  # He-normal weights, zero biases
+            p[name + ".w"] = rng.standard_normal((co, 3, 3, ci)) * np.sqrt(2.0 / (9 * ci))
+            p[name + ".b"] = np.zeros(co)
+        c0 = self.widths[0]
+        p["head.w"] = rng.standard_normal(c0) / np.sqrt(c0)
+        p["head.b"] = np.zeros(1)
+        self.load_params(p)
+        self._shape = None
+
+    # -- parameters ------------------------------------------------------------------
+    def _f32(self, a):
+        return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
+
+    def load_params(self, p: dict):
+        torch = self.torch
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            self.p = {k: self._f32(v).reshape(-1) for k, v in p.items()}
+            self.m = {k: torch.zeros_like(v) for k, v in self.p.items()}
+            self.v = {k: torch.zeros_like(v) for k, v in self.p.items()}
+            self.w16, self.wf16 = {}, {}
+            for name, ci, co in self.layers:
+                w = self.p[name + ".w"]
+                self.w16[name] = torch.empty(w.numel(), dtype=torch.bfloat16, device=self.device)
+                self.wf16[name] = torch.empty(w.numel(), dtype=torch.bfloat16, device=self.device)
+            self._refresh_copies()
+        self.t = 0
+
+    def _refresh_copies(self):
+        for name, ci, co in self.layers:
+            w = self.p[name + ".w"]
+            _ck(_lib.unet_to_bf16(ptr(w), ptr(self.w16[name]), w.numel(), self.s))
+            _ck(_lib.unet_flip_weights(ptr(self.w16[name]), ptr(self.wf16[name]), co, ci, self.s))
+
+    def params_numpy(self) -> dict:
+        self.stream.synchronize()
+        out = {}
+        for k, v in self.p.items():
+            a = v.cpu().numpy().astype(np.float64)
+            if k.endswith(".w") and not k.startswith("head"):
+                name = k[:-2]
+                ci, co = next((c, o) for n, c, o in self.layers if n == name)
+                a = a.reshape(co, 3, 3, ci)
+            out[k] = a
+        return out
+
+    # -- buffers -----------------------------------------------------------------------
+    def _alloc(self, N, H, W):
+        if self._shape == (N, H, W):
+            return
+        torch = self.torch
+        L = len(self.widths)
+        if H % (1 << (L - 1)) or W % (1 << (L - 1)):
+            raise UnetError(f"H and W must be multiples of {1 << (L - 1)}")
+        bf = lambda *s: torch.empty(s, dtype=torch.bfloat16, device=self.device)
+        f32 = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
+        b = {}
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            b["x0"], b["rin"], b["target"] = bf(N, H, W, self.in_channels), f32(N, H, W), f32(N, H, W)
+            b["out"], b["dout"] = f32(N, H, W), f32(N, H, W)
+            for lvl, c in enumerate(self.widths):
+                h, w = H >> lvl, W >> lvl
+                b[f"e{lvl}a"] = bf(N, h, w, c)
+                b[f"ge{lvl}a"] = bf(N, h, w, c)
+                b[f"ge{lvl}b"] = bf(N, h, w, c)
+                if lvl < L - 1:
+                    cu = self.widths[lvl + 1]
+                    b[f"cat{lvl}"] = bf(N, h, w, cu + c)     # [upsampled lower level | e{lvl}b]
+                    b[f"dcat{lvl}"] = bf(N, h, w, cu + c)
+                    b[f"pool{lvl}"] = bf(N, h // 2, w // 2, c)
+                    b[f"dpool{lvl}"] = bf(N, h // 2, w // 2, c)
+                    b[f"d{lvl}a"], b[f"d{lvl}b"] = bf(N, h, w, c), bf(N, h, w, c)
+                    b[f"gd{lvl}a"], b[f"gd{lvl}b"] = bf(N, h, w, c), bf(N, h, w, c)
+                else:
+                    b[f"e{lvl}b"] = bf(N, h, w, c)
+            need = 0
+            for name, ci, co in self.layers:
+                lvl = int(name[1])
+                nb = _S()
+                _ck(_lib.unet_wgrad_partial_bytes(N, H >> lvl, W >> lvl, ci, co, ctypes.byref(nb)))
+                need = max(need, nb.value)
+            nb = _S()
+            _ck(_lib.unet_head_partial_bytes(N, H, W, self.widths[0], ctypes.byref(nb)))
+            b["wpart"] = torch.empty(need, dtype=torch.uint8, device=self.device)
+            b["hpart"] = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            b["loss"] = f32(1)
+            self.g = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.buf = b
+        self._shape = (N, H, W)
+
+    # -- passes --------------------------------------------------------------------------
+    def _conv(self, name, x, ldx, offx, y, ldy, offy, N, h, w, flags=RELU, mask=None, ldm=0, offm=0):
+        ci, co = next((c, o) for n, c, o in self.layers if n == name)
+        _ck(_lib.unet_conv3x3_fwd(ptr(x), ldx, offx, ptr(self.w16[name]), ptr(self.p[name + ".b"]), ptr(y), ldy,
+                                  offy, ptr(mask), ldm, offm, N, h, w, ci, co, flags, self.s))
+
+    def forward(self, rho, rho_v, rho_l, cond, target=None):
+        """rho: FP64 [N, H, W] device densities; rho_v, rho_l, cond: FP64 [N] device
+        tensors (normalisation and the conditioning channel); target: FP64 [N, H, W]
+        device densities or None.  Returns the normalised prediction (FP32 [N, H, W],
+        a view into the model's buffer) and, with a target, the loss tensor."""
+        torch = self.torch
+        N, H, W = rho.shape
+        self._alloc(N, H, W)
+        b, L, wd = self.buf, len(self.widths), self.widths
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            _ck(_lib.unet_prepare_input(ptr(rho), ptr(rho_v), ptr(rho_l), ptr(cond), ptr(b["x0"]), ptr(b["rin"]),
+                                        N, H, W, self.s))
+            if target is not None:
+                # the target goes through the same normalisation
+                _ck(_lib.unet_prepare_input(ptr(target), ptr(rho_v), ptr(rho_l), ptr(cond), None, ptr(b["target"]),
+                                            N, H, W, self.s))
+            x, ldx, offx = b["x0"], self.in_channels, 0
+            for lvl in range(L):
+                h, w, c = H >> lvl, W >> lvl, wd[lvl]
+                self._conv(f"e{lvl}a", x, ldx, offx, b[f"e{lvl}a"], c, 0, N, h, w)
+                if lvl < L - 1:
+                    cu = wd[lvl + 1]
+                    cat = b[f"cat{lvl}"]
+                    self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, cat, cu + c, cu, N, h, w)
+                    _ck(_lib.unet_maxpool2_fwd(ptr(cat), cu + c, cu, ptr(b[f"pool{lvl}"]), c, 0, N, h, w, c, self.s))
+                    x, ldx, offx = b[f"pool{lvl}"], c, 0
+                else:
+                    self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"e{lvl}b"], c, 0, N, h, w)
+            low, ldl = b[f"e{L - 1}b"], wd[L - 1]
+            for lvl in reversed(range(L - 1)):
+                h, w, c, cu = H >> lvl, W >> lvl, wd[lvl], wd[lvl + 1]
+                cat = b[f"cat{lvl}"]
+                _ck(_lib.unet_upsample2_fwd(ptr(low), ldl, 0, ptr(cat), cu + c, 0, N, h // 2, w // 2, cu, self.s))
+                self._conv(f"d{lvl}a", cat, cu + c, 0, b[f"d{lvl}a"], c, 0, N, h, w)
+                self._conv(f"d{lvl}b", b[f"d{lvl}a"], c, 0, b[f"d{lvl}b"], c, 0, N, h, w)
+                low, ldl = b[f"d{lvl}b"], c
+            tgt = b["target"] if target is not None else None
+            _ck(_lib.unet_head_fwd(ptr(low), wd[0], ptr(self.p["head.w"]), ptr(self.p["head.b"]), ptr(b["rin"]),
+                                   ptr(tgt), ptr(b["out"]), ptr(b["dout"]), ptr(b["loss"]), ptr(b["hpart"]),
+                                   b["hpart"].numel(), N, H, W, wd[0], self.s))
+        return (b["out"], b["loss"]) if target is not None else b["out"]
+
+    def backward(self):
+        """Gradients (FP32, in self.g) of the loss of the last forward call with a target."""
+        torch = self.torch
+        N, H, W = self._shape
+        b, g, L, wd = self.buf, self.g, len(self.widths), self.widths
+        wp, nwp = b["wpart"], b["wpart"].numel()
+
+        def wgrad(name, x, ldx, offx, gy, ldg, h, w):
+            ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
+            _ck(_lib.unet_conv3x3_wgrad(ptr(x), ldx, offx, ptr(gy), ldg, 0, ptr(g[name + ".w"]), ptr(g[name + ".b"]),
+                                        ptr(wp), nwp, N, h, w, ci, co, self.s))
+
+        def dgrad(name, gy, ldg, dx, lddx, h, w, mask=None, ldm=0, offm=0):
+            ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
+            # input gradient = forward convolution of gy with the flipped weights
+            _ck(_lib.unet_conv3x3_fwd(ptr(gy), ldg, 0, ptr(self.wf16[name]), None, ptr(dx), lddx, 0, ptr(mask), ldm,
+                                      offm, N, h, w, co, ci, 0, self.s))
+
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            top = b["d0b"]
+            _ck(_lib.unet_head_bwd(ptr(top), wd[0], ptr(self.p["head.w"]), ptr(b["dout"]), ptr(b["gd0b"]),
+                                   ptr(g["head.w"]), ptr(g["head.b"]), ptr(b["hpart"]), b["hpart"].numel(), N, H, W,
+                                   wd[0], self.s))
+            # decoder, top level first
+            for lvl in range(L - 1):
+                h, w, c, cu = H >> lvl, W >> lvl, wd[lvl], wd[lvl + 1]
+                wgrad(f"d{lvl}b", b[f"d{lvl}a"], c, 0, b[f"gd{lvl}b"], c, h, w)
+                dgrad(f"d{lvl}b", b[f"gd{lvl}b"], c, b[f"gd{lvl}a"], c, h, w, mask=b[f"d{lvl}a"], ldm=c)
+                wgrad(f"d{lvl}a", b[f"cat{lvl}"], cu + c, 0, b[f"gd{lvl}a"], c, h, w)
+                dgrad(f"d{lvl}a", b[f"gd{lvl}a"], c, b[f"dcat{lvl}"], cu + c, h, w)
+                # gradient of the lower level's output, gated by its ReLU
+                if lvl + 1 < L - 1:
+                    low, dlow = b[f"d{lvl + 1}b"], b[f"gd{lvl + 1}b"]
+                else:
+                    low, dlow = b[f"e{lvl + 1}b"], b[f"ge{lvl + 1}b"]
+                _ck(_lib.unet_upsample2_bwd(ptr(b[f"dcat{lvl}"]), cu + c, 0, ptr(low), cu, 0, ptr(dlow), cu, 0, N,
+                                            h // 2, w // 2, cu, self.s))
+            # encoder, bottleneck first
+            for lvl in reversed(range(L)):
+                h, w, c = H >> lvl, W >> lvl, wd[lvl]
+                if lvl < L - 1:
+                    cu = wd[lvl + 1]
+                    cat = b[f"cat{lvl}"]
+                    # pooled-path gradient plus the skip-connection gradient, gated by e{lvl}b > 0
+                    _ck(_lib.unet_maxpool2_bwd(ptr(cat), cu + c, cu, ptr(b[f"dpool{lvl}"]), c, 0, ptr(b[f"dcat{lvl}"]),
+                                               cu + c, cu, ptr(b[f"ge{lvl}b"]), c, 0, 1, N, h, w, c, self.s))
+                wgrad(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"ge{lvl}b"], c, h, w)
+                dgrad(f"e{lvl}b", b[f"ge{lvl}b"], c, b[f"ge{lvl}a"], c, h, w, mask=b[f"e{lvl}a"], ldm=c)
+                if lvl > 0:
+                    cp = wd[lvl - 1]
+                    wgrad(f"e{lvl}a", b[f"pool{lvl - 1}"], cp, 0, b[f"ge{lvl}a"], c, h, w)
+                    dgrad(f"e{lvl}a", b[f"ge{lvl}a"], c, b[f"dpool{lvl - 1}"], cp, h, w)
+                else:
+                    wgrad("e0a", b["x0"], self.in_channels, 0, b["ge0a"], c, h, w)
+        return g
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        torch = self.torch
+        self.t += 1
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            for k, p in self.p.items():
+                name = k[:-2]
+                p16 = self.w16[name] if (k.endswith(".w") and name in self.w16) else None
+                _ck(_lib.unet_adam(ptr(p), ptr(self.g[k]), ptr(self.m[k]), ptr(self.v[k]), ptr(p16), p.numel(), lr,
+                                   b1, b2, eps, self.t, self.s))
+            for name, ci, co in self.layers:
+                _ck(_lib.unet_flip_weights(ptr(self.w16[name]), ptr(self.wf16[name]), co, ci, self.s))
+
+    def train_step(self, rho0, target, rho_v, rho_l, cond, lr=1e-3):
+        _, loss = self.forward(rho0, rho_v, rho_l, cond, target)
+        self.backward()
+        self.adam_step(lr)
+        return loss
+
+    def predict_density(self, rho0, rho_v, rho_l, cond):
+        """Predicted density (FP64 [N, H, W] device tensor): the normalised output mapped
+        back with each sample's (rho_v, rho_l)."""
+        torch = self.torch
+        out = self.forward(rho0, rho_v, rho_l, cond)
+        N, H, W = rho0.shape
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            res = torch.empty((N, H, W), dtype=torch.float64, device=self.device)
+            _ck(_lib.unet_output_density(ptr(out), ptr(rho_v), ptr(rho_l), ptr(res), N, H, W, self.s))
+        return res

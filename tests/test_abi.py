@@ -13,10 +13,10 @@ from oracle import thermo
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+def _declared(header="lbm.h", prefix="lbm_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_0-9]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -32,6 +32,36 @@ def test_library_exports_every_declared_function(lbm):
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
     assert sorted(lbm.EXPORTED) == names
+
+
+def test_library_exports_every_network_function(lbm):
+    from paper_2106_01557_amd import unet
+    names = _declared("unet.h", "unet_")
+    assert len(names) >= 15
+    lib = ctypes.CDLL(lbm.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(unet.EXPORTED) == names
+
+
+def test_network_calls_validate_before_launching(lbm):
+    from paper_2106_01557_amd import unet
+    lib = unet.library()
+    V = ctypes.c_void_p
+    buf = V(1 << 20)
+    # H not a power of two, C_out not a multiple of 16, misaligned tensor, bad ld/off
+    assert lib.unet_conv3x3_fwd(buf, 8, 0, buf, None, buf, 16, 0, None, 0, 0, 1, 6, 8, 8, 16, 0, None) == -1
+    assert lib.unet_conv3x3_fwd(buf, 8, 0, buf, None, buf, 24, 0, None, 0, 0, 1, 8, 8, 8, 24, 0, None) == -1
+    assert lib.unet_conv3x3_fwd(V((1 << 20) + 2), 8, 0, buf, None, buf, 16, 0, None, 0, 0, 1, 8, 8, 8, 16, 0,
+                                None) == -1
+    assert lib.unet_conv3x3_fwd(buf, 12, 0, buf, None, buf, 16, 0, None, 0, 0, 1, 8, 8, 8, 16, 0, None) == -1
+    assert lib.unet_conv3x3_fwd(buf, 8, 0, buf, None, buf, 16, 0, None, 0, 0, 1, 8, 8, 8, 16, 8, None) == -1
+    assert "flags" in lib.unet_last_error().decode()
+    nb = ctypes.c_size_t()
+    assert lib.unet_wgrad_partial_bytes(2, 64, 64, 32, 32, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib.unet_conv3x3_wgrad(buf, 32, 0, buf, 32, 0, buf, buf, buf, nb.value - 1, 2, 64, 64, 32, 32, None) == -1
+    assert lib.unet_adam(buf, buf, buf, buf, None, 10, ctypes.c_float(1e-3), ctypes.c_float(0.9),
+                         ctypes.c_float(0.999), ctypes.c_float(1e-8), 0, None) == -1
 
 
 @pytest.mark.parametrize("eos_kind", ["cs", "vdw"])
