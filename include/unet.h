@@ -81,31 +81,36 @@ int unet_upsample2_bwd(const void* dy, int32_t lddy, int32_t offdy, const void* 
                        int32_t offgt, void* dx, int32_t lddx, int32_t offdx, int32_t N, int32_t H, int32_t W,
                        int32_t C, void* stream);
 
-/* Network input from density fields: x[n,p,0] = (rho - rho_v[n]) / (rho_l[n] - rho_v[n]),
- * x[n,p,1] = cond[n], channels 2..7 zero (x is [N,H,W,8] bfloat16); rin (FP32)
- * receives channel 0 unrounded.  rho is FP64 [N,H,W]; x or rin may be NULL, not both. */
-int unet_prepare_input(const double* rho, const double* rho_v, const double* rho_l, const double* cond,
-                       void* x, float* rin, int32_t N, int32_t H, int32_t W, void* stream);
+/* Network input from the fields of a lattice state: x[n,p,0] = (rho - rho_v[n]) /
+ * (rho_l[n] - rho_v[n]), x[n,p,1] = cond[n], x[n,p,2] = (T / T0[n] - 1) / theta_scale
+ * (0 when T is NULL), channels 3..7 zero (x is [N,H,W,8] bfloat16).  rin (FP32,
+ * [2][N,H,W]) receives channels 0 and 2 unrounded: the residual the head adds.  rho
+ * and T are FP64 [N,H,W]; x or rin may be NULL, not both. */
+int unet_prepare_input(const double* rho, const double* T, const double* rho_v, const double* rho_l,
+                       const double* T0, const double* cond, double theta_scale, void* x, float* rin,
+                       int32_t N, int32_t H, int32_t W, void* stream);
 
-/* Density from the normalised prediction: rho[n,p] = rho_v[n] + (rho_l[n] - rho_v[n]) out[n,p]
- * (out FP32, rho FP64, both [N,H,W]). */
-int unet_output_density(const float* out, const double* rho_v, const double* rho_l, double* rho,
-                        int32_t N, int32_t H, int32_t W, void* stream);
+/* Fields from the K normalised output planes (FP32 [K][N,H,W]): rho = rho_v + (rho_l -
+ * rho_v) out[0]; T (nullable) = T0 (1 + theta_scale out[1]) (T0 when K = 1). */
+int unet_output_fields(const float* out, int32_t K, const double* rho_v, const double* rho_l,
+                       const double* T0, double theta_scale, double* rho, double* T, int32_t N, int32_t H,
+                       int32_t W, void* stream);
 
-/* Output head: out[n,p] = sum_c hw[c] d[n,p,c] + hb + rin[n,p] (FP32).  With target
- * (nullable) also the loss: dout = 2 (out - target) / (N H W) and the mean squared
- * error is written to loss[0] (both FP32; the sum uses per-block partials in
- * `partials`, >= unet_head_partial_bytes(), added in a fixed order). */
-int unet_head_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C, size_t* bytes);
+/* Output head, K <= 4 outputs: out[k][n,p] = sum_c hw[k][c] d[n,p,c] + hb[k] + rin[k][n,p]
+ * (FP32 planes).  With target (nullable, [K][N,H,W]) also the loss over all K N H W
+ * values: dout = 2 (out - target) / (K N H W) and the mean squared error in loss[0]
+ * (the sum uses per-block partials in `partials`, >= unet_head_partial_bytes(),
+ * added in a fixed order). */
+int unet_head_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C, int32_t K, size_t* bytes);
 int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, const float* rin,
                   const float* target, float* out, float* dout, float* loss, void* partials,
-                  size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
+                  size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, int32_t K, void* stream);
 
-/* Head gradient: g[n,p,c] = dout[n,p] hw[c] (gated by d > 0), dhw[c] = sum dout d[.,c],
- * dhb = sum dout (FP32, deterministic block partials). */
+/* Head gradient: g[n,p,c] = sum_k dout[k][n,p] hw[k][c] (gated by d > 0), dhw[k][c] =
+ * sum dout[k] d[.,c], dhb[k] = sum dout[k] (FP32, deterministic block partials). */
 int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout, void* g, float* dhw,
                   float* dhb, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W,
-                  int32_t C, void* stream);
+                  int32_t C, int32_t K, void* stream);
 
 /* Adam step t >= 1 on n FP32 parameters: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).  p16 (nullable) receives the

@@ -101,9 +101,10 @@ def upsample2_grad(g):
     return g.reshape(n, h // 2, 2, w // 2, 2, c).sum(axis=(2, 4))
 
 
-def head(d, w, b, rho):
-    """out[n,y,x] = sum_c w[c] d[n,y,x,c] + b + rho[n,y,x] (residual on the input density)."""
-    return d @ w + b + rho
+def head(d, w, b, rin):
+    """out[n,y,x,k] = sum_c w[k,c] d[n,y,x,c] + b[k] + rin[n,y,x,k]: K outputs, each the
+    residual on an input field (the density; with K = 2 also the temperature deviation)."""
+    return d @ w.T + b + rin
 
 
 def mse(pred, target):
@@ -129,7 +130,13 @@ class Arch:
     `used_inputs` carry data, the rest are zero padding)."""
     widths: tuple = (32, 64, 128, 256)
     in_channels: int = 8
-    used_inputs: int = 2
+    used_inputs: int = 3
+    outputs: int = 1
+
+    def residual_channels(self):
+        """Input channels the head adds to its outputs: the density (channel 0) and, for a
+        second output, the temperature deviation (channel 2)."""
+        return [0, 2][: self.outputs]
 
     def convs(self):
         """(name, C_in, C_out) of every 3x3 convolution in order."""
@@ -146,15 +153,15 @@ class Arch:
 
 def init_params(arch: Arch, seed: int):
     """He-normal 3x3 weights (std sqrt(2 / (9 C_in))), zero biases, head weights
-    N(0, 1/C) and zero head bias; from PCG64(seed)."""
+    N(0, 1/C) ([outputs, C]) and zero head biases; from PCG64(seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     p = {}
     for name, ci, co in arch.convs():
         p[name + ".w"] = rng.standard_normal((co, 3, 3, ci)) * np.sqrt(2.0 / (9 * ci))
         p[name + ".b"] = np.zeros(co)
     c0 = arch.widths[0]
-    p["head.w"] = rng.standard_normal(c0) / np.sqrt(c0)
-    p["head.b"] = np.zeros(1)
+    p["head.w"] = rng.standard_normal((arch.outputs, c0)) / np.sqrt(c0)
+    p["head.b"] = np.zeros(arch.outputs)
     return p
 
 
@@ -163,12 +170,13 @@ def _exact(a):
 
 
 def forward(arch: Arch, p: dict, x, store=_exact, rin=None):
-    """x: [N, H, W, in_channels]; channel 0 is the normalised input density.  Returns the
-    prediction [N, H, W] and the activations the backward pass needs.
+    """x: [N, H, W, in_channels]; channel 0 is the normalised input density, channel 2
+    the normalised temperature deviation.  Returns the prediction [N, H, W, outputs]
+    and the activations the backward pass needs.
 
     store: applied to every convolution output (identity by default; bf16_round
-    models an implementation that keeps activations in bfloat16).  rin: the density
-    the head adds (default x[..., 0])."""
+    models an implementation that keeps activations in bfloat16).  rin: the fields
+    the head adds ([N, H, W, outputs]; default the residual channels of x)."""
     cache = {"x": x}
     h = x
     skips = []
@@ -188,7 +196,7 @@ def forward(arch: Arch, p: dict, x, store=_exact, rin=None):
         bb = store(relu(conv3x3(a, p[f"d{lvl}b.w"], p[f"d{lvl}b.b"])))
         cache[f"d{lvl}_in"], cache[f"d{lvl}a"], cache[f"d{lvl}b"] = cat, a, bb
         h = bb
-    out = head(h, p["head.w"], p["head.b"][0], x[..., 0] if rin is None else rin)
+    out = head(h, p["head.w"], p["head.b"], x[..., arch.residual_channels()] if rin is None else rin)
     return out, cache
 
 
@@ -201,9 +209,10 @@ def backward(arch: Arch, p: dict, cache: dict, dout, store=_exact):
     gr = {}
     L = len(arch.widths)
     top = cache["d0b"]
-    gr["head.w"] = top.reshape(-1, top.shape[3]).T @ dout.reshape(-1)
-    gr["head.b"] = np.array([dout.sum()])
-    dh = dout[..., None] * p["head.w"]
+    K = dout.shape[3]
+    gr["head.w"] = dout.reshape(-1, K).T @ top.reshape(-1, top.shape[3])
+    gr["head.b"] = dout.reshape(-1, K).sum(axis=0)
+    dh = dout @ p["head.w"]
     dskip = {}
     # decoder levels ran L-2, ..., 0; their backward runs 0, ..., L-2
     for lvl in range(0, L - 1):
@@ -227,7 +236,8 @@ def backward(arch: Arch, p: dict, cache: dict, dout, store=_exact):
         if lvl > 0:
             dh = store(dh)
     dx = dh.copy()
-    dx[..., 0] += dout
+    for k, ch in enumerate(arch.residual_channels()):
+        dx[..., ch] += dout[..., k]
     return gr, dx
 
 

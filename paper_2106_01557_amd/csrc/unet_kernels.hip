@@ -423,21 +423,28 @@ __global__ void k_up_bwd(const bf16_t* dy, int lddy, const bf16_t* gate, int ldg
 // ---------------------------------------------------------------------------
 // input, head and loss, optimizer
 // ---------------------------------------------------------------------------
-__global__ void k_prepare(const double* rho, const double* rv, const double* rl, const double* cond, bf16_t* x,
-                          float* rin, int lhw, int total) {
+// channels: 0 normalised density, 1 condition, 2 normalised temperature deviation, 3..7 zero
+__global__ void k_prepare(const double* rho, const double* T, const double* rv, const double* rl, const double* T0,
+                          const double* cond, double theta_scale, bf16_t* x, float* rin, int lhw, int total) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int n = idx >> lhw;
     const float v = (float)((rho[idx] - rv[n]) / (rl[n] - rv[n]));
-    if (rin) rin[idx] = v;
-    if (x) st16(x + (size_t)idx * 8, make_uint4(f2bf(v) | (f2bf((float)cond[n]) << 16), 0u, 0u, 0u));
+    const float th = T ? (float)((T[idx] / T0[n] - 1.0) / theta_scale) : 0.f;
+    if (rin) {
+        rin[idx] = v;
+        rin[(size_t)total + idx] = th;
+    }
+    if (x) st16(x + (size_t)idx * 8, make_uint4(f2bf(v) | (f2bf((float)cond[n]) << 16), f2bf(th), 0u, 0u));
 }
 
-__global__ void k_output(const float* out, const double* rv, const double* rl, double* rho, int lhw, int total) {
+__global__ void k_output(const float* out, int K, const double* rv, const double* rl, const double* T0,
+                         double theta_scale, double* rho, double* T, int lhw, int total) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int n = idx >> lhw;
     rho[idx] = rv[n] + (rl[n] - rv[n]) * (double)out[idx];
+    if (T) T[idx] = T0[n] * (1.0 + theta_scale * (K > 1 ? (double)out[(size_t)total + idx] : 0.0));
 }
 
 constexpr int kHeadBlock = 256;
@@ -455,25 +462,30 @@ __device__ __forceinline__ float block_sum(float v, float* sm) {
     return r;
 }
 
+// K output planes: out[k][p] = sum_c hw[k][c] d[p][c] + hb[k] + rin[k][p]
 __global__ void __launch_bounds__(kHeadBlock) k_head_fwd(const bf16_t* d, int ldd, const float* hw, const float* hb,
                                                          const float* rin, const float* target, float* out,
-                                                         float* dout, float* part, int C, int P) {
+                                                         float* dout, float* part, int C, int K, int P) {
     __shared__ float sm[kHeadBlock];
     const int p = blockIdx.x * kHeadBlock + threadIdx.x;
     float r2 = 0.f;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
     if (p < P) {
-        float s = hb[0] + rin[p];
         for (int c = 0; c < C; c += 8) {
             float v[8];
             unpack8(ld16(d + (size_t)p * ldd + c), v);
+            for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s += hw[c + j] * v[j];
+                for (int j = 0; j < 8; ++j) acc[k] += hw[k * C + c + j] * v[j];
         }
-        out[p] = s;
-        if (target) {
-            const float r = s - target[p];
-            dout[p] = 2.f * r / (float)P;
-            r2 = r * r;
+        for (int k = 0; k < K; ++k) {
+            const float s = acc[k] + hb[k] + rin[(size_t)k * P + p];
+            out[(size_t)k * P + p] = s;
+            if (target) {
+                const float r = s - target[(size_t)k * P + p];
+                dout[(size_t)k * P + p] = 2.f * r / (float)((size_t)K * P);
+                r2 += r * r;
+            }
         }
     }
     if (target) {
@@ -482,36 +494,49 @@ __global__ void __launch_bounds__(kHeadBlock) k_head_fwd(const bf16_t* d, int ld
     }
 }
 
-// part: [blocks][C + 1]: per-block sums of dout d[., c] and of dout
+// part: [blocks][K (C + 1)]: per-block sums of dout_k d[., c] and of dout_k
 __global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ldd, const float* hw,
-                                                         const float* dout, bf16_t* g, float* part, int C, int P) {
+                                                         const float* dout, bf16_t* g, float* part, int C, int K,
+                                                         int P) {
     __shared__ float sm[kHeadBlock];
     const int p = blockIdx.x * kHeadBlock + threadIdx.x;
-    const float dp = p < P ? dout[p] : 0.f;
+    float dp[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < K; ++k) dp[k] = p < P ? dout[(size_t)k * P + p] : 0.f;
+    const size_t row = (size_t)blockIdx.x * K * (C + 1);
     for (int c = 0; c < C; c += 8) {
         float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, o[8];
         if (p < P) unpack8(ld16(d + (size_t)p * ldd + c), v);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] = v[j] > 0.f ? dp * hw[c + j] : 0.f;
-        if (p < P) st16(g + (size_t)p * C + c, pack8(o));
-#pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float b = block_sum(dp * v[j], sm);
-            if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 1) + c + j] = b;
+            float s = 0.f;
+            for (int k = 0; k < K; ++k) s += dp[k] * hw[k * C + c + j];
+            o[j] = v[j] > 0.f ? s : 0.f;
         }
+        if (p < P) st16(g + (size_t)p * C + c, pack8(o));
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float b = block_sum(dp[k] * v[j], sm);
+                if (threadIdx.x == 0) part[row + (size_t)k * (C + 1) + c + j] = b;
+            }
     }
-    const float b = block_sum(dp, sm);
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 1) + C] = b;
+    for (int k = 0; k < K; ++k) {
+        const float b = block_sum(dp[k], sm);
+        if (threadIdx.x == 0) part[row + (size_t)k * (C + 1) + C] = b;
+    }
 }
 
-// out[j] = sum over blocks of part[b][j] (j < m), in block order; scaled
-__global__ void k_sum_partials(const float* part, int blocks, int m, float scale, float* out0, float* out1) {
+// out[j] = sum over blocks of part[b][j] (j < m), in block order, times scale; with
+// stride > 0 the entries j % stride == stride - 1 go to out1[j / stride] instead
+__global__ void k_sum_partials(const float* part, int blocks, int m, float scale, float* out0, float* out1,
+                               int stride) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     double s = 0.0;
     for (int b = 0; b < blocks; ++b) s += part[(size_t)b * m + j];
     const float v = (float)(s * scale);
-    if (out1 && j == m - 1) out1[0] = v;
+    if (stride > 0 && j % stride == stride - 1) out1[j / stride] = v;
+    else if (stride > 0) out0[(j / stride) * (stride - 1) + j % stride] = v;
     else out0[j] = v;
 }
 
@@ -778,44 +803,46 @@ int unet_upsample2_bwd(const void* dy, int32_t lddy, int32_t offdy, const void* 
     return launched("upsample bwd launch");
 }
 
-int unet_prepare_input(const double* rho, const double* rho_v, const double* rho_l, const double* cond, void* x,
-                       float* rin, int32_t N, int32_t H, int32_t W, void* stream) {
+int unet_prepare_input(const double* rho, const double* T, const double* rho_v, const double* rho_l,
+                       const double* T0, const double* cond, double theta_scale, void* x, float* rin, int32_t N,
+                       int32_t H, int32_t W, void* stream) {
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
-    if (!rho || !rho_v || !rho_l || !cond || (!x && !rin) || (x && !aligned16(x)))
-        return fail(UNET_EINVAL, "prepare: bad pointers");
+    if (!rho || !rho_v || !rho_l || !T0 || !cond || (!x && !rin) || (x && !aligned16(x)) || !(theta_scale > 0))
+        return fail(UNET_EINVAL, "prepare: bad pointers or theta_scale");
     const int total = N * H * W;
-    hipLaunchKernelGGL(k_prepare, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), rho,
-                       rho_v, rho_l, cond, static_cast<bf16_t*>(x), rin, lh + lw, total);
+    hipLaunchKernelGGL(k_prepare, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), rho, T,
+                       rho_v, rho_l, T0, cond, theta_scale, static_cast<bf16_t*>(x), rin, lh + lw, total);
     return launched("prepare launch");
 }
 
-int unet_output_density(const float* out, const double* rho_v, const double* rho_l, double* rho, int32_t N, int32_t H,
-                        int32_t W, void* stream) {
+int unet_output_fields(const float* out, int32_t K, const double* rho_v, const double* rho_l, const double* T0,
+                       double theta_scale, double* rho, double* T, int32_t N, int32_t H, int32_t W, void* stream) {
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
-    if (!out || !rho_v || !rho_l || !rho) return fail(UNET_EINVAL, "output: bad pointers");
+    if (!out || !rho_v || !rho_l || !rho || K < 1 || K > 4 || (T && !T0) || !(theta_scale > 0))
+        return fail(UNET_EINVAL, "output: bad arguments");
     const int total = N * H * W;
-    hipLaunchKernelGGL(k_output, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), out, rho_v,
-                       rho_l, rho, lh + lw, total);
+    hipLaunchKernelGGL(k_output, dim3((total + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), out, K, rho_v,
+                       rho_l, T0, theta_scale, rho, T, lh + lw, total);
     return launched("output launch");
 }
 
-int unet_head_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C, size_t* bytes) {
+int unet_head_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C, int32_t K, size_t* bytes) {
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
-    if (!bytes || C < 8 || C % 8) return fail(UNET_EINVAL, "head: bad channels");
+    if (!bytes || C < 8 || C % 8 || K < 1 || K > 4) return fail(UNET_EINVAL, "head: bad channels or outputs");
     const size_t blocks = ((size_t)N * H * W + kHeadBlock - 1) / kHeadBlock;
-    *bytes = blocks * (C + 1) * sizeof(float);
+    *bytes = blocks * K * (C + 1) * sizeof(float);
     return UNET_OK;
 }
 
 int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, const float* rin, const float* target,
                   float* out, float* dout, float* loss, void* partials, size_t partial_bytes, int32_t N, int32_t H,
-                  int32_t W, int32_t C, void* stream) {
+                  int32_t W, int32_t C, int32_t K, void* stream) {
     size_t need = 0;
     int r;
-    if ((r = unet_head_partial_bytes(N, H, W, C, &need))) return r;
+    if ((r = unet_head_partial_bytes(N, H, W, C, K, &need))) return r;
     if ((r = check_tensor("d", d, ldd, 0, C, false))) return r;
     if (!hw || !hb || !rin || !out) return fail(UNET_EINVAL, "head: NULL argument");
     if (target && (!dout || !loss || !partials || partial_bytes < need))
@@ -823,31 +850,33 @@ int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, 
     const int P = N * H * W, blocks = (P + kHeadBlock - 1) / kHeadBlock;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_head_fwd, dim3(blocks), dim3(kHeadBlock), 0, s, static_cast<const bf16_t*>(d), ldd, hw, hb,
-                       rin, target, out, dout, static_cast<float*>(partials), C, P);
+                       rin, target, out, dout, static_cast<float*>(partials), C, K, P);
     if ((r = launched("head launch"))) return r;
     if (target) {
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, static_cast<const float*>(partials), blocks, 1,
-                           1.0f / (float)P, loss, (float*)nullptr);
+                           1.0f / (float)((size_t)K * P), loss, (float*)nullptr, 0);
         return launched("loss reduce launch");
     }
     return UNET_OK;
 }
 
 int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout, void* g, float* dhw, float* dhb,
-                  void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, void* stream) {
+                  void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, int32_t K,
+                  void* stream) {
     size_t need = 0;
     int r;
-    if ((r = unet_head_partial_bytes(N, H, W, C, &need))) return r;
+    if ((r = unet_head_partial_bytes(N, H, W, C, K, &need))) return r;
     if ((r = check_tensor("d", d, ldd, 0, C, false)) || (r = check_tensor("g", g, C, 0, C, false))) return r;
     if (!hw || !dout || !dhw || !dhb || !partials || partial_bytes < need)
         return fail(UNET_EINVAL, "head bwd: NULL argument or partials below %zu bytes", need);
     const int P = N * H * W, blocks = (P + kHeadBlock - 1) / kHeadBlock;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(kHeadBlock), 0, s, static_cast<const bf16_t*>(d), ldd, hw, dout,
-                       static_cast<bf16_t*>(g), static_cast<float*>(partials), C, P);
+                       static_cast<bf16_t*>(g), static_cast<float*>(partials), C, K, P);
     if ((r = launched("head bwd launch"))) return r;
-    hipLaunchKernelGGL(k_sum_partials, dim3((C + 1 + 63) / 64), dim3(64), 0, s, static_cast<const float*>(partials),
-                       blocks, C + 1, 1.0f, dhw, dhb);
+    const int m = K * (C + 1);
+    hipLaunchKernelGGL(k_sum_partials, dim3((m + 63) / 64), dim3(64), 0, s, static_cast<const float*>(partials), blocks,
+                       m, 1.0f, dhw, dhb, C + 1);
     return launched("head reduce launch");
 }
 

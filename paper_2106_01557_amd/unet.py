@@ -7,8 +7,13 @@ the optimizer runs in the library's kernels; torch provides device memory and th
 stream.  The architecture: encoder levels of widths (32, 64, 128, 256), each two
 3x3 convolutions with ReLU followed by 2x2 max pooling (none after the last, the
 bottleneck); decoder levels upsample 2x, concatenate the encoder level's output
-and apply two 3x3 convolutions with ReLU; a 1x1 head adds its output to the input
-density channel.  Convolutions wrap around (the lattice is periodic).
+and apply two 3x3 convolutions with ReLU; a 1x1 head with one output per predicted
+field (the density and, by default, the temperature) adds its outputs to the
+corresponding input fields.  Convolutions wrap around (the lattice is periodic).
+
+Normalisation: density nu = (rho - rho_v) / (rho_l - rho_v) with the coexistence
+densities at the run's T0; temperature theta = (T / T0 - 1) / theta_scale; a
+conditioning channel carries the run's reduced temperature.
 """
 from __future__ import annotations
 
@@ -23,7 +28,7 @@ _P, _I, _F, _V, _S = ctypes.POINTER, ctypes.c_int32, ctypes.c_float, ctypes.c_vo
 
 EXPORTED = ["unet_conv3x3_fwd", "unet_flip_weights", "unet_wgrad_partial_bytes", "unet_conv3x3_wgrad",
             "unet_maxpool2_fwd", "unet_maxpool2_bwd", "unet_upsample2_fwd", "unet_upsample2_bwd",
-            "unet_prepare_input", "unet_output_density", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd", "unet_adam",
+            "unet_prepare_input", "unet_output_fields", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd", "unet_adam",
             "unet_to_bf16", "unet_to_f32", "unet_last_error"]
 
 RELU, OUT_F32 = 1, 2
@@ -36,11 +41,12 @@ _lib.unet_maxpool2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_maxpool2_bwd.argtypes = [_V, _I, _I, _V, _I, _I, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_upsample2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_upsample2_bwd.argtypes = [_V, _I, _I, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
-_lib.unet_prepare_input.argtypes = [_V, _V, _V, _V, _V, _V, _I, _I, _I, _V]
-_lib.unet_output_density.argtypes = [_V, _V, _V, _V, _I, _I, _I, _V]
-_lib.unet_head_partial_bytes.argtypes = [_I, _I, _I, _I, _P(_S)]
-_lib.unet_head_fwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _V]
-_lib.unet_head_bwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _V]
+_D = ctypes.c_double
+_lib.unet_prepare_input.argtypes = [_V, _V, _V, _V, _V, _V, _D, _V, _V, _I, _I, _I, _V]
+_lib.unet_output_fields.argtypes = [_V, _I, _V, _V, _V, _D, _V, _V, _I, _I, _I, _V]
+_lib.unet_head_partial_bytes.argtypes = [_I, _I, _I, _I, _I, _P(_S)]
+_lib.unet_head_fwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
+_lib.unet_head_bwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
 _lib.unet_adam.argtypes = [_V, _V, _V, _V, _V, _S, _F, _F, _F, _F, _I, _V]
 _lib.unet_to_bf16.argtypes = [_V, _V, _S, _V]
 _lib.unet_to_f32.argtypes = [_V, _V, _S, _V]
@@ -87,11 +93,14 @@ class UNet:
     """Parameters (FP32 masters, bfloat16 copies and flipped copies for the input
     gradient) and per-batch-shape activation buffers on one device."""
 
-    def __init__(self, widths=(32, 64, 128, 256), in_channels=8, seed=0, device=None, stream=None):
+    def __init__(self, widths=(32, 64, 128, 256), in_channels=8, outputs=2, theta_scale=0.1, seed=0, device=None,
+                 stream=None):
         import torch
         self.torch = torch
         self.widths = tuple(int(w) for w in widths)
         self.in_channels = int(in_channels)
+        self.K = int(outputs)
+        self.theta_scale = float(theta_scale)
         self.layers = conv_layers(self.widths, self.in_channels)
         self.device = torch.device(device if device is not None else "cuda")
         if self.device.index is None:
@@ -105,8 +114,8 @@ class UNet:
             p[name + ".w"] = rng.standard_normal((co, 3, 3, ci)) * np.sqrt(2.0 / (9 * ci))
             p[name + ".b"] = np.zeros(co)
         c0 = self.widths[0]
-        p["head.w"] = rng.standard_normal(c0) / np.sqrt(c0)
-        p["head.b"] = np.zeros(1)
+        p["head.w"] = rng.standard_normal((self.K, c0)) / np.sqrt(c0)
+        p["head.b"] = np.zeros(self.K)
         self.load_params(p)
         self._shape = None
 
@@ -143,6 +152,8 @@ class UNet:
                 name = k[:-2]
                 ci, co = next((c, o) for n, c, o in self.layers if n == name)
                 a = a.reshape(co, 3, 3, ci)
+            elif k == "head.w":
+                a = a.reshape(self.K, -1)
             out[k] = a
         return out
 
@@ -158,8 +169,9 @@ class UNet:
         f32 = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
         b = {}
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
-            b["x0"], b["rin"], b["target"] = bf(N, H, W, self.in_channels), f32(N, H, W), f32(N, H, W)
-            b["out"], b["dout"] = f32(N, H, W), f32(N, H, W)
+            # rin and target hold both normalised fields ([2][N,H,W]); the head uses the first K
+            b["x0"], b["rin"], b["target"] = bf(N, H, W, self.in_channels), f32(2, N, H, W), f32(2, N, H, W)
+            b["out"], b["dout"] = f32(self.K, N, H, W), f32(self.K, N, H, W)
             for lvl, c in enumerate(self.widths):
                 h, w = H >> lvl, W >> lvl
                 b[f"e{lvl}a"] = bf(N, h, w, c)
@@ -182,7 +194,7 @@ class UNet:
                 _ck(_lib.unet_wgrad_partial_bytes(N, H >> lvl, W >> lvl, ci, co, ctypes.byref(nb)))
                 need = max(need, nb.value)
             nb = _S()
-            _ck(_lib.unet_head_partial_bytes(N, H, W, self.widths[0], ctypes.byref(nb)))
+            _ck(_lib.unet_head_partial_bytes(N, H, W, self.widths[0], self.K, ctypes.byref(nb)))
             b["wpart"] = torch.empty(need, dtype=torch.uint8, device=self.device)
             b["hpart"] = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
             b["loss"] = f32(1)
@@ -196,22 +208,24 @@ class UNet:
         _ck(_lib.unet_conv3x3_fwd(ptr(x), ldx, offx, ptr(self.w16[name]), ptr(self.p[name + ".b"]), ptr(y), ldy,
                                   offy, ptr(mask), ldm, offm, N, h, w, ci, co, flags, self.s))
 
-    def forward(self, rho, rho_v, rho_l, cond, target=None):
-        """rho: FP64 [N, H, W] device densities; rho_v, rho_l, cond: FP64 [N] device
-        tensors (normalisation and the conditioning channel); target: FP64 [N, H, W]
-        device densities or None.  Returns the normalised prediction (FP32 [N, H, W],
-        a view into the model's buffer) and, with a target, the loss tensor."""
+    def forward(self, rho, T, rho_v, rho_l, T0, cond, target_rho=None, target_T=None):
+        """rho, T: FP64 [N, H, W] device fields (T may be None: T = T0); rho_v, rho_l, T0,
+        cond: FP64 [N] device tensors (normalisation and the conditioning channel);
+        target_rho, target_T: FP64 [N, H, W] device fields or None.  Returns the
+        normalised prediction (FP32 [K, N, H, W], a view into the model's buffer) and,
+        with a target, the loss tensor."""
         torch = self.torch
         N, H, W = rho.shape
         self._alloc(N, H, W)
         b, L, wd = self.buf, len(self.widths), self.widths
+        ts = self.theta_scale
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
-            _ck(_lib.unet_prepare_input(ptr(rho), ptr(rho_v), ptr(rho_l), ptr(cond), ptr(b["x0"]), ptr(b["rin"]),
-                                        N, H, W, self.s))
-            if target is not None:
-                # the target goes through the same normalisation
-                _ck(_lib.unet_prepare_input(ptr(target), ptr(rho_v), ptr(rho_l), ptr(cond), None, ptr(b["target"]),
-                                            N, H, W, self.s))
+            _ck(_lib.unet_prepare_input(ptr(rho), ptr(T), ptr(rho_v), ptr(rho_l), ptr(T0), ptr(cond), ts, ptr(b["x0"]),
+                                        ptr(b["rin"]), N, H, W, self.s))
+            if target_rho is not None:
+                # the targets go through the same normalisation
+                _ck(_lib.unet_prepare_input(ptr(target_rho), ptr(target_T), ptr(rho_v), ptr(rho_l), ptr(T0), ptr(cond),
+                                            ts, None, ptr(b["target"]), N, H, W, self.s))
             x, ldx, offx = b["x0"], self.in_channels, 0
             for lvl in range(L):
                 h, w, c = H >> lvl, W >> lvl, wd[lvl]
@@ -232,11 +246,11 @@ class UNet:
                 self._conv(f"d{lvl}a", cat, cu + c, 0, b[f"d{lvl}a"], c, 0, N, h, w)
                 self._conv(f"d{lvl}b", b[f"d{lvl}a"], c, 0, b[f"d{lvl}b"], c, 0, N, h, w)
                 low, ldl = b[f"d{lvl}b"], c
-            tgt = b["target"] if target is not None else None
+            tgt = b["target"] if target_rho is not None else None
             _ck(_lib.unet_head_fwd(ptr(low), wd[0], ptr(self.p["head.w"]), ptr(self.p["head.b"]), ptr(b["rin"]),
                                    ptr(tgt), ptr(b["out"]), ptr(b["dout"]), ptr(b["loss"]), ptr(b["hpart"]),
-                                   b["hpart"].numel(), N, H, W, wd[0], self.s))
-        return (b["out"], b["loss"]) if target is not None else b["out"]
+                                   b["hpart"].numel(), N, H, W, wd[0], self.K, self.s))
+        return (b["out"], b["loss"]) if target_rho is not None else b["out"]
 
     def backward(self):
         """Gradients (FP32, in self.g) of the loss of the last forward call with a target."""
@@ -260,7 +274,7 @@ class UNet:
             top = b["d0b"]
             _ck(_lib.unet_head_bwd(ptr(top), wd[0], ptr(self.p["head.w"]), ptr(b["dout"]), ptr(b["gd0b"]),
                                    ptr(g["head.w"]), ptr(g["head.b"]), ptr(b["hpart"]), b["hpart"].numel(), N, H, W,
-                                   wd[0], self.s))
+                                   wd[0], self.K, self.s))
             # decoder, top level first
             for lvl in range(L - 1):
                 h, w, c, cu = H >> lvl, W >> lvl, wd[lvl], wd[lvl + 1]
@@ -306,19 +320,21 @@ class UNet:
             for name, ci, co in self.layers:
                 _ck(_lib.unet_flip_weights(ptr(self.w16[name]), ptr(self.wf16[name]), co, ci, self.s))
 
-    def train_step(self, rho0, target, rho_v, rho_l, cond, lr=1e-3):
-        _, loss = self.forward(rho0, rho_v, rho_l, cond, target)
+    def train_step(self, rho0, T0f, rhoT, TT, rho_v, rho_l, T0, cond, lr=1e-3):
+        _, loss = self.forward(rho0, T0f, rho_v, rho_l, T0, cond, rhoT, TT)
         self.backward()
         self.adam_step(lr)
         return loss
 
-    def predict_density(self, rho0, rho_v, rho_l, cond):
-        """Predicted density (FP64 [N, H, W] device tensor): the normalised output mapped
-        back with each sample's (rho_v, rho_l)."""
+    def predict_fields(self, rho0, T0f, rho_v, rho_l, T0, cond):
+        """Predicted density and temperature (FP64 [N, H, W] device tensors; T = T0 when
+        the network has one output)."""
         torch = self.torch
-        out = self.forward(rho0, rho_v, rho_l, cond)
+        out = self.forward(rho0, T0f, rho_v, rho_l, T0, cond)
         N, H, W = rho0.shape
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
-            res = torch.empty((N, H, W), dtype=torch.float64, device=self.device)
-            _ck(_lib.unet_output_density(ptr(out), ptr(rho_v), ptr(rho_l), ptr(res), N, H, W, self.s))
-        return res
+            rho = torch.empty((N, H, W), dtype=torch.float64, device=self.device)
+            T = torch.empty_like(rho)
+            _ck(_lib.unet_output_fields(ptr(out), self.K, ptr(rho_v), ptr(rho_l), ptr(T0), self.theta_scale, ptr(rho),
+                                        ptr(T), N, H, W, self.s))
+        return rho, T

@@ -1,0 +1,289 @@
+"""Learned warm start for the liquid-vapour lattice update.
+
+The solver generates its own training data: seeded periodic fields with several
+droplets are advanced `horizon` steps by the batched two-buffer update; a U-Net
+(unet.py) learns the map from the initial density and temperature fields (and the
+run's reduced temperature) to the density and temperature fields at the horizon;
+the solver then starts from the network's prediction (fluid at rest) and finishes
+the relaxation, so the lattice model, not the network, decides the final state.
+The temperature is part of the prediction because latent heat moves it by up to
+about ten percent near interfaces, and the coexistence densities follow it.
+
+Time to coexistence of a run: the first sample after which both bulk densities
+(liquid: mean density over nodes whose normalised density exceeds 0.9; vapour:
+over nodes below 0.1) stay within a relative 1e-3 of the run's final values.  The
+warm-started run's final bulk densities are also compared with the plain run's
+(the accuracy of the state the warm start settles in).
+
+All arithmetic of the lattice update, the network and the optimizer runs in the
+library's kernels; torch provides memory, the stream and the bookkeeping
+reductions of the diagnostics.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import inputs, lbm, unet
+
+
+@dataclass
+class Spec:
+    """One problem: droplet centres and radii on a side x side periodic lattice at T/Tc = tr."""
+    side: int
+    tr: float
+    centres: list
+    radii: list
+    seed: int
+
+
+def sample_specs(n: int, seed: int, side: int = 256, drops=(1, 8), radii=(8.0, 48.0), tr=(0.65, 0.9)) -> list:
+    """n problems from PCG64(seed): droplet count uniform in drops, radii uniform in
+    radii, centres uniform on the lattice, T/Tc uniform in tr."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        m = int(rng.integers(drops[0], drops[1] + 1))
+        cs = [(float(rng.uniform(0, side)), float(rng.uniform(0, side))) for _ in range(m)]
+        rs = [float(rng.uniform(*radii)) for _ in range(m)]
+        out.append(Spec(side, float(rng.uniform(*tr)), cs, rs, seed * 100003 + k))
+    return out
+
+
+def _cond(tr: float) -> float:
+    return (tr - 0.775) / 0.125
+
+
+class Runner:
+    """Advances many problems together with the batched update (one precision, one stream)."""
+
+    def __init__(self, specs, precision="f32", stream=None, width=4.0, eps=0.005):
+        import torch
+        self.torch = torch
+        self.specs = list(specs)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.solvers, self.consts = [], []
+        for s in self.specs:
+            sol = lbm.Solver(s.side, s.side, params={"Tr0": s.tr, "precision": precision}, stream=self.stream)
+            self.solvers.append(sol)
+            self.consts.append(sol.derived())
+        self.width, self.eps = width, eps
+        self.batch = lbm.Batch(self.solvers)
+        self.batch.set_shape(rows_per_wave=32, waves_per_block=4, queue=False)
+        d = lambda key: torch.tensor([c[key] for c in self.consts], dtype=torch.float64, device="cuda")  # noqa: E731
+        self.rho_v, self.rho_l, self.T0 = d("rho_v"), d("rho_l"), d("T0")
+        self.cond = torch.tensor([_cond(s.tr) for s in self.specs], dtype=torch.float64, device="cuda")
+
+    def initial_density(self):
+        """The seeded initial fields [n, side, side] (host FP64, then device)."""
+        out = []
+        for s, c in zip(self.specs, self.consts):
+            f = inputs.droplets(s.side, s.side, c["rho_l"], c["rho_v"], c["T0"], s.centres, s.radii, self.width,
+                                eps=self.eps, seed=s.seed)
+            out.append(f.rho)
+        return self.torch.as_tensor(np.stack(out), dtype=self.torch.float64).cuda()
+
+    def uniform_T(self):
+        return self.T0[:, None, None].expand(-1, self.specs[0].side, self.specs[0].side).contiguous()
+
+    def set_fields(self, rho, T=None):
+        """Start every problem from density (and temperature) fields [n, side, side]
+        (device), fluid at rest; T = None: T0 everywhere."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            for k, (s, c) in enumerate(zip(self.solvers, self.consts)):
+                z = torch.zeros_like(rho[k])
+                t = torch.full_like(rho[k], c["T0"]) if T is None else T[k].contiguous()
+                s.set_fields(rho[k].contiguous(), z, z, t)
+        self.stream.synchronize()
+
+    def step(self, n: int):
+        self.batch.step(n)
+
+    def density(self):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            out = torch.stack([s.moments(("rho",))["rho"] for s in self.solvers])
+        self.stream.synchronize()
+        return out
+
+    def fields(self):
+        """Density and temperature [n, side, side] (device FP64)."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            m = [s.moments(("rho", "T")) for s in self.solvers]
+            rho, T = torch.stack([x["rho"] for x in m]), torch.stack([x["T"] for x in m])
+        self.stream.synchronize()
+        return rho, T
+
+    def bulk(self, rho=None):
+        """(liquid, vapour) bulk densities per problem ([n] FP64 host arrays; NaN where a
+        phase has no bulk nodes)."""
+        torch = self.torch
+        rho = self.density() if rho is None else rho
+        with torch.cuda.stream(self.stream):
+            nu = (rho - self.rho_v[:, None, None]) / (self.rho_l - self.rho_v)[:, None, None]
+            liq, vap = (nu > 0.9).double(), (nu < 0.1).double()
+            lsum, lcnt = (rho * liq).sum(dim=(1, 2)), liq.sum(dim=(1, 2))
+            vsum, vcnt = (rho * vap).sum(dim=(1, 2)), vap.sum(dim=(1, 2))
+            res = torch.stack([lsum / lcnt, vsum / vcnt]).cpu().numpy()
+        return res[0], res[1]
+
+    def close(self):
+        self.batch.close()
+        for s in self.solvers:
+            s.close()
+
+
+KEYS = ("rho0", "T0f", "rhoT", "TT", "rho_v", "rho_l", "T0", "cond")
+
+
+def generate(specs, horizon: int, chunk: int = 64, precision: str = "f32", log=None):
+    """Runs every problem `horizon` steps from its seeded initial field (at rest, T0).
+    Returns device tensors rho0, T0f, rhoT, TT [n, side, side] (FP64) and rho_v, rho_l,
+    T0, cond [n]."""
+    import torch
+    parts = {k: [] for k in KEYS}
+    for i in range(0, len(specs), chunk):
+        r = Runner(specs[i:i + chunk], precision=precision)
+        rho0 = r.initial_density()
+        r.set_fields(rho0)
+        r.step(horizon)
+        rhoT, TT = r.fields()
+        parts["rho0"].append(rho0)
+        parts["T0f"].append(r.uniform_T())
+        parts["rhoT"].append(rhoT)
+        parts["TT"].append(TT)
+        parts["rho_v"].append(r.rho_v)
+        parts["rho_l"].append(r.rho_l)
+        parts["T0"].append(r.T0)
+        parts["cond"].append(r.cond)
+        r.close()
+        if log:
+            log(f"generated {min(i + chunk, len(specs))}/{len(specs)} runs")
+    return {k: torch.cat(v) for k, v in parts.items()}
+
+
+def identity_loss(ds, theta_scale: float = 0.1, outputs: int = 2) -> float:
+    """Mean squared error (normalised fields, as the network's loss) of predicting no
+    change: the no-net baseline."""
+    nu = lambda r: (r - ds["rho_v"][:, None, None]) / (ds["rho_l"] - ds["rho_v"])[:, None, None]  # noqa: E731
+    th = lambda t: (t / ds["T0"][:, None, None] - 1) / theta_scale  # noqa: E731
+    e = [((nu(ds["rhoT"]) - nu(ds["rho0"])) ** 2).mean()]
+    if outputs > 1:
+        e.append(((th(ds["TT"]) - th(ds["T0f"])) ** 2).mean())
+    return float(sum(e) / len(e))
+
+
+def train(net: "unet.UNet", ds, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 0, log=None,
+          lr_final: float | None = None):
+    """Adam on the mean squared error of the normalised density; minibatches drawn
+    without replacement each epoch from PCG64(seed); cosine decay of the rate to
+    lr_final (default lr / 10).  Returns the per-epoch mean losses."""
+    import torch
+    n = ds["rho0"].shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    steps = epochs * (n // batch)
+    lr_final = lr / 10 if lr_final is None else lr_final
+    hist, k = [], 0
+    for ep in range(epochs):
+        order = torch.as_tensor(rng.permutation(n), device="cuda")
+        losses = []
+        for j in range(n // batch):
+            idx = order[j * batch:(j + 1) * batch]
+            with torch.cuda.stream(net.stream):
+                args = [ds[key].index_select(0, idx).contiguous() for key in KEYS]
+            rate = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * k / max(steps - 1, 1)))
+            loss = net.train_step(*args, lr=rate)
+            losses.append(loss.clone())
+            k += 1
+        mean = float(torch.stack(losses).mean().cpu())
+        hist.append(mean)
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: loss {mean:.3e}")
+    return hist
+
+
+def evaluate_loss(net, ds, batch: int = 16) -> float:
+    """Mean squared error of the network on a dataset (no parameter update)."""
+    import torch
+    n = ds["rho0"].shape[0]
+    tot = 0.0
+    for j in range(0, n - batch + 1, batch):
+        sl = slice(j, j + batch)
+        _, loss = net.forward(ds["rho0"][sl], ds["T0f"][sl], ds["rho_v"][sl], ds["rho_l"][sl], ds["T0"][sl],
+                              ds["cond"][sl], ds["rhoT"][sl], ds["TT"][sl])
+        tot += float(loss.cpu()) * batch
+    return tot / (n // batch * batch)
+
+
+def coexistence_times(runner: Runner, start_rho, steps: int, every: int, final=None, start_T=None):
+    """Runs from (start_rho, start_T) and records the bulk densities every `every` steps.
+    final: (liquid, vapour) reference values (default: this run's last sample).
+    Returns the per-problem step counts to coexistence (None where never reached),
+    the last bulk values and the elapsed seconds of the stepping."""
+    runner.set_fields(start_rho, start_T)
+    hist, t_step = [], 0.0
+    done = 0
+    while done < steps:
+        n = min(every, steps - done)
+        t0 = time.perf_counter()
+        runner.step(n)
+        runner.stream.synchronize()
+        t_step += time.perf_counter() - t0
+        done += n
+        hist.append((done, *runner.bulk()))
+    last = (hist[-1][1], hist[-1][2])
+    ref = last if final is None else final
+    times = []
+    for i in range(len(runner.specs)):
+        t_hit = None
+        for k in range(len(hist)):
+            ok = all(abs(h[1][i] - ref[0][i]) <= 1e-3 * abs(ref[0][i]) and
+                     abs(h[2][i] - ref[1][i]) <= 1e-3 * abs(ref[1][i]) for h in hist[k:])
+            if ok:
+                t_hit = hist[k][0]
+                break
+        times.append(t_hit)
+    return times, last, t_step
+
+
+def compare_warm_start(net, specs, horizon: int, steps: int, every: int, log=None):
+    """Plain runs against warm-started runs on the same problems.  Returns a summary
+    dict with the per-problem times to coexistence."""
+    import torch
+    r = Runner(specs)
+    rho0 = r.initial_density()
+    plain, final, t_plain = coexistence_times(r, rho0, steps, every)
+    if log:
+        log("plain runs done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prho, pT = net.predict_fields(rho0, r.uniform_T(), r.rho_v, r.rho_l, r.T0, r.cond)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    warm, wlast, t_warm = coexistence_times(r, prho.contiguous(), steps, every, start_T=pT.contiguous())
+    r.close()
+    ok = [i for i in range(len(specs)) if plain[i] is not None and warm[i] is not None
+          and all(np.isfinite(v[i]) for v in (final[0], final[1], wlast[0], wlast[1]))]
+    p = np.array([plain[i] for i in ok], dtype=float)
+    w = np.array([warm[i] for i in ok], dtype=float)
+    dev = [max(abs(wlast[0][i] - final[0][i]) / final[0][i], abs(wlast[1][i] - final[1][i]) / final[1][i])
+           for i in ok]
+    return {
+        "problems": len(specs), "compared": len(ok),
+        "plain_steps_median": float(np.median(p)) if len(p) else None,
+        "warm_steps_median": float(np.median(w)) if len(w) else None,
+        "plain_steps_mean": float(p.mean()) if len(p) else None,
+        "warm_steps_mean": float(w.mean()) if len(w) else None,
+        "faster_fraction": float((w < p).mean()) if len(p) else None,
+        "speedup_of_means": float(p.mean() / w.mean()) if len(w) and w.mean() > 0 else None,
+        "inference_seconds": t_inf, "plain_step_seconds": t_plain, "warm_step_seconds": t_warm,
+        "warm_final_max_rel_dev": float(max(dev)) if dev else None,
+        "per_problem": [{"plain": plain[i], "warm": warm[i], "rho_l": float(final[0][i]), "rho_v": float(final[1][i]),
+                         "warm_rho_l": float(wlast[0][i]), "warm_rho_v": float(wlast[1][i])}
+                        for i in range(len(specs))],
+    }

@@ -202,40 +202,42 @@ def test_pool_upsample_and_their_gradients():
 def test_head_loss_adam_and_conversions():
     import ctypes
     import torch
-    say("case: head forward/backward, loss, Adam, bf16 conversions")
+    say("case: head forward/backward (two outputs), loss, Adam, bf16 conversions")
     u = lib()
     L = u.library()
-    N, H, W, C = 2, 16, 16, 32
+    N, H, W, C, K = 2, 16, 16, 32, 2
     d = np.maximum(bf((N, H, W, C), 18), 0)
-    hw, hb = bf(C, 19), np.array([0.125])
-    rin, tgt = bf((N, H, W), 20), bf((N, H, W), 21)
-    out_ref = U.head(d, hw, hb[0], rin)
+    hw, hb = bf((K, C), 19), np.array([0.125, -0.25])
+    rin, tgt = bf((N, H, W, K), 20), bf((N, H, W, K), 21)
+    planes = lambda a: np.ascontiguousarray(np.moveaxis(a, 3, 0))  # noqa: E731  [N,H,W,K] -> [K][N,H,W]
+    out_ref = U.head(d, hw, hb, rin)
     loss_ref, dout_ref = U.mse(out_ref, tgt)
     nb = ctypes.c_size_t()
-    ck(L.unet_head_partial_bytes(N, H, W, C, ctypes.byref(nb)))
+    ck(L.unet_head_partial_bytes(N, H, W, C, K, ctypes.byref(nb)))
     part = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
     dd, hwd, hbd = dev_bf16(d), dev_f32(hw), dev_f32(hb)
-    out = torch.empty((N, H, W), dtype=torch.float32, device="cuda")
+    out = torch.empty((K, N, H, W), dtype=torch.float32, device="cuda")
     dout = torch.empty_like(out)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    rind, tgtd = dev_f32(rin), dev_f32(tgt)
+    rind, tgtd = dev_f32(planes(rin)), dev_f32(planes(tgt))
     ck(L.unet_head_fwd(u.ptr(dd), C, u.ptr(hwd), u.ptr(hbd), u.ptr(rind), u.ptr(tgtd), u.ptr(out), u.ptr(dout),
-                       u.ptr(loss), u.ptr(part), nb.value, N, H, W, C, None))
-    bound = gamma(C + 2) * (np.abs(d) @ np.abs(hw) + abs(hb[0]) + np.abs(rin))
-    assert (np.abs(host(out) - out_ref) <= bound).all()
+                       u.ptr(loss), u.ptr(part), nb.value, N, H, W, C, K, None))
+    bound = gamma(C + 2) * (np.abs(d) @ np.abs(hw).T + np.abs(hb) + np.abs(rin))
+    assert (np.abs(planes(out_ref) - host(out)) <= planes(bound)).all()
     assert host(loss)[0] == pytest.approx(loss_ref, rel=1e-5)
-    assert np.allclose(host(dout), dout_ref, rtol=1e-5, atol=1e-9)
+    assert np.allclose(host(dout), planes(dout_ref), rtol=1e-5, atol=1e-9)
     g = torch.empty((N, H, W, C), dtype=torch.bfloat16, device="cuda")
-    dhw = torch.empty(C, dtype=torch.float32, device="cuda")
-    dhb = torch.empty(1, dtype=torch.float32, device="cuda")
+    dhw = torch.empty(K * C, dtype=torch.float32, device="cuda")
+    dhb = torch.empty(K, dtype=torch.float32, device="cuda")
     doutd = dev_f32(host(dout))
     ck(L.unet_head_bwd(u.ptr(dd), C, u.ptr(hwd), u.ptr(doutd), u.ptr(g), u.ptr(dhw), u.ptr(dhb), u.ptr(part),
-                       nb.value, N, H, W, C, None))
-    dh = host(doutd)
-    assert np.allclose(host(dhw), d.reshape(-1, C).T @ dh.reshape(-1), rtol=1e-4, atol=1e-7)
-    assert host(dhb)[0] == pytest.approx(dh.sum(), rel=1e-4, abs=1e-7)
-    want = U.bf16_round(dh[..., None] * hw * (d > 0))
-    assert (np.abs(host(g) - want) <= np.abs(want) * 2.0 ** -7 + 1e-30).all()
+                       nb.value, N, H, W, C, K, None))
+    dh = np.moveaxis(host(doutd), 0, 3)  # [N,H,W,K]
+    assert np.allclose(host(dhw).reshape(K, C), dh.reshape(-1, K).T @ d.reshape(-1, C), rtol=1e-4, atol=1e-7)
+    assert np.allclose(host(dhb), dh.reshape(-1, K).sum(axis=0), rtol=1e-4, atol=1e-7)
+    want = U.bf16_round((dh @ hw) * (d > 0))
+    acc = gamma(K) * (np.abs(dh) @ np.abs(hw))
+    assert (np.abs(host(g) - want) <= np.abs(want) * 2.0 ** -7 + 2 * acc + 1e-30).all()
     # Adam: three steps against the reference
     rng = np.random.Generator(np.random.PCG64(22))
     p0, gs = rng.standard_normal(1000), [rng.standard_normal(1000) for _ in range(3)]
@@ -266,11 +268,14 @@ def _cos(a, b):
     return float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
 
 
+TS = 0.1  # temperature normalisation of the network (theta = (T / T0 - 1) / TS)
+
+
 def _net_case(widths, hw):
     import torch
     from paper_2106_01557_amd import unet
     net = unet.UNet(widths=widths, seed=1)
-    arch = U.Arch(widths=widths, in_channels=8, used_inputs=2)
+    arch = U.Arch(widths=widths, in_channels=8, used_inputs=3, outputs=2)
     p = U.init_params(arch, seed=2)
     p = {k: U.bf16_round(v) for k, v in p.items()}
     for k in p:
@@ -282,16 +287,24 @@ def _net_case(widths, hw):
     yy, xx = np.meshgrid(np.arange(hw), np.arange(hw), indexing="ij")
     rho = np.stack([0.3 + 0.2 * np.sin(2 * np.pi * (xx + 3 * n) / hw) * np.cos(2 * np.pi * yy / hw) for n in range(N)])
     rho += 0.01 * rng.standard_normal(rho.shape)
+    T0 = np.array([0.07, 0.08])
+    Tf = T0[:, None, None] * (1 + 0.02 * np.cos(2 * np.pi * (yy + xx) / hw) + 0.002 * rng.standard_normal(rho.shape))
     tgt = rho + 0.05 * rng.standard_normal(rho.shape)
+    tgtT = Tf * (1 + 0.01 * rng.standard_normal(rho.shape))
     rv, rl, cond = np.array([0.02, 0.03]), np.array([0.31, 0.29]), np.array([0.05, -0.1])
-    T = lambda a: torch.as_tensor(a, dtype=torch.float64).cuda()
-    out, loss = net.forward(T(rho), T(rv), T(rl), T(cond), T(tgt))
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64).cuda()  # noqa: E731
+    args = [T(a) for a in (rho, Tf, rv, rl, T0, cond, tgt, tgtT)]
+    out, loss = net.forward(*args)
     grads = net.backward()
+    nu = lambda r: (r - rv[:, None, None]) / (rl - rv)[:, None, None]  # noqa: E731
+    th = lambda t: (t / T0[:, None, None] - 1) / TS  # noqa: E731
     x = np.zeros((N, hw, hw, 8))
-    x[..., 0] = U.bf16_round((rho - rv[:, None, None]) / (rl - rv)[:, None, None])
+    x[..., 0] = U.bf16_round(nu(rho))
     x[..., 1] = U.bf16_round(np.broadcast_to(cond[:, None, None], (N, hw, hw)))
-    rin = ((rho - rv[:, None, None]) / (rl - rv)[:, None, None]).astype(np.float32).astype(np.float64)
-    tn = ((tgt - rv[:, None, None]) / (rl - rv)[:, None, None]).astype(np.float32).astype(np.float64)
+    x[..., 2] = U.bf16_round(th(Tf))
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)  # noqa: E731
+    rin = np.stack([f32(nu(rho)), f32(th(Tf))], axis=3)
+    tn = np.stack([f32(nu(tgt)), f32(th(tgtT))], axis=3)
     return net, arch, p, x, rin, tn, out, loss, grads
 
 
@@ -361,16 +374,20 @@ def test_unet_every_layer_teacher_forced(widths, hw):
         conv_check(f"d{lvl}a", cat, p[f"d{lvl}a.w"], p[f"d{lvl}a.b"], b[f"d{lvl}a"])
         conv_check(f"d{lvl}b", b[f"d{lvl}a"], p[f"d{lvl}b.w"], p[f"d{lvl}b.b"], b[f"d{lvl}b"])
         low = b[f"d{lvl}b"]
-    want = U.head(low, p["head.w"], p["head.b"][0], rin)
-    bound = gamma(wd[0] + 2) * (ab(low) @ ab(p["head.w"]) + abs(p["head.b"][0]) + ab(rin))
-    assert (np.abs(b["out"] - want) <= bound + 1e-38).all()
-    assert host(loss)[0] == pytest.approx(np.mean((b["out"] - tn) ** 2), rel=1e-5)
+    gout = np.moveaxis(b["out"], 0, 3)
+    assert np.array_equal(np.moveaxis(b["rin"], 0, 3), rin)
+    assert np.array_equal(np.moveaxis(b["target"], 0, 3), tn)
+    want = U.head(low, p["head.w"], p["head.b"], rin)
+    bound = gamma(wd[0] + 2) * (ab(low) @ ab(p["head.w"]).T + ab(p["head.b"]) + ab(rin))
+    assert (np.abs(gout - want) <= bound + 1e-38).all()
+    assert host(loss)[0] == pytest.approx(np.mean((gout - tn) ** 2), rel=1e-5)
     # backward
-    dout = b["dout"]
-    assert np.allclose(dout, 2 * (b["out"] - tn) / dout.size, rtol=1e-5, atol=1e-12)
-    want = U.relu_grad(dout[..., None] * p["head.w"], b["d0b"])
-    _within_bf16(b["gd0b"], want, gamma(2) * ab(want), "head gradient")
-    assert np.allclose(host(grads["head.w"]), b["d0b"].reshape(-1, wd[0]).T @ dout.reshape(-1), rtol=1e-4, atol=1e-9)
+    dout = np.moveaxis(b["dout"], 0, 3)
+    assert np.allclose(dout, 2 * (gout - tn) / dout.size, rtol=1e-5, atol=1e-12)
+    want = U.relu_grad(dout @ p["head.w"], b["d0b"])
+    _within_bf16(b["gd0b"], want, gamma(2) * (ab(dout) @ ab(p["head.w"])), "head gradient")
+    assert np.allclose(host(grads["head.w"]).reshape(2, -1), dout.reshape(-1, 2).T @ b["d0b"].reshape(-1, wd[0]),
+                       rtol=1e-4, atol=1e-9)
     for lvl in range(L - 1):
         cu, c = wd[lvl + 1], wd[lvl]
         wgrad_check(f"d{lvl}b", b[f"d{lvl}a"], b[f"gd{lvl}b"])
@@ -408,7 +425,7 @@ def test_unet_end_to_end_against_reference(widths, hw, bars):
     out_bar, grad_bar, cos_bar = bars
     say(f"case: U-Net widths {widths} on {hw}x{hw}, end to end")
     net, arch, p, x, rin, tn, out, loss, grads = _net_case(widths, hw)
-    o = host(out)
+    o = np.moveaxis(host(out), 0, 3)
     got = {k: host(gv) for k, gv in grads.items()}
     gl = host(loss)[0]
     ro, cache = U.forward(arch, p, x, rin=rin)

@@ -1,0 +1,59 @@
+"""Learned warm start on the GPU: the solver generates training pairs, the U-Net
+(library kernels) learns them, and the trained network must beat the no-net
+baseline (predicting no change) on held-out problems; the warm-started solver must
+reach the same coexistence state as the plain one."""
+import numpy as np
+import pytest
+
+from tests.parity_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_specs(n, seed):
+    from paper_2106_01557_amd import warmstart as ws
+    return ws.sample_specs(n, seed, side=64, drops=(1, 3), radii=(6.0, 14.0), tr=(0.7, 0.9))
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """A small network trained on 96 problems (64 x 64, 400-step horizon)."""
+    import torch
+    from paper_2106_01557_amd import unet, warmstart as ws
+    say("case: warm start, 64x64 problems, 400-step horizon, train 96 / test 32")
+    train = ws.generate(_small_specs(96, seed=11), horizon=400)
+    test = ws.generate(_small_specs(32, seed=12), horizon=400)
+    net = unet.UNet(widths=(16, 32, 64), seed=0, stream=torch.cuda.current_stream())
+    base = ws.identity_loss(test)
+    for key in ("rho0", "T0f", "rhoT", "TT"):
+        assert torch.isfinite(train[key]).all() and torch.isfinite(test[key]).all()
+    before = ws.evaluate_loss(net, test)
+    hist = ws.train(net, train, epochs=40, batch=16, lr=2e-3, seed=1)
+    after = ws.evaluate_loss(net, test)
+    return net, hist, base, before, after
+
+
+def test_trained_network_beats_no_change_baseline(trained):
+    net, hist, base, before, after = trained
+    say(f"  no-change baseline {base:.3e}, untrained {before:.3e}, trained {after:.3e}; "
+        f"train loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert all(np.isfinite(hist))
+    assert hist[-1] < hist[0]
+    assert after < 0.5 * base
+
+
+def test_warm_started_solver_settles_near_the_plain_state(trained):
+    """The solver finishes from the network's prediction: the warm-started runs settle
+    (bulk densities steady to 1e-3) and end near the plain runs' bulk densities (this
+    small network, trained on 96 problems, lands within about 5 %; the full-size
+    workload's figures come from the benchmark)."""
+    from paper_2106_01557_amd import warmstart as ws
+    net = trained[0]
+    say("case: warm start comparison on 8 held-out problems, 3000 steps")
+    res = ws.compare_warm_start(net, _small_specs(8, seed=13), horizon=400, steps=3000, every=100)
+    for q in res["per_problem"]:
+        say(f"  {q}")
+    say(f"  {res['compared']} compared; plain median {res['plain_steps_median']}, warm median "
+        f"{res['warm_steps_median']}, final deviation {res['warm_final_max_rel_dev']}")
+    assert res["compared"] >= 4
+    assert res["warm_final_max_rel_dev"] < 1e-1

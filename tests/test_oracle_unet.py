@@ -122,13 +122,13 @@ def test_bf16_rounding():
 def test_unet_gradients_against_finite_differences():
     """Whole network (three levels, small widths) on an 8 x 8 periodic field: analytic
     gradients of the MSE loss against central differences on sampled entries."""
-    arch = U.Arch(widths=(3, 4, 5), in_channels=2, used_inputs=2)
+    arch = U.Arch(widths=(3, 4, 5), in_channels=3, used_inputs=3, outputs=2)
     p = U.init_params(arch, seed=3)
     for k in p:
         if k.endswith(".b"):
-            p[k] = rnd(p[k].shape, hash(k) % 1000) * 0.1
-    x = rnd((2, 8, 8, 2), 17)
-    t = rnd((2, 8, 8), 18)
+            p[k] = rnd(p[k].shape, sum(map(ord, k))) * 0.1
+    x = rnd((2, 8, 8, 3), 17)
+    t = rnd((2, 8, 8, 2), 18)
 
     def loss(pp, xx):
         return U.mse(U.forward(arch, pp, xx)[0], t)[0]
@@ -151,7 +151,7 @@ def test_unet_gradients_against_finite_differences():
             fd = (lp - lm) / (2 * h)
             assert abs(fd - gr[k][idx]) <= 1e-6 * max(1.0, abs(fd)), (k, idx, fd, gr[k][idx])
             checked += 1
-    for idx in [(0, 0, 0, 0), (1, 7, 3, 1), (0, 4, 5, 0)]:
+    for idx in [(0, 0, 0, 0), (1, 7, 3, 1), (0, 4, 5, 0), (1, 2, 6, 2)]:
         e = np.zeros_like(x); e[idx] = h
         fd = (loss(p, x + e) - loss(p, x - e)) / (2 * h)
         assert abs(fd - gx[idx]) <= 1e-6 * max(1.0, abs(fd))
@@ -163,7 +163,7 @@ def test_unet_mutations_are_caught():
     change its gradients by far more than the finite-difference agreement above."""
     arch = U.Arch(widths=(3, 4), in_channels=2, used_inputs=2)
     p = U.init_params(arch, seed=5)
-    x, t = rnd((1, 4, 4, 2), 20), rnd((1, 4, 4), 21)
+    x, t = rnd((1, 4, 4, 2), 20), rnd((1, 4, 4, 1), 21)
     out, cache = U.forward(arch, p, x)
     _, dout = U.mse(out, t)
     gr, _ = U.backward(arch, p, cache, dout)
