@@ -3,6 +3,7 @@
     python bench.py [--steps K] [--warmup W] [--precision f32|f64|f16|bf16] [--scheme ab|aa]
                     [--n 4096] [--no-cpu-baseline] [--gpus 1]
     python bench.py --workload batch64 [--steps K] [--coexistence STEPS]
+    python bench.py --workload warmstart [--train-runs 2000] [--horizon 5000] [--epochs 20]
 
 Workload: a static droplet on a periodic 4096 x 4096 D2Q9 lattice, radius 512 at
 the domain centre, tanh interface of width 4 nodes, Carnahan-Starling EOS with the
@@ -250,6 +251,104 @@ def batch_coexistence(b, sols, spec, steps, every, ms_per_step) -> dict:
     }
 
 
+def unet_step_flops(widths, in_channels, N, H, W) -> float:
+    """Dense FLOPs of one training step's 3x3 convolutions: forward, input gradient (all
+    layers but the first) and weight gradient, 2 N h w 9 C_in C_out each."""
+    from paper_2106_01557_amd import unet
+    tot = 0.0
+    for name, ci, co in unet.conv_layers(widths, in_channels):
+        lvl = int(name[1])
+        f = 2.0 * N * (H >> lvl) * (W >> lvl) * 9 * ci * co
+        tot += f * (2 if name == "e0a" else 3)
+    return tot
+
+
+def run_warmstart(args) -> dict:
+    """Learned warm start on 256 x 256 problems: generation of training data by the
+    batched solver, training of the U-Net on the matrix cores, held-out loss against the
+    no-change baseline, and plain against warm-started time to coexistence."""
+    import numpy as np
+    import torch
+    from paper_2106_01557_amd import unet, warmstart as ws
+
+    torch.cuda.set_device(0)
+    log = lambda m: print(f"# {m}", file=sys.stderr, flush=True)  # noqa: E731
+    side = 256
+    specs = ws.sample_specs(args.train_runs + args.test_runs, seed=3, side=side)
+    t0 = time.perf_counter()
+    ds, failed = ws.generate(specs, args.horizon, log=log)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    gen_mlups = len(specs) * side * side * args.horizon / t_gen / 1e6
+    n_ok = ds["rho0"].shape[0]
+    n_train = n_ok - args.test_runs
+    tr = {k: v[:n_train] for k, v in ds.items()}
+    te = {k: v[n_train:] for k, v in ds.items()}
+    del ds
+    bad = set(failed)
+    cmp_pool = [s_ for i, s_ in enumerate(specs) if i not in bad][n_train:]
+    net = unet.UNet(seed=0, stream=torch.cuda.current_stream())
+    base = ws.identity_loss(te)
+    before = ws.evaluate_loss(net, te)
+    # one timed training step (inputs resident), then the training run
+    B = args.batch
+    args_b = [tr[k][:B].contiguous() for k in ws.KEYS]
+    for _ in range(3):
+        net.train_step(*args_b, lr=0.0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        net.train_step(*args_b, lr=0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / reps
+    flops = unet_step_flops(net.widths, net.in_channels, B, side, side)
+    net = unet.UNet(seed=0, stream=torch.cuda.current_stream())  # fresh parameters for the run
+    t0 = time.perf_counter()
+    hist = ws.train(net, tr, epochs=args.epochs, batch=B, lr=args.lr, seed=4, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    after = ws.evaluate_loss(net, te)
+    log(f"held-out loss: no-change {base:.3e}, untrained {before:.3e}, trained {after:.3e}")
+    cmp_specs = cmp_pool[: args.compare_runs]
+    eq = ws.equal_error_steps(net, cmp_specs, args.horizon, 250, log=log)
+    log(f"equal-error steps saved: median {eq['steps_saved_median']:.0f} of {args.horizon}")
+    res = ws.compare_warm_start(net, cmp_specs, args.horizon, args.compare_steps, args.check_every, log=log)
+    per = res.pop("per_problem")
+    samples_s = args.epochs * (n_train // B) * B / t_train
+    achieved = flops / (step_ms * 1e-3) / 1e12
+    return {
+        "metric": "warm-start U-Net training samples/s (256x256, fwd+bwd+Adam)",
+        "value": round(samples_s, 2),
+        "unit": "samples/s",
+        "n_gpus": 1, "steps": args.epochs * (n_train // B), "warmup": 3,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 (FP32 accumulate, FP32 master weights)", "data": "synthetic (solver-generated)",
+        "config": {
+            "workload": "256x256 periodic problems, 1-8 droplets R U[8,48], T/Tc U[0.7,0.9], tanh W=4, +-0.5% "
+                        f"noise, PCG64 seed 3; {n_train} train / {args.test_runs} test runs, horizon "
+                        f"{args.horizon} steps; U-Net widths {list(net.widths)}, batch {B}, {args.epochs} epochs",
+            "batch": B, "epochs": args.epochs,
+        },
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(achieved / 2500.0, 4), "traffic": None,
+                     "kernel": "one training step (all 3x3 convolution kernels, dense FLOPs)",
+                     "flops_per_step": flops},
+        "data_generation": {"runs": len(specs), "non_finite_runs": len(failed),
+                            "non_finite_Tr": [round(specs[i].tr, 4) for i in failed],
+                            "seconds": round(t_gen, 2), "MLUPS": round(gen_mlups, 1)},
+        "training": {"seconds": round(t_train, 2), "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]},
+        "held_out": {"no_change_loss": base, "untrained_loss": before, "trained_loss": after,
+                     "ratio_to_no_change": after / base},
+        "equal_error": eq,
+        "warm_start": res,
+        "warm_start_per_problem": per,
+    }
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
     """A plain device copy of known size: read nbytes + write nbytes per launch.  Profiling
     it with the same HBM counters gives the factor that turns counter readings into bytes."""
@@ -270,7 +369,15 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="droplet4096", choices=["droplet4096", "batch64"])
+    ap.add_argument("--workload", default="droplet4096", choices=["droplet4096", "batch64", "warmstart"])
+    ap.add_argument("--train-runs", type=int, default=2000)
+    ap.add_argument("--test-runs", type=int, default=64)
+    ap.add_argument("--horizon", type=int, default=5000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--compare-runs", type=int, default=64)
+    ap.add_argument("--compare-steps", type=int, default=20000)
     ap.add_argument("--autotune-steps", type=int, default=5)
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--coexistence", type=int, default=0,
@@ -297,6 +404,9 @@ def main() -> int:
 
     if args.workload == "batch64":
         print(json.dumps(run_batch(args)), flush=True)
+        return 0
+    if args.workload == "warmstart":
+        print(json.dumps(run_warmstart(args)), flush=True)
         return 0
 
     import torch

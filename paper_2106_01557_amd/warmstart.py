@@ -40,7 +40,7 @@ class Spec:
     seed: int
 
 
-def sample_specs(n: int, seed: int, side: int = 256, drops=(1, 8), radii=(8.0, 48.0), tr=(0.65, 0.9)) -> list:
+def sample_specs(n: int, seed: int, side: int = 256, drops=(1, 8), radii=(8.0, 48.0), tr=(0.7, 0.9)) -> list:
     """n problems from PCG64(seed): droplet count uniform in drops, radii uniform in
     radii, centres uniform on the lattice, T/Tc uniform in tr."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -144,27 +144,27 @@ KEYS = ("rho0", "T0f", "rhoT", "TT", "rho_v", "rho_l", "T0", "cond")
 def generate(specs, horizon: int, chunk: int = 64, precision: str = "f32", log=None):
     """Runs every problem `horizon` steps from its seeded initial field (at rest, T0).
     Returns device tensors rho0, T0f, rhoT, TT [n, side, side] (FP64) and rho_v, rho_l,
-    T0, cond [n]."""
+    T0, cond [n] of the runs that stayed finite, and the indices (into specs) of those
+    that did not."""
     import torch
     parts = {k: [] for k in KEYS}
+    failed = []
     for i in range(0, len(specs), chunk):
         r = Runner(specs[i:i + chunk], precision=precision)
         rho0 = r.initial_density()
         r.set_fields(rho0)
         r.step(horizon)
         rhoT, TT = r.fields()
-        parts["rho0"].append(rho0)
-        parts["T0f"].append(r.uniform_T())
-        parts["rhoT"].append(rhoT)
-        parts["TT"].append(TT)
-        parts["rho_v"].append(r.rho_v)
-        parts["rho_l"].append(r.rho_l)
-        parts["T0"].append(r.T0)
-        parts["cond"].append(r.cond)
+        ok = torch.isfinite(rhoT).all(dim=(1, 2)) & torch.isfinite(TT).all(dim=(1, 2))
+        failed += [i + j for j in range(len(ok)) if not bool(ok[j])]
+        keep = torch.nonzero(ok).flatten()
+        for key, v in (("rho0", rho0), ("T0f", r.uniform_T()), ("rhoT", rhoT), ("TT", TT), ("rho_v", r.rho_v),
+                       ("rho_l", r.rho_l), ("T0", r.T0), ("cond", r.cond)):
+            parts[key].append(v.index_select(0, keep))
         r.close()
         if log:
-            log(f"generated {min(i + chunk, len(specs))}/{len(specs)} runs")
-    return {k: torch.cat(v) for k, v in parts.items()}
+            log(f"generated {min(i + chunk, len(specs))}/{len(specs)} runs ({len(failed)} non-finite so far)")
+    return {k: torch.cat(v) for k, v in parts.items()}, failed
 
 
 def identity_loss(ds, theta_scale: float = 0.1, outputs: int = 2) -> float:
@@ -286,4 +286,74 @@ def compare_warm_start(net, specs, horizon: int, steps: int, every: int, log=Non
         "per_problem": [{"plain": plain[i], "warm": warm[i], "rho_l": float(final[0][i]), "rho_v": float(final[1][i]),
                          "warm_rho_l": float(wlast[0][i]), "warm_rho_v": float(wlast[1][i])}
                         for i in range(len(specs))],
+    }
+
+
+def _mse_fields(rho, T, rho_ref, T_ref, rho_v, rho_l, T0, theta_scale=0.1, outputs=2):
+    """Per-problem mean squared difference of the normalised fields (the network's loss)."""
+    sc = (rho_l - rho_v)[:, None, None]
+    e = ((rho - rho_ref) / sc) ** 2
+    e = e.mean(dim=(1, 2))
+    if outputs > 1:
+        e = 0.5 * (e + (((T - T_ref) / T0[:, None, None] / theta_scale) ** 2).mean(dim=(1, 2)))
+    return e
+
+
+def equal_error_steps(net, specs, horizon: int, every: int, log=None):
+    """Steps the warm start saves at equal error: for each problem, the number of plain
+    solver steps from the initial field after which the state is as close to the
+    horizon state (normalised mean squared difference of density and temperature) as
+    the network's prediction is; linear interpolation between samples every `every`
+    steps.  Returns a summary with the per-problem values."""
+    import torch
+    r = Runner(specs)
+    rho0 = r.initial_density()
+    T0f = r.uniform_T()
+    r.set_fields(rho0)
+    r.step(horizon)
+    rhoT, TT = r.fields()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prho, pT = net.predict_fields(rho0, T0f, r.rho_v, r.rho_l, r.T0, r.cond)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    ek = dict(rho_v=r.rho_v, rho_l=r.rho_l, T0=r.T0, outputs=net.K)
+    e_net = _mse_fields(prho, pT, rhoT, TT, **ek).cpu().numpy()
+    r.set_fields(rho0)
+    curve = [(0, _mse_fields(rho0, T0f, rhoT, TT, **ek).cpu().numpy())]
+    t_step = 0.0
+    for s in range(every, horizon + 1, every):
+        t1 = time.perf_counter()
+        r.step(every)
+        r.stream.synchronize()
+        t_step += time.perf_counter() - t1
+        rho, T = r.fields()
+        curve.append((s, _mse_fields(rho, T, rhoT, TT, **ek).cpu().numpy()))
+    r.close()
+    steps = np.array([c[0] for c in curve], dtype=float)
+    errs = np.stack([c[1] for c in curve])  # [samples, problems]
+    saved = []
+    for i in range(len(specs)):
+        e = errs[:, i]
+        hit = np.nonzero(e <= e_net[i])[0]
+        if len(hit) == 0:
+            saved.append(0.0)
+            continue
+        k = hit[0]
+        if k == 0:
+            saved.append(0.0)  # no better than the initial field
+            continue
+        # interpolate in log error between the samples around the crossing
+        a, b_ = np.log(max(e[k - 1], 1e-30)), np.log(max(e[k], 1e-30))
+        f = (np.log(max(e_net[i], 1e-30)) - a) / (b_ - a) if b_ != a else 1.0
+        saved.append(float(steps[k - 1] + f * (steps[k] - steps[k - 1])))
+    saved = np.array(saved)
+    step_s = t_step / horizon  # seconds per batched step of all problems together
+    return {
+        "problems": len(specs), "horizon": horizon,
+        "net_mse_median": float(np.median(e_net)), "no_change_mse_median": float(np.median(errs[0])),
+        "steps_saved_median": float(np.median(saved)), "steps_saved_mean": float(saved.mean()),
+        "fraction_of_horizon_median": float(np.median(saved) / horizon),
+        "seconds_saved_mean": float(saved.mean() * step_s), "inference_seconds": t_inf,
+        "per_problem_steps_saved": [round(float(v), 1) for v in saved],
     }

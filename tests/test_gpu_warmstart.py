@@ -21,8 +21,9 @@ def trained():
     import torch
     from paper_2106_01557_amd import unet, warmstart as ws
     say("case: warm start, 64x64 problems, 400-step horizon, train 96 / test 32")
-    train = ws.generate(_small_specs(96, seed=11), horizon=400)
-    test = ws.generate(_small_specs(32, seed=12), horizon=400)
+    train, bad_train = ws.generate(_small_specs(96, seed=11), horizon=400)
+    test, bad_test = ws.generate(_small_specs(32, seed=12), horizon=400)
+    assert not bad_train and not bad_test
     net = unet.UNet(widths=(16, 32, 64), seed=0, stream=torch.cuda.current_stream())
     base = ws.identity_loss(test)
     for key in ("rho0", "T0f", "rhoT", "TT"):
@@ -57,3 +58,16 @@ def test_warm_started_solver_settles_near_the_plain_state(trained):
         f"{res['warm_steps_median']}, final deviation {res['warm_final_max_rel_dev']}")
     assert res["compared"] >= 4
     assert res["warm_final_max_rel_dev"] < 1e-1
+
+
+def test_equal_error_steps_are_positive_for_the_trained_network(trained):
+    """The trained network's prediction is worth a positive number of solver steps on
+    held-out problems (the plain run needs that many steps to get as close to the
+    horizon state)."""
+    from paper_2106_01557_amd import warmstart as ws
+    say("case: equal-error steps saved, 16 held-out problems")
+    eq = ws.equal_error_steps(trained[0], _small_specs(16, seed=14), horizon=400, every=25)
+    say(f"  net mse {eq['net_mse_median']:.3e}, no-change {eq['no_change_mse_median']:.3e}, saved median "
+        f"{eq['steps_saved_median']:.0f} of 400: {eq['per_problem_steps_saved']}")
+    assert eq["net_mse_median"] < eq["no_change_mse_median"]
+    assert eq["steps_saved_median"] > 0
