@@ -301,8 +301,19 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= Cout * (K + 1)) return;
     const int o = idx / (K + 1), k = idx - o * (K + 1);
-    float s = 0.f;
-    for (int z = 0; z < slabs; ++z) s += part[((size_t)z * Cout + o) * Kt + k];
+    const size_t stride = (size_t)Cout * Kt;
+    const float* q = part + (size_t)o * Kt + k;
+    // four independent chains (z mod 4), combined in a fixed order: deterministic
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int z = 0;
+    for (; z + 4 <= slabs; z += 4) {
+        a0 += q[(size_t)z * stride];
+        a1 += q[(size_t)(z + 1) * stride];
+        a2 += q[(size_t)(z + 2) * stride];
+        a3 += q[(size_t)(z + 3) * stride];
+    }
+    for (; z < slabs; ++z) a0 += q[(size_t)z * stride];
+    const float s = (a0 + a1) + (a2 + a3);
     if (k < K) dw[(size_t)o * K + k] = s;
     else if (db) db[o] = s;
 }
@@ -494,15 +505,22 @@ __global__ void __launch_bounds__(kHeadBlock) k_head_fwd(const bf16_t* d, int ld
     }
 }
 
-// part: [blocks][K (C + 1)]: per-block sums of dout_k d[., c] and of dout_k
+// wavefront sum (xor butterfly: the same association in every wavefront)
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// part: [blocks * 4 wavefronts][K (C + 1)]: per-wavefront sums of dout_k d[., c] and of dout_k
 __global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ldd, const float* hw,
                                                          const float* dout, bf16_t* g, float* part, int C, int K,
                                                          int P) {
-    __shared__ float sm[kHeadBlock];
     const int p = blockIdx.x * kHeadBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     float dp[4] = {0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < K; ++k) dp[k] = p < P ? dout[(size_t)k * P + p] : 0.f;
-    const size_t row = (size_t)blockIdx.x * K * (C + 1);
+    const size_t row = ((size_t)blockIdx.x * (kHeadBlock / 64) + (threadIdx.x >> 6)) * K * (C + 1);
     for (int c = 0; c < C; c += 8) {
         float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, o[8];
         if (p < P) unpack8(ld16(d + (size_t)p * ldd + c), v);
@@ -516,25 +534,34 @@ __global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ld
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const float b = block_sum(dp[k] * v[j], sm);
-                if (threadIdx.x == 0) part[row + (size_t)k * (C + 1) + c + j] = b;
+                const float b = wave_sum(dp[k] * v[j]);
+                if (lane == 0) part[row + (size_t)k * (C + 1) + c + j] = b;
             }
     }
     for (int k = 0; k < K; ++k) {
-        const float b = block_sum(dp[k], sm);
-        if (threadIdx.x == 0) part[row + (size_t)k * (C + 1) + C] = b;
+        const float b = wave_sum(dp[k]);
+        if (lane == 0) part[row + (size_t)k * (C + 1) + C] = b;
     }
 }
 
-// out[j] = sum over blocks of part[b][j] (j < m), in block order, times scale; with
-// stride > 0 the entries j % stride == stride - 1 go to out1[j / stride] instead
-__global__ void k_sum_partials(const float* part, int blocks, int m, float scale, float* out0, float* out1,
-                               int stride) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
+// out[j] = sum over blocks of part[b][j] (j < m) times scale, one workgroup per j:
+// thread t sums rows t, t + 256, ... in order, then a fixed tree combines the 256
+// partial sums (deterministic).  With stride > 0 the entries j % stride == stride - 1
+// go to out1[j / stride] and the others to out0 with those entries skipped.
+__global__ void __launch_bounds__(256) k_sum_partials(const float* part, int blocks, int m, float scale, float* out0,
+                                                      float* out1, int stride) {
+    __shared__ double sm[256];
+    const int j = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += part[(size_t)b * m + j];
-    const float v = (float)(s * scale);
+    for (int b = threadIdx.x; b < blocks; b += 256) s += part[(size_t)b * m + j];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const float v = (float)(sm[0] * scale);
     if (stride > 0 && j % stride == stride - 1) out1[j / stride] = v;
     else if (stride > 0) out0[(j / stride) * (stride - 1) + j % stride] = v;
     else out0[j] = v;
@@ -634,7 +661,7 @@ WgPlan wgrad_plan(int P, int Cin, int Cout) {
     w.Kt = 64 * w.ktiles;
     w.CT = Cout % 64 == 0 ? 64 : 32;
     w.ctiles = (Cout + w.CT - 1) / w.CT;
-    const int want = 4096;  // workgroups to aim for
+    const int want = 1024;  // workgroups to aim for: four per CU; longer slabs keep the partials small
     int slabs = (want + w.ktiles * w.ctiles - 1) / (w.ktiles * w.ctiles);
     const int max_slabs = (P + 255) / 256;  // at least 256 pixels per slab
     if (slabs > max_slabs) slabs = max_slabs;
@@ -833,7 +860,7 @@ int unet_head_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C, int32_t 
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
     if (!bytes || C < 8 || C % 8 || K < 1 || K > 4) return fail(UNET_EINVAL, "head: bad channels or outputs");
     const size_t blocks = ((size_t)N * H * W + kHeadBlock - 1) / kHeadBlock;
-    *bytes = blocks * K * (C + 1) * sizeof(float);
+    *bytes = blocks * (kHeadBlock / 64) * K * (C + 1) * sizeof(float);  // one row per wavefront
     return UNET_OK;
 }
 
@@ -853,7 +880,7 @@ int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, 
                        rin, target, out, dout, static_cast<float*>(partials), C, K, P);
     if ((r = launched("head launch"))) return r;
     if (target) {
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, static_cast<const float*>(partials), blocks, 1,
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, static_cast<const float*>(partials), blocks, 1,
                            1.0f / (float)((size_t)K * P), loss, (float*)nullptr, 0);
         return launched("loss reduce launch");
     }
@@ -875,8 +902,8 @@ int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout
                        static_cast<bf16_t*>(g), static_cast<float*>(partials), C, K, P);
     if ((r = launched("head bwd launch"))) return r;
     const int m = K * (C + 1);
-    hipLaunchKernelGGL(k_sum_partials, dim3((m + 63) / 64), dim3(64), 0, s, static_cast<const float*>(partials), blocks,
-                       m, 1.0f, dhw, dhb, C + 1);
+    hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(256), 0, s, static_cast<const float*>(partials),
+                       blocks * (kHeadBlock / 64), m, 1.0f, dhw, dhb, C + 1);
     return launched("head reduce launch");
 }
 
