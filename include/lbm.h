@@ -201,7 +201,7 @@ int lbm_maxwell(const lbm_eos* eos, double Tr, double out[4]);
  * single-lattice calls (moments, invariants, save/load, even lbm_step); the
  * batch notices a member stepped alone and re-reads its buffers.  Members must
  * outlive the batch and share one precision and one stream, and each must keep
- * 35 population planes below 4 GiB (32-bit buffer offsets). */
+ * 19 nx ny bytes-per-value below 4 GiB (32-bit buffer offsets). */
 typedef struct lbm_batch lbm_batch;  /* opaque; owned by the library */
 
 /* Work distribution of a batched launch. */

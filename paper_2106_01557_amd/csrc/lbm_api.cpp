@@ -300,12 +300,6 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     if ((r = check_lattice(lat)) || (r = check_eos(eos)) || (r = check_params(p))) return r;
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_EINVAL, "out of host memory");
-    if ((size_t)lat->nx * lat->ny * lbm_dev::storage_bytes(p->precision) >= ((size_t)1 << 32)) {
-        fail(nullptr, LBM_EINVAL, "one population plane must stay below 4 GiB (32-bit offsets); got %d x %d",
-             lat->nx, lat->ny);
-        delete c;
-        return LBM_EINVAL;
-    }
     c->lat = *lat;
     c->eos = *eos;
     c->p = *p;

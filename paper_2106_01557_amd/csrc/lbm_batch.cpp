@@ -297,8 +297,8 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* 
         if (c->p.precision != m0->p.precision)
             return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one precision", i);
         if (c->stream != m0->stream) return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one stream", i);
-        if ((size_t)35 * c->lat.nx * c->lat.ny * lbm_dev::storage_bytes(c->p.precision) >= ((size_t)1 << 32))
-            return bfail(nullptr, LBM_EINVAL, "member %d: %d x %d is too large for a batch (35 planes must stay below 4 GiB)",
+        if ((size_t)19 * c->lat.nx * c->lat.ny * lbm_dev::storage_bytes(c->p.precision) >= ((size_t)1 << 32))
+            return bfail(nullptr, LBM_EINVAL, "member %d: %d x %d is too large for a batch (19 nx ny sizeof must stay below 4 GiB)",
                          i, c->lat.nx, c->lat.ny);
         for (int32_t j = 0; j < i; ++j)
             if (members[j] == c) return bfail(nullptr, LBM_EINVAL, "member %d appears twice", i);

@@ -1,8 +1,11 @@
 // HIP kernels for gfx950 (MI355X): the lattice update of the liquid-vapour
 // double-distribution model and its diagnostics.
 //
-// Layout in HBM: structure of arrays, 18 planes of nx*ny values (plane i < 9 is
-// f_i, plane 9 + i is g_i), each plane row-major [y][x] with x fastest.
+// Layout in HBM: row-interleaved structure of arrays [y][s][x]: for each lattice row
+// y, the 18 population rows (slot s < 9 is f_s, slot 9 + s is g_s) follow each other,
+// x fastest.  A wavefront's 36 row accesses of one step then fall in three
+// contiguous blocks of 18 rows instead of 18 planes far apart, which keeps the DRAM
+// page and channel pattern close to a plain copy.
 // Velocity order (SM Eq. (1)): 0 rest, 1 (+x), 2 (+y), 3 (-x), 4 (-y),
 // 5 (+x,+y), 6 (-x,+y), 7 (-x,-y), 8 (+x,-y).
 //
@@ -13,6 +16,8 @@
 // and the closure p_LBE = c_s^2 (rho + eta) = p_BE (Eq. (15)).  No MFMA: the
 // update is not a contraction; it is bound by HBM traffic (36 values per node
 // per step in the fused two-buffer scheme).
+
+#include <cstdlib>
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
@@ -66,6 +71,9 @@ __device__ inline int remap_xcd(int b, int nb) {
 }
 
 __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Element index of slot s (0..17) at node (x, y) in the row-interleaved layout.
+__device__ inline size_t slot_index(int s, int x, int y, int nx) { return ((size_t)y * 18 + s) * (size_t)nx + x; }
 
 // ---------------------------------------------------------------------------
 // pointwise model pieces
@@ -312,15 +320,16 @@ __device__ inline int wrap_row(int v, int n) {
 }
 
 // Addressing: with kBuf every access is a raw buffer instruction on one resource
-// per state buffer whose record count covers all 18 planes; for row accesses the
-// plane offset goes in the scalar offset and the lane's row/column byte offset in
-// the vector offset, for the gather the whole offset is per lane.  A lane that
-// must not store, or whose gather slot is unused, gets the vector offset
-// drop = 2^32 - 1 - 17 * plane_bytes: for every plane the total offset then lies at
-// or past the record count without leaving 32 bits, so the hardware drops the
-// store (or returns zero) whether or not it counts the scalar offset in its range
-// check.  That needs 35 * plane_bytes < 2^32, which the launcher checks; larger
-// lattices use 64-bit plane addresses and branches instead.
+// per state buffer whose record count covers the whole buffer; for row accesses the
+// slot offset (s times the bytes of one population row) goes in the scalar offset and
+// the lane's row-block/column byte offset in the vector offset, for the gather the
+// whole offset is per lane.  A lane that must not store, or whose gather slot is
+// unused, gets the vector offset drop = 2^32 - 1 - 17 * row_bytes: for every slot
+// the total offset then lies at or past the record count without leaving 32 bits,
+// so the hardware drops the store (or returns zero) whether or not it counts the
+// scalar offset in its range check.  That needs buffer_bytes + 17 * row_bytes < 2^32
+// (the launcher checks 19 * nx * ny * sizeof(S) < 2^32); larger lattices use 64-bit
+// addresses and branches instead.
 template <typename S>
 struct Bits;
 template <>
@@ -364,51 +373,60 @@ struct Bits<__hip_bfloat16> {
 template <typename S, bool kBuf>
 struct Planes;
 
+// Byte offsets within a state buffer: 32 bits on the buffer-instruction path.
+template <bool kBuf>
+struct OffT {
+    using type = size_t;
+};
+template <>
+struct OffT<true> {
+    using type = unsigned;
+};
+
 template <typename S>
 struct Planes<S, true> {
     __amdgpu_buffer_rsrc_t r;
-    unsigned pb, drop;
-    __device__ Planes(const void* base, size_t plane_bytes)
-        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)(unsigned)(18 * plane_bytes),
-                                              0x00020000)),
-          pb((unsigned)plane_bytes),
-          drop((0xFFFFFFFFu - 17u * (unsigned)plane_bytes) & ~(unsigned)(sizeof(S) - 1)) {}
+    unsigned ps, drop;  // ps: bytes of one population row (the slot stride)
+    __device__ Planes(const void* base, size_t total_bytes, unsigned row_bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)(unsigned)total_bytes, 0x00020000)),
+          ps(row_bytes),
+          drop((0xFFFFFFFFu - 17u * row_bytes) & ~(unsigned)(sizeof(S) - 1)) {}
     template <typename C>
     __device__ C ld(int i, unsigned off, C ref) const {
-        const S v = Bits<S>::ld(r, off, pb * (unsigned)i);
+        const S v = Bits<S>::ld(r, off, ps * (unsigned)i);
         return Io<S, C>::ld(&v, 0, ref);
     }
-    // per-lane plane; an unused slot reads zero
+    // per-lane slot; an unused gather slot reads zero
     template <typename C>
-    __device__ C gather(unsigned plane, unsigned off, bool on, C ref) const {
-        const S v = Bits<S>::ld(r, on ? pb * plane + off : drop, 0u);
+    __device__ C gather(unsigned slot, unsigned off, bool on, C ref) const {
+        const S v = Bits<S>::ld(r, on ? ps * slot + off : drop, 0u);
         return Io<S, C>::ld(&v, 0, ref);
     }
     template <typename C>
     __device__ void st(int i, unsigned off, C v, C ref, bool valid) const {
         S t;
         Io<S, C>::st(&t, 0, v, ref);
-        Bits<S>::st(t, r, valid ? off : drop, pb * (unsigned)i);
+        Bits<S>::st(t, r, valid ? off : drop, ps * (unsigned)i);
     }
 };
 
 template <typename S>
 struct Planes<S, false> {
     char* base;
-    size_t pb;
-    __device__ Planes(const void* b, size_t plane_bytes) : base((char*)b), pb(plane_bytes) {}
+    size_t ps;
+    __device__ Planes(const void* b, size_t, unsigned row_bytes) : base((char*)b), ps(row_bytes) {}
     template <typename C>
-    __device__ C ld(int i, unsigned off, C ref) const {
-        return Io<S, C>::ld(reinterpret_cast<const S*>(base + pb * i + off), 0, ref);
+    __device__ C ld(int i, size_t off, C ref) const {
+        return Io<S, C>::ld(reinterpret_cast<const S*>(base + ps * i + off), 0, ref);
     }
     template <typename C>
-    __device__ C gather(unsigned plane, unsigned off, bool on, C ref) const {
-        // unused slots read plane 0 at offset 0 (a valid address) and are ignored
-        return on ? Io<S, C>::ld(reinterpret_cast<const S*>(base + pb * plane + off), 0, ref) : C(0);
+    __device__ C gather(unsigned slot, size_t off, bool on, C ref) const {
+        // unused slots read slot 0 at offset 0 (a valid address) and are ignored
+        return on ? Io<S, C>::ld(reinterpret_cast<const S*>(base + ps * slot + off), 0, ref) : C(0);
     }
     template <typename C>
-    __device__ void st(int i, unsigned off, C v, C ref, bool valid) const {
-        if (valid) Io<S, C>::st(reinterpret_cast<S*>(base + pb * i + off), 0, v, ref);
+    __device__ void st(int i, size_t off, C v, C ref, bool valid) const {
+        if (valid) Io<S, C>::st(reinterpret_cast<S*>(base + ps * i + off), 0, v, ref);
     }
 };
 
@@ -421,7 +439,7 @@ __device__ inline C sum9(const C* f) {
 // names a population, a column and the row offset -e_y of that population.
 struct Strip {
     int nx, ny;
-    unsigned rowb, esz;
+    unsigned rowb, esz;   // bytes of one population row; bytes per value
     unsigned xc;          // the lane's column (clamped to a valid column past the strip end)
     bool owner;           // the lane holds an owned column
     int last;             // last owned lane
@@ -429,34 +447,37 @@ struct Strip {
     bool fon, gon;
     unsigned fplane, gplane, fcol, gcol;
     int fdy, gdy;
-    __device__ unsigned off(int y, unsigned x) const { return (unsigned)y * rowb + x * esz; }
 };
 
-// Raw loads for one target row: plane i at source row y - e_iy, aligned, and the
-// gather.  up/mid/dn are the byte offsets of source rows y+1, y, y-1 (periodic).
+// Raw loads for one target row: slot i at source row y - e_iy, aligned, and the
+// gather.  up/mid/dn are the byte offsets of the row blocks of source rows y+1, y,
+// y-1 (periodic).
 template <typename S, typename C, bool kBuf>
-__device__ inline void load_target_row(const Planes<S, kBuf>& B, int first, const Strip& G, unsigned up,
-                                       unsigned mid, unsigned dn, bool is_f, const C* ref, C* raw, C& gth) {
+__device__ inline void load_target_row(const Planes<S, kBuf>& B, int first, const Strip& G,
+                                       typename OffT<kBuf>::type up, typename OffT<kBuf>::type mid,
+                                       typename OffT<kBuf>::type dn, bool is_f, const C* ref, C* raw, C& gth) {
+    using Off = typename OffT<kBuf>::type;
     const unsigned xo = G.xc * G.esz;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const unsigned r = kEy[i] < 0 ? up : (kEy[i] > 0 ? dn : mid);
+        const Off r = kEy[i] < 0 ? up : (kEy[i] > 0 ? dn : mid);
         raw[i] = B.template ld<C>(first + i, r + xo, ref[i]);
     }
     const unsigned plane = is_f ? G.fplane : G.gplane;
     const unsigned col = is_f ? G.fcol : G.gcol;
     const int dy = is_f ? G.fdy : G.gdy;  // -e_y of the slot's population
     const bool on = is_f ? G.fon : G.gon;
-    const unsigned r = dy > 0 ? up : (dy < 0 ? dn : mid);
-    // the gather's reference is the plane's own (it differs per lane)
+    const Off r = dy > 0 ? up : (dy < 0 ? dn : mid);
+    // the gather's reference is the slot's own (it differs per lane)
     gth = B.template gather<C>(first + plane, r + col * G.esz, on, ref[plane]);
 }
 
-// Byte offset of the next row, periodic in y: one conditional subtraction is exact
-// because the offset is always below the plane size.
-__device__ inline unsigned next_row(unsigned o, unsigned rowb, unsigned pb) {
-    o += rowb;
-    return o >= pb ? o - pb : o;
+// Byte offset of the next row block, periodic in y: one conditional subtraction is
+// exact because the offset is always below the buffer size.
+template <typename Off>
+__device__ inline Off next_row(Off o, Off block, Off total) {
+    o += block;
+    return o >= total ? o - total : o;
 }
 
 // Streamed populations of the target row from its raw loads (DPP shifts plus the
@@ -547,7 +568,8 @@ struct Dens {
 // R[0..3] hold the byte offsets of rows y+1 .. y+4 (periodic); yo that of row y.
 template <int kStage, typename S, typename C, bool kBuf>
 __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
-                                       const Strip& G, unsigned yo, unsigned (&R)[4], C (&fA)[9], C (&fB)[9],
+                                       const Strip& G, typename OffT<kBuf>::type yo,
+                                       typename OffT<kBuf>::type (&R)[4], C (&fA)[9], C (&fB)[9],
                                        C (&rC)[9], C& hC, C (&gA)[9], C (&rgB)[9], C& hgB, Dens<C>& dm,
                                        Dens<C>& dc, Dens<C>& dp) {
     const int lane = threadIdx.x & 63;
@@ -570,7 +592,7 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
     stencil(rE, dp.v, rW, dm.v, rNE, rNW, rSW, rSE, sx, sy);
     C fo[9], go[9];
     collide(P, fA, gA, dc.v, sx, sy, fo, go);
-    const unsigned o = yo + G.xc * G.esz;
+    const typename OffT<kBuf>::type o = yo + G.xc * G.esz;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         out.template st<C>(i, o, fo[i], P.ref_f[i], G.owner);
@@ -639,20 +661,25 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
         G.gcol = grp == 0 ? l1 : r1;
         G.gdy = pg == 5 || pg == 6 ? -1 : (pg == 7 || pg == 8 ? 1 : 0);
     }
-    const size_t pb = (size_t)nx * ny * sizeof(S);
-    const Planes<S, kBuf> Pin(in, pb);
-    const Planes<S, kBuf> Pout(out, pb);
+    using Off = typename OffT<kBuf>::type;
+    const size_t total = (size_t)18 * nx * ny * sizeof(S);
+    const Planes<S, kBuf> Pin(in, total, G.rowb);
+    const Planes<S, kBuf> Pout(out, total, G.rowb);
     const int y0 = chunk * rows, y1 = min(ny, y0 + rows);
-    const unsigned pbu = (unsigned)pb;  // only used when the byte offsets fit in 32 bits
+    const Off blk = (Off)18 * G.rowb;  // bytes of one row block (all 18 slots of a row)
+    const Off tot = (Off)total;
 
     // register ring: streamed f of rows y, y+1 and raw loads of row y+2; streamed g of
     // row y and raw loads of row y+1; densities of rows y-1, y, y+1
     C fA[9], fB[9], rC[9], hC, gA[9], rgB[9], hgB;
     Dens<C> dm, dc, dp;
-    // byte offsets of rows y0-2 .. y0+3 (periodic)
-    unsigned ro[6];
+    // byte offsets of the row blocks of rows y0-2 .. y0+3 (periodic)
+    Off ro[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ro[k] = __builtin_amdgcn_readfirstlane((unsigned)wrap_row(y0 - 2 + k, ny) * G.rowb);
+    for (int k = 0; k < 6; ++k) {
+        const int yy = __builtin_amdgcn_readfirstlane(wrap_row(y0 - 2 + k, ny));
+        ro[k] = (Off)yy * blk;
+    }
     {
         C r[9], h, t[9];
         load_target_row<S, C, kBuf>(Pin, 0, G, ro[2], ro[1], ro[0], true, P.ref_f, r, h);
@@ -672,8 +699,8 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
 #pragma unroll
     for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(rgB[i]), "v"(rC[i]));
     asm volatile("" ::"v"(hgB), "v"(hC));
-    unsigned R[4] = {ro[3], ro[4], ro[5], next_row(ro[5], G.rowb, pbu)};  // rows y+1 .. y+4
-    unsigned yo = ro[2];
+    Off R[4] = {ro[3], ro[4], ro[5], next_row<Off>(ro[5], blk, tot)};  // rows y+1 .. y+4
+    Off yo = ro[2];
     int y = y0;
     for (; y < y1 - 2; ++y) {
         ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
@@ -681,7 +708,7 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
         R[0] = R[1];
         R[1] = R[2];
         R[2] = R[3];
-        R[3] = next_row(R[3], G.rowb, pbu);
+        R[3] = next_row<Off>(R[3], blk, tot);
     }
     if (y < y1 - 1) {
         ab_row<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
@@ -711,7 +738,7 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
 // Queue mode: a persistent grid; the item range is cut into `groups` contiguous
 // ranges, one per XCD (a block's XCD is its index modulo 8), and the wavefronts of
 // an XCD take items of its range from an atomic counter until it is exhausted.
-// Every lattice must satisfy the 32-bit buffer-offset bound (35 planes < 4 GiB).
+// Every lattice must satisfy the 32-bit buffer-offset bound (19 nx ny sizeof(S) < 2^32).
 template <typename S, typename C>
 __device__ __forceinline__ void batch_item(const BatchDesc<C>* __restrict__ desc, const int32_t* __restrict__ starts,
                                            const int nlat, const int w, const int parity) {
@@ -785,17 +812,19 @@ template <typename S, typename C>
 __global__ void __launch_bounds__(256)
 k_step_aa(S* __restrict__ st, const double* __restrict__ rho_arr, const Consts<C> P, const int parity) {
     using IO = Io<S, C>;
-    const int nx = P.nx, ny = P.ny, N = nx * ny;
+    const int nx = P.nx, ny = P.ny;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= nx || y >= ny) return;
     int rs[9], ro[9], ws[9], wo[9];
     aa_offsets<S, C>(parity, x, y, nx, ny, rs, ro, ws, wo);
+    // node offsets k = y' nx + x' -> element index of slot s: k + (17 y' + s) nx
     C f[9], g[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        f[i] = IO::ld(st + (size_t)rs[i] * N, ro[i], P.ref_f[i]);
-        g[i] = IO::ld(st + (size_t)(9 + rs[i]) * N, ro[i], P.ref_g[i]);
+        const size_t b = (size_t)ro[i] + (size_t)(17 * (ro[i] / nx)) * nx;
+        f[i] = IO::ld(st + b + (size_t)rs[i] * nx, 0, P.ref_f[i]);
+        g[i] = IO::ld(st + b + (size_t)(9 + rs[i]) * nx, 0, P.ref_g[i]);
     }
     const int xe = wrap(x + 1, nx), xw = wrap(x - 1, nx);
     const int yn = wrap(y + 1, ny) * nx, ys = wrap(y - 1, ny) * nx, yc = y * nx;
@@ -807,8 +836,9 @@ k_step_aa(S* __restrict__ st, const double* __restrict__ rho_arr, const Consts<C
     collide(P, f, g, rho, sx, sy, fo, go);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        IO::st(st + (size_t)ws[i] * N, wo[i], fo[i], P.ref_f[i]);
-        IO::st(st + (size_t)(9 + ws[i]) * N, wo[i], go[i], P.ref_g[i]);
+        const size_t b = (size_t)wo[i] + (size_t)(17 * (wo[i] / nx)) * nx;
+        IO::st(st + b + (size_t)ws[i] * nx, 0, fo[i], P.ref_f[i]);
+        IO::st(st + b + (size_t)(9 + ws[i]) * nx, 0, go[i], P.ref_g[i]);
     }
 }
 
@@ -818,16 +848,17 @@ k_step_aa(S* __restrict__ st, const double* __restrict__ rho_arr, const Consts<C
 template <typename S, typename C>
 __device__ inline void load_node(const S* st, const Consts<C>& P, int layout, int x, int y, C* f, C* g) {
     using IO = Io<S, C>;
-    const int nx = P.nx, ny = P.ny, N = nx * ny;
+    const int nx = P.nx, ny = P.ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        int slot = i, off = y * nx + x;
+        int slot = i, xs = x, ys = y;
         if (layout != 0) {
             slot = layout == 1 ? kOpp[i] : i;
-            off = wrap(y - kEy[i], ny) * nx + wrap(x - kEx[i], nx);
+            xs = wrap(x - kEx[i], nx);
+            ys = wrap(y - kEy[i], ny);
         }
-        f[i] = IO::ld(st + (size_t)slot * N, off, P.ref_f[i]);
-        g[i] = IO::ld(st + (size_t)(9 + slot) * N, off, P.ref_g[i]);
+        f[i] = IO::ld(st + slot_index(slot, xs, ys, nx), 0, P.ref_f[i]);
+        g[i] = IO::ld(st + slot_index(9 + slot, xs, ys, nx), 0, P.ref_g[i]);
     }
 }
 
@@ -874,9 +905,10 @@ k_init(S* __restrict__ st, const double* __restrict__ rho_in, const double* __re
     const int y = k / P.nx, x = k - y * P.nx;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const int o = layout == 2 ? wrap(y - kEy[i], P.ny) * P.nx + wrap(x - kEx[i], P.nx) : k;
-        IO::st(st + (size_t)i * N, o, f[i], P.ref_f[i]);
-        IO::st(st + (size_t)(9 + i) * N, o, g[i], P.ref_g[i]);
+        const int xs = layout == 2 ? wrap(x - kEx[i], P.nx) : x;
+        const int ys = layout == 2 ? wrap(y - kEy[i], P.ny) : y;
+        IO::st(st + slot_index(i, xs, ys, P.nx), 0, f[i], P.ref_f[i]);
+        IO::st(st + slot_index(9 + i, xs, ys, P.nx), 0, g[i], P.ref_g[i]);
     }
 }
 
@@ -997,6 +1029,11 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double* __restric
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+bool generic_addressing() {
+    const char* e = std::getenv("LBM_GENERIC_ADDRESSING");
+    return e && e[0] == '1';
+}
+
 template <typename S, typename C>
 struct Launch {
     static hipError_t init(const void* cv, void* st, const double* r, const double* u, const double* v,
@@ -1029,8 +1066,9 @@ struct Launch {
         const int nblocks = (nitems + wpb - 1) / wpb;
         const S* i = static_cast<const S*>(in);
         S* o = static_cast<S*>(out);
-        // raw buffer addressing needs every plane offset and the drop offset in 32 bits
-        const bool kBuf = (size_t)35 * P.nx * P.ny * sizeof(S) < ((size_t)1 << 32);
+        // raw buffer addressing needs every offset and the drop offset in 32 bits;
+        // LBM_GENERIC_ADDRESSING=1 selects the 64-bit path for any size (for tests)
+        const bool kBuf = (size_t)19 * P.nx * P.ny * sizeof(S) < ((size_t)1 << 32) && !generic_addressing();
         if (kBuf) return step_ab_wpb<true>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
         return step_ab_wpb<false>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
     }

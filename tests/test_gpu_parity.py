@@ -83,6 +83,26 @@ def test_launch_shapes_are_bitwise_identical(cs_model):
                     assert np.array_equal(g[k], ref[k]), (prec, rows, wpb, k)
 
 
+def test_generic_addressing_path_matches_oracle(cs_model, monkeypatch):
+    """Lattices whose state exceeds the 32-bit buffer-offset range take the 64-bit
+    addressing path; LBM_GENERIC_ADDRESSING=1 forces it on a small ragged lattice (two
+    strips of 64 + 6 columns), which must meet the same bars against the oracle.  The
+    two paths are separately compiled, so they agree to rounding, not bitwise."""
+    d = cs_model.d
+    say("case: FP64/FP32 AB 70x45, generic (64-bit) addressing, 60 steps")
+    f = inputs.random_smooth(70, 45, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.4, 0.05 * d.cs, 0.05, seed=22)
+    o, _ = oracle_moments(cs_model, f, 60)
+    for prec, tol in (("f64", TOL64), ("f32", TOL32)):
+        params = {"precision": prec, "rows_per_wave": 16, "waves_per_block": 2}
+        monkeypatch.delenv("LBM_GENERIC_ADDRESSING", raising=False)
+        a, _ = gpu_moments(70, 45, f, 60, params=params)
+        monkeypatch.setenv("LBM_GENERIC_ADDRESSING", "1")
+        b, _ = gpu_moments(70, 45, f, 60, params=params)
+        monkeypatch.delenv("LBM_GENERIC_ADDRESSING")
+        say(f"  {prec}: paths differ by {errors(a, b, d)}")
+        assert_close(b, o, d, tol, f"generic addressing {prec}")
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 64), (64, 1), (2, 2), (3, 5), (62, 3), (63, 2), (124, 7), (1, 1)])
 def test_fp64_edge_shapes(cs_model, nx, ny):
     d = cs_model.d
