@@ -54,7 +54,7 @@ def measured_traffic(tag: str, shape: tuple):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha") != kernel_sha():
         return None
-    if kv.get("launch_shape") != f"{shape[0]}x{shape[1]}":
+    if kv.get("launch_shape") != "x".join(str(v) for v in shape):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -390,6 +390,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--columns-per-lane", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -415,7 +416,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     n = args.n
     params = {"Tr0": 0.75, "precision": args.precision, "scheme": args.scheme,
-              "rows_per_wave": args.rows_per_wave, "waves_per_block": args.waves_per_block}
+              "rows_per_wave": args.rows_per_wave, "waves_per_block": args.waves_per_block,
+              "columns_per_lane": args.columns_per_lane}
     stream = torch.cuda.Stream()
     solver = lbm.Solver(n, n, params=params, stream=stream)
     d = solver.derived()
@@ -471,7 +473,7 @@ def main() -> int:
                         f"K_EOS=0.479820, K_INT=2.294922), T/Tc=0.75, +-0.5% noise seed 1",
             "nx": n, "ny": n, "precision": args.precision, "scheme": args.scheme,
             "bytes_per_node_step": 36 * STORAGE_BYTES[args.precision],
-            "launch_shape": f"{shape[0]} rows/wave x {shape[1]} waves/block",
+            "launch_shape": f"{shape[0]} rows/wave x {shape[1]} waves/block x {shape[2]} columns/lane",
         },
         "roofline": {
             "bound": "hbm",

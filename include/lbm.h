@@ -100,6 +100,9 @@ typedef struct {
     int32_t scheme;       /* LBM_SCHEME_AB or LBM_SCHEME_AA                             */
     int32_t rows_per_wave;/* rows one wavefront marches through per launch; 0 = auto    */
     int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = auto                                 */
+    int32_t columns_per_lane;/* two-buffer kernel: columns per lane, 1 or 2; 0 = auto
+                                (2 for 4- and 2-byte storage with an even nx, else 1);
+                                2 is taken only where allowed                           */
 } lbm_params;
 
 /* Fills *p with the paper's numerical-test parameters (varpi = 1/6, gamma1 = -2,
@@ -168,9 +171,11 @@ int lbm_invariants(lbm_ctx* ctx, double* out, int n_out);
 int lbm_derived(const lbm_ctx* ctx, double* out, int n);
 
 /* Effective launch shape of the fused two-buffer kernel (after resolving the
- * 0 = auto values of lbm_params): rows each wavefront marches through and
- * wavefronts per workgroup.  Host-only; never fails for a valid context. */
-int lbm_launch_shape(const lbm_ctx* ctx, int32_t* rows_per_wave, int32_t* waves_per_block);
+ * 0 = auto values of lbm_params): rows each wavefront marches through,
+ * wavefronts per workgroup and columns per lane (columns_per_lane may be NULL).
+ * Host-only; never fails for a valid context. */
+int lbm_launch_shape(const lbm_ctx* ctx, int32_t* rows_per_wave, int32_t* waves_per_block,
+                     int32_t* columns_per_lane);
 
 /* Number of completed steps since lbm_set_fields(). */
 int lbm_step_count(const lbm_ctx* ctx, int64_t* steps);
@@ -201,7 +206,7 @@ int lbm_maxwell(const lbm_eos* eos, double Tr, double out[4]);
  * single-lattice calls (moments, invariants, save/load, even lbm_step); the
  * batch notices a member stepped alone and re-reads its buffers.  Members must
  * outlive the batch and share one precision and one stream, and each must keep
- * 19 nx ny bytes-per-value below 4 GiB (32-bit buffer offsets). */
+ * (18 ny + 17) nx bytes-per-value below 4 GiB (32-bit buffer offsets). */
 typedef struct lbm_batch lbm_batch;  /* opaque; owned by the library */
 
 /* Work distribution of a batched launch. */

@@ -84,6 +84,8 @@ int check_params(const lbm_params* p) {
     const int w = p->waves_per_block;
     if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8))
         return fail(nullptr, LBM_EINVAL, "waves_per_block must be 0, 1, 2, 4 or 8 (got %d)", w);
+    if (p->columns_per_lane < 0 || p->columns_per_lane > 2)
+        return fail(nullptr, LBM_EINVAL, "columns_per_lane must be 0, 1 or 2 (got %d)", p->columns_per_lane);
     return LBM_OK;
 }
 
@@ -312,6 +314,11 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     c->consts = p->precision == LBM_F64 ? (const void*)&c->c64 : (const void*)&c->c32;
     c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : 128;
     c->shape.waves_per_block = p->waves_per_block > 0 ? p->waves_per_block : 4;
+    {
+        // two columns per lane: 4- and 2-byte storage, even rows, two-buffer scheme
+        const bool pair_ok = p->precision != LBM_F64 && lat->nx % 2 == 0;
+        c->shape.columns_per_lane = (p->columns_per_lane == 1 || !pair_ok) ? 1 : 2;
+    }
     c->host_only = workspace == nullptr;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (!c->host_only) {
@@ -422,8 +429,9 @@ int lbm_derived(const lbm_ctx* c, double* out, int n) {
     return LBM_OK;
 }
 
-int lbm_launch_shape(const lbm_ctx* c, int32_t* rows_per_wave, int32_t* waves_per_block) {
+int lbm_launch_shape(const lbm_ctx* c, int32_t* rows_per_wave, int32_t* waves_per_block, int32_t* columns_per_lane) {
     if (!c || !rows_per_wave || !waves_per_block) return LBM_EINVAL;
+    if (columns_per_lane) *columns_per_lane = c->p.scheme == LBM_SCHEME_AB ? c->shape.columns_per_lane : 1;
     *rows_per_wave = c->shape.rows_per_wave;
     *waves_per_block = c->shape.waves_per_block;
     return LBM_OK;

@@ -83,7 +83,8 @@ int plan(lbm_batch* b) {
     for (size_t i = 0; i < b->m.size(); ++i) {
         const lbm_ctx* c = b->m[i];
         b->starts_host[i] = (int32_t)acc;
-        acc += (int64_t)((c->lat.nx + 63) / 64) * ((c->lat.ny + rows - 1) / rows);
+        const int width = 64 * c->shape.columns_per_lane;  // strip width of the member's kernel form
+        acc += (int64_t)((c->lat.nx + width - 1) / width) * ((c->lat.ny + rows - 1) / rows);
         nodes += (int64_t)c->lat.nx * c->lat.ny;
         if (acc >= ((int64_t)1 << 31)) return bfail(b, LBM_EINVAL, "too many work items for 32-bit indices");
     }
@@ -123,7 +124,8 @@ void fill_desc(const lbm_batch* b, unsigned char* dst) {
         // the next launch has parity b->parity and reads buf[b->parity]
         d.buf[b->parity] = c->buf[c->cur];
         d.buf[b->parity ^ 1] = c->buf[c->cur ^ 1];
-        d.nstrips = (c->lat.nx + 63) / 64;
+        d.cols = c->shape.columns_per_lane;
+        d.nstrips = (c->lat.nx + 64 * d.cols - 1) / (64 * d.cols);
         d.rows = b->shape.rows_per_wave;
         std::memcpy(dst + i * sizeof d, &d, sizeof d);
     }
@@ -297,8 +299,8 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* 
         if (c->p.precision != m0->p.precision)
             return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one precision", i);
         if (c->stream != m0->stream) return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one stream", i);
-        if ((size_t)19 * c->lat.nx * c->lat.ny * lbm_dev::storage_bytes(c->p.precision) >= ((size_t)1 << 32))
-            return bfail(nullptr, LBM_EINVAL, "member %d: %d x %d is too large for a batch (19 nx ny sizeof must stay below 4 GiB)",
+        if (((size_t)18 * c->lat.ny + 17) * c->lat.nx * lbm_dev::storage_bytes(c->p.precision) + 64 >= ((size_t)1 << 32))
+            return bfail(nullptr, LBM_EINVAL, "member %d: %d x %d is too large for a batch (its state must stay below 4 GiB)",
                          i, c->lat.nx, c->lat.ny);
         for (int32_t j = 0; j < i; ++j)
             if (members[j] == c) return bfail(nullptr, LBM_EINVAL, "member %d appears twice", i);

@@ -44,6 +44,7 @@ enum Precision { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 struct LaunchShape {
     int rows_per_wave;     // rows a wavefront marches through
     int waves_per_block;   // independent wavefronts per workgroup
+    int columns_per_lane;  // 0 auto (two where the form allows), 1 or 2
 };
 
 // All launchers enqueue on `stream` and return the hipError_t of the launch.
@@ -77,7 +78,8 @@ struct BatchDesc {
     const void* buf[2];
     int32_t nstrips;
     int32_t rows;
-    int32_t pad_[2];
+    int32_t cols;          // columns per lane of the two-buffer kernel (1 or 2)
+    int32_t pad_;
 };
 
 // Work distribution of a batched launch.

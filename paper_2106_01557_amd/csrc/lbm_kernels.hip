@@ -324,12 +324,13 @@ __device__ inline int wrap_row(int v, int n) {
 // slot offset (s times the bytes of one population row) goes in the scalar offset and
 // the lane's row-block/column byte offset in the vector offset, for the gather the
 // whole offset is per lane.  A lane that must not store, or whose gather slot is
-// unused, gets the vector offset drop = 2^32 - 1 - 17 * row_bytes: for every slot
-// the total offset then lies at or past the record count without leaving 32 bits,
-// so the hardware drops the store (or returns zero) whether or not it counts the
-// scalar offset in its range check.  That needs buffer_bytes + 17 * row_bytes < 2^32
-// (the launcher checks 19 * nx * ny * sizeof(S) < 2^32); larger lattices use 64-bit
-// addresses and branches instead.
+// unused, gets the vector offset drop = (2^32 - 16 - 17 * row_bytes) rounded down to
+// a multiple of 16: for every slot every dword of an access of up to 16 bytes then
+// lies at or past the record count and below 2^32, so the hardware drops the store
+// (or returns zero) whether or not it counts the scalar offset in its range check,
+// and no component offset wraps around.  That needs buffer_bytes + 17 * row_bytes +
+// 32 < 2^32 (checked by fits_32bit); larger lattices use 64-bit addresses and
+// branches instead.
 template <typename S>
 struct Bits;
 template <>
@@ -390,7 +391,7 @@ struct Planes<S, true> {
     __device__ Planes(const void* base, size_t total_bytes, unsigned row_bytes)
         : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)(unsigned)total_bytes, 0x00020000)),
           ps(row_bytes),
-          drop((0xFFFFFFFFu - 17u * row_bytes) & ~(unsigned)(sizeof(S) - 1)) {}
+          drop((0xFFFFFFF0u - 17u * row_bytes) & ~15u) {}
     template <typename C>
     __device__ C ld(int i, unsigned off, C ref) const {
         const S v = Bits<S>::ld(r, off, ps * (unsigned)i);
@@ -730,6 +731,304 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
 }
 
 // ---------------------------------------------------------------------------
+// fused two-buffer step, two columns per lane (128-column strips, even nx)
+// ---------------------------------------------------------------------------
+// Lane L holds the aligned column pair (x0 + 2L, x0 + 2L + 1): every row access is one
+// 8-byte (FP32) or 4-byte (16-bit) load or store per lane, twice the bytes per
+// instruction of the one-column form, and the pull shift needs one DPP per slot and
+// pair: for e_x = +1 the first column takes the west lane's second value, for e_x = -1
+// the second column takes the east lane's first value.  The gather slots, the halo
+// columns and the order of every sum are those of the one-column form, so the result
+// is bitwise the same.  Loads run one row ahead: f of row y+2 and g of row y+1 are in
+// flight while row y collides.
+template <typename S>
+struct Bits2;
+template <>
+struct Bits2<float> {
+    using V2 = unsigned __attribute__((ext_vector_type(2)));
+    __device__ static void ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s, float& a, float& b) {
+        // keep the builtin's own vector type: converting it to an ext_vector on
+        // assignment compiles to a one-dword load whose value fills both elements
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0);
+        a = __builtin_bit_cast(float, (unsigned)t[0]);
+        b = __builtin_bit_cast(float, (unsigned)t[1]);
+    }
+    __device__ static void st(float a, float b, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        V2 t;
+        t.x = __builtin_bit_cast(unsigned, a);
+        t.y = __builtin_bit_cast(unsigned, b);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, v, s, 0);
+    }
+};
+template <typename H>
+struct Bits2Half {
+    __device__ static void ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s, H& a, H& b) {
+        const unsigned t = __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+        a = __builtin_bit_cast(H, (unsigned short)(t & 0xffffu));
+        b = __builtin_bit_cast(H, (unsigned short)(t >> 16));
+    }
+    __device__ static void st(H a, H b, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        const unsigned t = (unsigned)__builtin_bit_cast(unsigned short, a) |
+                           ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(t, r, v, s, 0);
+    }
+};
+template <>
+struct Bits2<__half> : Bits2Half<__half> {};
+template <>
+struct Bits2<__hip_bfloat16> : Bits2Half<__hip_bfloat16> {};
+
+// pair access on top of Planes: slot i, byte offset of the pair's first column
+template <typename S, typename C>
+__device__ inline void ld2(const Planes<S, true>& B, int i, unsigned off, C ref, C& a, C& b) {
+    S u, v;
+    Bits2<S>::ld(B.r, off, B.ps * (unsigned)i, u, v);
+    a = Io<S, C>::ld(&u, 0, ref);
+    b = Io<S, C>::ld(&v, 0, ref);
+}
+template <typename S, typename C>
+__device__ inline void ld2(const Planes<S, false>& B, int i, size_t off, C ref, C& a, C& b) {
+    const S* q = reinterpret_cast<const S*>(B.base + B.ps * i + off);
+    a = Io<S, C>::ld(q, 0, ref);
+    b = Io<S, C>::ld(q, 1, ref);
+}
+template <typename S, typename C>
+__device__ inline void st2(const Planes<S, true>& B, int i, unsigned off, C a, C b, C ref, bool valid) {
+    S u, v;
+    Io<S, C>::st(&u, 0, a, ref);
+    Io<S, C>::st(&v, 0, b, ref);
+    Bits2<S>::st(u, v, B.r, valid ? off : B.drop, B.ps * (unsigned)i);
+}
+template <typename S, typename C>
+__device__ inline void st2(const Planes<S, false>& B, int i, size_t off, C a, C b, C ref, bool valid) {
+    if (!valid) return;
+    S* q = reinterpret_cast<S*>(B.base + B.ps * i + off);
+    Io<S, C>::st(q, 0, a, ref);
+    Io<S, C>::st(q, 1, b, ref);
+}
+
+// Raw loads of one target row for both columns of the lane, and the gather.
+template <typename S, typename C, bool kBuf>
+__device__ inline void load_target_row2(const Planes<S, kBuf>& B, int first, const Strip& G,
+                                        typename OffT<kBuf>::type up, typename OffT<kBuf>::type mid,
+                                        typename OffT<kBuf>::type dn, bool is_f, const C* ref, C* ra, C* rb, C& gth) {
+    using Off = typename OffT<kBuf>::type;
+    const unsigned xo = G.xc * G.esz;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Off r = kEy[i] < 0 ? up : (kEy[i] > 0 ? dn : mid);
+        ld2<S, C>(B, first + i, r + xo, ref[i], ra[i], rb[i]);
+    }
+    const unsigned plane = is_f ? G.fplane : G.gplane;
+    const unsigned col = is_f ? G.fcol : G.gcol;
+    const int dy = is_f ? G.fdy : G.gdy;
+    const bool on = is_f ? G.fon : G.gon;
+    const Off r = dy > 0 ? up : (dy < 0 ? dn : mid);
+    gth = B.template gather<C>(first + plane, r + col * G.esz, on, ref[plane]);
+}
+
+template <typename C>
+struct Dens2 {
+    C a, b, L, R;  // the lane's two densities and the two halo columns' densities (uniform)
+};
+
+template <typename C>
+__device__ inline void finish_f2(const Strip& G, const C* ra, const C* rb, C gth, C* fa, C* fb, Dens2<C>& d) {
+    const int lane = threadIdx.x & 63;
+    C w1 = dpp_from_west(rb[1]), w5 = dpp_from_west(rb[5]), w8 = dpp_from_west(rb[8]);
+    C e3 = dpp_from_east(ra[3]), e6 = dpp_from_east(ra[6]), e7 = dpp_from_east(ra[7]);
+    pin(w1), pin(w5), pin(w8), pin(e3), pin(e6), pin(e7);
+    const C g6 = lane_value(gth, 6), g7 = lane_value(gth, 7), g8 = lane_value(gth, 8);
+    const C g15 = lane_value(gth, 15), g16 = lane_value(gth, 16), g17 = lane_value(gth, 17);
+    const bool first = lane == 0, lastl = lane == G.last;
+    fa[0] = ra[0], fa[2] = ra[2], fa[4] = ra[4];
+    fb[0] = rb[0], fb[2] = rb[2], fb[4] = rb[4];
+    fa[1] = first ? g6 : w1, fb[1] = ra[1];
+    fa[5] = first ? g7 : w5, fb[5] = ra[5];
+    fa[8] = first ? g8 : w8, fb[8] = ra[8];
+    fa[3] = rb[3], fb[3] = lastl ? g15 : e3;
+    fa[6] = rb[6], fb[6] = lastl ? g16 : e6;
+    fa[7] = rb[7], fb[7] = lastl ? g17 : e7;
+    d.a = sum9(fa);
+    d.b = sum9(fb);
+    C h[9];
+    h[0] = lane_value(gth, 0);
+    h[2] = lane_value(gth, 1);
+    h[4] = lane_value(gth, 2);
+    h[1] = lane_value(gth, 3);
+    h[5] = lane_value(gth, 4);
+    h[8] = lane_value(gth, 5);
+    h[3] = lane_value(ra[3], 0);
+    h[6] = lane_value(ra[6], 0);
+    h[7] = lane_value(ra[7], 0);
+    d.L = sum9(h);
+    h[0] = lane_value(gth, 9);
+    h[2] = lane_value(gth, 10);
+    h[4] = lane_value(gth, 11);
+    h[3] = lane_value(gth, 12);
+    h[6] = lane_value(gth, 13);
+    h[7] = lane_value(gth, 14);
+    h[1] = lane_value(rb[1], G.last);
+    h[5] = lane_value(rb[5], G.last);
+    h[8] = lane_value(rb[8], G.last);
+    d.R = sum9(h);
+}
+
+template <typename C>
+__device__ inline void finish_g2(const Strip& G, const C* ra, const C* rb, C gth, C* ga, C* gb) {
+    const int lane = threadIdx.x & 63;
+    C w1 = dpp_from_west(rb[1]), w5 = dpp_from_west(rb[5]), w8 = dpp_from_west(rb[8]);
+    C e3 = dpp_from_east(ra[3]), e6 = dpp_from_east(ra[6]), e7 = dpp_from_east(ra[7]);
+    pin(w1), pin(w5), pin(w8), pin(e3), pin(e6), pin(e7);
+    const C g0 = lane_value(gth, 0), g1 = lane_value(gth, 1), g2 = lane_value(gth, 2);
+    const C g3 = lane_value(gth, 3), g4 = lane_value(gth, 4), g5 = lane_value(gth, 5);
+    const bool first = lane == 0, lastl = lane == G.last;
+    ga[0] = ra[0], ga[2] = ra[2], ga[4] = ra[4];
+    gb[0] = rb[0], gb[2] = rb[2], gb[4] = rb[4];
+    ga[1] = first ? g0 : w1, gb[1] = ra[1];
+    ga[5] = first ? g1 : w5, gb[5] = ra[5];
+    ga[8] = first ? g2 : w8, gb[8] = ra[8];
+    ga[3] = rb[3], gb[3] = lastl ? g3 : e3;
+    ga[6] = rb[6], gb[6] = lastl ? g4 : e6;
+    ga[7] = rb[7], gb[7] = lastl ? g5 : e7;
+}
+
+// One row: issue the raw loads of f(y+2) and g(y+1) (kLoad), collide row y for both
+// columns, store, then rotate (kRotate): densities, f(y+1) -> f(y), finish the new
+// loads.  R[0..2]: byte offsets of the row blocks of rows y+1 .. y+3; yo: row y.
+template <bool kLoad, bool kRotate, typename S, typename C, bool kBuf>
+__device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
+                                        const Strip& G, typename OffT<kBuf>::type yo,
+                                        const typename OffT<kBuf>::type (&R)[3], C (&fAa)[9], C (&fAb)[9],
+                                        C (&fBa)[9], C (&fBb)[9], C (&gAa)[9], C (&gAb)[9], Dens2<C>& dm,
+                                        Dens2<C>& dc, Dens2<C>& dp) {
+    const int lane = threadIdx.x & 63;
+    C rfa[9], rfb[9], hf, rga[9], rgb[9], hg;
+    if (kLoad) {
+        load_target_row2<S, C, kBuf>(in, 0, G, R[2], R[1], R[0], true, P.ref_f, rfa, rfb, hf);
+        load_target_row2<S, C, kBuf>(in, 9, G, R[1], R[0], yo, false, P.ref_g, rga, rgb, hg);
+    }
+    C wc = dpp_from_west(dc.b), ec = dpp_from_east(dc.a);
+    C wm = dpp_from_west(dm.b), em = dpp_from_east(dm.a);
+    C wp = dpp_from_west(dp.b), ep = dpp_from_east(dp.a);
+    pin(wc), pin(ec), pin(wm), pin(em), pin(wp), pin(ep);
+    const bool first = lane == 0, lastl = lane == G.last;
+    C sxa, sya, sxb, syb;
+    // column a: west neighbour from the west lane (or the halo), east is column b
+    stencil(dc.b, dp.a, first ? dc.L : wc, dm.a, dp.b, first ? dp.L : wp, first ? dm.L : wm, dm.b, sxa, sya);
+    // column b: west is column a, east neighbour from the east lane (or the halo)
+    stencil(lastl ? dc.R : ec, dp.b, dc.a, dm.b, lastl ? dp.R : ep, dp.a, dm.a, lastl ? dm.R : em, sxb, syb);
+    const typename OffT<kBuf>::type o = yo + G.xc * G.esz;
+    {
+        C foa[9], goa[9], fob[9], gob[9];
+        collide(P, fAa, gAa, dc.a, sxa, sya, foa, goa);
+        collide(P, fAb, gAb, dc.b, sxb, syb, fob, gob);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            st2<S, C>(out, i, o, foa[i], fob[i], P.ref_f[i], G.owner);
+            st2<S, C>(out, 9 + i, o, goa[i], gob[i], P.ref_g[i], G.owner);
+        }
+    }
+    if (kRotate) {
+        dm = dc;
+        dc = dp;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            fAa[i] = fBa[i];
+            fAb[i] = fBb[i];
+        }
+        finish_f2(G, rfa, rfb, hf, fBa, fBb, dp);
+        finish_g2(G, rga, rgb, hg, gAa, gAb);
+    }
+}
+
+// One work item of the two-column form: a strip of up to 128 columns (nx even).
+template <typename S, typename C, bool kBuf>
+__device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restrict__ out, const Consts<C>& P,
+                                          const int w, const int nstrips, const int rows) {
+    using Off = typename OffT<kBuf>::type;
+    const int lane = threadIdx.x & 63;
+    const int strip = w % nstrips, chunk = w / nstrips;
+    const int nx = P.nx, ny = P.ny;
+    const int x0 = strip * 128;
+    const int owned = min(128, nx - x0);  // even
+    Strip G;
+    G.nx = nx;
+    G.ny = ny;
+    G.rowb = (unsigned)nx * sizeof(S);
+    G.esz = sizeof(S);
+    G.owner = 2 * lane < owned;
+    G.xc = (unsigned)(G.owner ? x0 + 2 * lane : nx - 2);  // first column of the lane's pair
+    G.last = __builtin_amdgcn_readfirstlane(owned / 2 - 1);
+    {
+        const unsigned l1 = __builtin_amdgcn_readfirstlane(wrap_row(x0 - 1, nx));
+        const unsigned l2 = __builtin_amdgcn_readfirstlane(wrap_row(x0 - 2, nx));
+        const unsigned r1 = __builtin_amdgcn_readfirstlane(wrap_row(x0 + owned, nx));
+        const unsigned r2 = __builtin_amdgcn_readfirstlane(wrap_row(x0 + owned + 1, nx));
+        const int k = lane % 3, grp = lane / 3;
+        const int axis0 = k == 0 ? 0 : (k == 1 ? 2 : 4);
+        const int east = k == 0 ? 1 : (k == 1 ? 5 : 8);
+        const int west = k == 0 ? 3 : (k == 1 ? 6 : 7);
+        const int pf = (grp == 0 || grp == 3) ? axis0 : ((grp == 1 || grp == 2) ? east : west);
+        const unsigned cf = grp == 1 ? l2 : (grp == 4 ? r2 : ((grp == 0 || grp == 2) ? l1 : r1));
+        G.fon = lane < 18;
+        G.fplane = (unsigned)pf;
+        G.fcol = cf;
+        G.fdy = pf == 2 || pf == 5 || pf == 6 ? -1 : (pf == 4 || pf == 7 || pf == 8 ? 1 : 0);
+        const int pg = grp == 0 ? east : west;
+        G.gon = lane < 6;
+        G.gplane = (unsigned)pg;
+        G.gcol = grp == 0 ? l1 : r1;
+        G.gdy = pg == 5 || pg == 6 ? -1 : (pg == 7 || pg == 8 ? 1 : 0);
+    }
+    const size_t total = (size_t)18 * nx * ny * sizeof(S);
+    const Planes<S, kBuf> Pin(in, total, G.rowb);
+    const Planes<S, kBuf> Pout(out, total, G.rowb);
+    const int y0 = chunk * rows, y1 = min(ny, y0 + rows);
+    const Off blk = (Off)18 * G.rowb;
+    const Off tot = (Off)total;
+    Off ro[5];  // row blocks of rows y0-2 .. y0+2
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int yy = __builtin_amdgcn_readfirstlane(wrap_row(y0 - 2 + k, ny));
+        ro[k] = (Off)yy * blk;
+    }
+    C fAa[9], fAb[9], fBa[9], fBb[9], gAa[9], gAb[9];
+    Dens2<C> dm, dc, dp;
+    {
+        C ra[9], rb[9], h, ta[9], tb[9];
+        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[2], ro[1], ro[0], true, P.ref_f, ra, rb, h);  // f(y0-1)
+        finish_f2(G, ra, rb, h, ta, tb, dm);
+        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[3], ro[2], ro[1], true, P.ref_f, ra, rb, h);  // f(y0)
+        finish_f2(G, ra, rb, h, fAa, fAb, dc);
+        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[4], ro[3], ro[2], true, P.ref_f, ra, rb, h);  // f(y0+1)
+        finish_f2(G, ra, rb, h, fBa, fBb, dp);
+        load_target_row2<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, ra, rb, h);  // g(y0)
+        finish_g2(G, ra, rb, h, gAa, gAb);
+    }
+    Off R[3] = {ro[3], ro[4], next_row<Off>(ro[4], blk, tot)};  // rows y+1 .. y+3
+    Off yo = ro[2];
+    int y = y0;
+    for (; y < y1 - 1; ++y) {
+        ab_row2<true, true, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, gAa, gAb, dm, dc, dp);
+        yo = R[0];
+        R[0] = R[1];
+        R[1] = R[2];
+        R[2] = next_row<Off>(R[2], blk, tot);
+    }
+    ab_row2<false, false, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, gAa, gAb, dm, dc, dp);
+}
+
+template <typename S, typename C, int WPB, bool kBuf>
+__global__ void __launch_bounds__(64 * WPB)
+k_step_ab2(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, const int nstrips, const int rows,
+           const int nitems) {
+    const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
+    if (w >= nitems) return;
+    ab_strip2<S, C, kBuf>(in, out, P, w, nstrips, rows);
+}
+
+// ---------------------------------------------------------------------------
 // batched form: many independent lattices, one launch per step
 // ---------------------------------------------------------------------------
 // The lattice owning global item w is found by a binary search over `starts` (uniform,
@@ -738,7 +1037,8 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
 // Queue mode: a persistent grid; the item range is cut into `groups` contiguous
 // ranges, one per XCD (a block's XCD is its index modulo 8), and the wavefronts of
 // an XCD take items of its range from an atomic counter until it is exhausted.
-// Every lattice must satisfy the 32-bit buffer-offset bound (19 nx ny sizeof(S) < 2^32).
+// Every lattice must satisfy the 32-bit buffer-offset bound ((18 ny + 17) nx sizeof(S)
+// + 64 < 2^32, checked on the host).
 template <typename S, typename C>
 __device__ __forceinline__ void batch_item(const BatchDesc<C>* __restrict__ desc, const int32_t* __restrict__ starts,
                                            const int nlat, const int w, const int parity) {
@@ -752,7 +1052,14 @@ __device__ __forceinline__ void batch_item(const BatchDesc<C>* __restrict__ desc
     const BatchDesc<C>* D = desc + b;
     const S* in = static_cast<const S*>(D->buf[parity]);
     S* out = const_cast<S*>(static_cast<const S*>(D->buf[parity ^ 1]));
-    ab_strip<S, C, true>(in, out, D->P, __builtin_amdgcn_readfirstlane(w - starts[b]), D->nstrips, D->rows);
+    const int item = __builtin_amdgcn_readfirstlane(w - starts[b]);
+    if constexpr (sizeof(S) <= 4) {
+        if (D->cols == 2) {
+            ab_strip2<S, C, true>(in, out, D->P, item, D->nstrips, D->rows);
+            return;
+        }
+    }
+    ab_strip<S, C, true>(in, out, D->P, item, D->nstrips, D->rows);
 }
 
 template <typename S, typename C, int WPB, bool kQueue>
@@ -1034,8 +1341,16 @@ bool generic_addressing() {
     return e && e[0] == '1';
 }
 
+// The buffer-instruction path's offset bound (see Planes): every offset, including
+// the drop offset plus a 16-byte access, stays below 2^32.
+bool fits_32bit(int nx, int ny, size_t esz) {
+    return ((size_t)18 * ny + 17) * (size_t)nx * esz + 64 < ((size_t)1 << 32);
+}
+
 template <typename S, typename C>
 struct Launch {
+    // the two-column form: 4- and 2-byte storage and an even row length
+    static bool pair_columns(int nx) { return sizeof(S) <= 4 && nx % 2 == 0; }
     static hipError_t init(const void* cv, void* st, const double* r, const double* u, const double* v,
                            const double* T, int layout, hipStream_t s) {
         const Consts<C>& P = *static_cast<const Consts<C>*>(cv);
@@ -1056,8 +1371,34 @@ struct Launch {
         }
         return hipGetLastError();
     }
+    template <bool kBuf>
+    static hipError_t step_ab2_wpb(const S* i, S* o, const Consts<C>& P, int nstrips, int rows, int nitems, int wpb,
+                                   int nblocks, hipStream_t s) {
+        switch (wpb) {
+            case 1: hipLaunchKernelGGL((k_step_ab2<S, C, 1, kBuf>), dim3(nblocks), dim3(64), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 2: hipLaunchKernelGGL((k_step_ab2<S, C, 2, kBuf>), dim3(nblocks), dim3(128), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 4: hipLaunchKernelGGL((k_step_ab2<S, C, 4, kBuf>), dim3(nblocks), dim3(256), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 8: hipLaunchKernelGGL((k_step_ab2<S, C, 8, kBuf>), dim3(nblocks), dim3(512), 0, s, i, o, P, nstrips, rows, nitems); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     static hipError_t step_ab(const void* cv, const void* in, void* out, LaunchShape sh, hipStream_t s) {
         const Consts<C>& P = *static_cast<const Consts<C>*>(cv);
+        if constexpr (sizeof(S) <= 4) {
+            if (pair_columns(P.nx) && sh.columns_per_lane != 1) {
+                const int nstrips = (P.nx + 127) / 128;
+                const int rows = sh.rows_per_wave;
+                const int nitems = nstrips * ((P.ny + rows - 1) / rows);
+                const int wpb = sh.waves_per_block;
+                const int nblocks = (nitems + wpb - 1) / wpb;
+                const bool kBuf = fits_32bit(P.nx, P.ny, sizeof(S)) && !generic_addressing();
+                const S* i = static_cast<const S*>(in);
+                S* o = static_cast<S*>(out);
+                if (kBuf) return step_ab2_wpb<true>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
+                return step_ab2_wpb<false>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
+            }
+        }
         const int nstrips = (P.nx + 63) / 64;
         const int rows = sh.rows_per_wave;
         const int nchunks = (P.ny + rows - 1) / rows;
@@ -1068,7 +1409,7 @@ struct Launch {
         S* o = static_cast<S*>(out);
         // raw buffer addressing needs every offset and the drop offset in 32 bits;
         // LBM_GENERIC_ADDRESSING=1 selects the 64-bit path for any size (for tests)
-        const bool kBuf = (size_t)19 * P.nx * P.ny * sizeof(S) < ((size_t)1 << 32) && !generic_addressing();
+        const bool kBuf = fits_32bit(P.nx, P.ny, sizeof(S)) && !generic_addressing();
         if (kBuf) return step_ab_wpb<true>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
         return step_ab_wpb<false>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
     }

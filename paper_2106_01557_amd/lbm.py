@@ -43,7 +43,7 @@ class _Eos(ctypes.Structure):
 _PARAM_DOUBLES = ["Tr0", "K_int", "varpi", "gamma1", "gamma2", "tau_p", "s_eps", "sigma_e", "sigma_eps",
                   "sigma_q", "sigma_p", "tau_j_v", "lambda_ratio", "cv", "ste", "dTr_ste", "C_ref", "accel_x",
                   "accel_y", "cs_override", "rho_ref", "T_ref"]
-_PARAM_INTS = ["precision", "scheme", "rows_per_wave", "waves_per_block"]
+_PARAM_INTS = ["precision", "scheme", "rows_per_wave", "waves_per_block", "columns_per_lane"]
 
 
 class _Params(ctypes.Structure):
@@ -79,7 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_moments.argtypes = [V, V, V, V, V]
     lib.lbm_invariants.argtypes = [V, P(D), I]
     lib.lbm_derived.argtypes = [V, P(D), I]
-    lib.lbm_launch_shape.argtypes = [V, P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.lbm_launch_shape.argtypes = [V, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]
     lib.lbm_step_count.argtypes = [V, P(ctypes.c_int64)]
     lib.lbm_state_bytes.argtypes = [V, P(S)]
     lib.lbm_save_state.argtypes = [V, V, P(ctypes.c_int64)]
@@ -289,9 +289,10 @@ class Solver:
         return dict(zip(DERIVED_NAMES, list(buf)))
 
     def launch_shape(self) -> tuple:
-        r, w = ctypes.c_int32(), ctypes.c_int32()
-        _check(_lib.lbm_launch_shape(self._ctx, ctypes.byref(r), ctypes.byref(w)))
-        return r.value, w.value
+        """(rows per wavefront, wavefronts per workgroup, columns per lane)."""
+        r, w, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.lbm_launch_shape(self._ctx, ctypes.byref(r), ctypes.byref(w), ctypes.byref(c)))
+        return r.value, w.value, c.value
 
     @property
     def steps(self) -> int:

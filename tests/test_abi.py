@@ -79,7 +79,7 @@ def test_host_constants_match_oracle(lbm, eos_kind, overrides):
     ({"Tr0": 1.0}, "Tr0"), ({"Tr0": -0.1}, "Tr0"), ({"K_int": 0.0}, "K_int"), ({"varpi": 0.4}, "varpi"),
     ({"tau_p": 0.0}, "tau_p"), ({"sigma_q": 2.0}, "sigma_q"), ({"s_eps": 0.0}, "s_eps"),
     ({"tau_j_v": -1.0}, "tau_j_v"), ({"lambda_ratio": 0.0}, "lambda_ratio"), ({"precision": 7}, "precision"),
-    ({"scheme": 3}, "scheme"), ({"waves_per_block": 3}, "waves_per_block"), ({"cs_override": -1.0}, "cs_override"),
+    ({"scheme": 3}, "scheme"), ({"waves_per_block": 3}, "waves_per_block"), ({"columns_per_lane": 3}, "columns_per_lane"), ({"cs_override": -1.0}, "cs_override"),
     ({"cv": 0.0, "ste": 0.0}, "cv"), ({"accel_x": float("nan")}, "acceleration"),
 ])
 def test_invalid_parameters_are_rejected_before_any_device_call(lbm, bad, msg):

@@ -83,6 +83,27 @@ def test_launch_shapes_are_bitwise_identical(cs_model):
                     assert np.array_equal(g[k], ref[k]), (prec, rows, wpb, k)
 
 
+@pytest.mark.parametrize("nx,ny", [(70, 45), (130, 67), (200, 96), (2, 5), (256, 3), (4, 130)])
+def test_two_column_form_is_bitwise_identical(cs_model, nx, ny):
+    """The two-columns-per-lane kernel (even nx, 4- and 2-byte storage) against the
+    one-column kernel: same gather slots, halo columns and summation order, so the
+    states agree bitwise.  Covers a strip whose only lane is both first and last
+    (130 = 128 + 2), nx = 2 (both halo columns wrap onto the strip itself) and
+    ragged row chunks."""
+    d = cs_model.d
+    say(f"case: two-column vs one-column form, {nx}x{ny}, f32/f16/bf16, 25 steps")
+    f = inputs.random_smooth(nx, ny, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.4, 0.04 * d.cs, 0.04, seed=nx + ny)
+    for prec in ("f32", "f16", "bf16"):
+        out = []
+        for cols in (1, 2):
+            s = gpu_solver(nx, ny, params={"precision": prec, "columns_per_lane": cols, "rows_per_wave": 16})
+            assert s.launch_shape()[2] == cols
+            g, _ = gpu_moments(nx, ny, f, 25, solver=s)
+            out.append(g)
+        for k in out[0]:
+            assert np.array_equal(out[0][k], out[1][k]), (prec, k, float(np.abs(out[0][k] - out[1][k]).max()))
+
+
 def test_generic_addressing_path_matches_oracle(cs_model, monkeypatch):
     """Lattices whose state exceeds the 32-bit buffer-offset range take the 64-bit
     addressing path; LBM_GENERIC_ADDRESSING=1 forces it on a small ragged lattice (two
