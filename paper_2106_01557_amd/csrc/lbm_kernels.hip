@@ -739,8 +739,9 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
 // pair: for e_x = +1 the first column takes the west lane's second value, for e_x = -1
 // the second column takes the east lane's first value.  The gather slots, the halo
 // columns and the order of every sum are those of the one-column form, so the result
-// is bitwise the same.  Loads run one row ahead: f of row y+2 and g of row y+1 are in
-// flight while row y collides.
+// is bitwise the same.  Loads run two rows ahead: f of row y+3 and g of row y+2 are
+// issued while row y collides (each row's arithmetic alone does not cover the memory
+// latency at one or two wavefronts per SIMD).
 template <typename S>
 struct Bits2;
 template <>
@@ -893,20 +894,23 @@ __device__ inline void finish_g2(const Strip& G, const C* ra, const C* rb, C gth
     ga[7] = rb[7], gb[7] = lastl ? g5 : e7;
 }
 
-// One row: issue the raw loads of f(y+2) and g(y+1) (kLoad), collide row y for both
-// columns, store, then rotate (kRotate): densities, f(y+1) -> f(y), finish the new
-// loads.  R[0..2]: byte offsets of the row blocks of rows y+1 .. y+3; yo: row y.
-template <bool kLoad, bool kRotate, typename S, typename C, bool kBuf>
+// One row of the two-column march.  kStage = 2: issue the raw loads of f(y+3) and
+// g(y+2), collide row y for both columns, store, then rotate (densities, f(y+1) ->
+// f(y), finish the raw loads of f(y+2) and g(y+1) issued one row earlier); kStage = 1:
+// the same without new loads; kStage = 0: collide and store only (last row).
+// R[0..3]: byte offsets of the row blocks of rows y+1 .. y+4; yo: row y.
+template <int kStage, typename S, typename C, bool kBuf>
 __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
                                         const Strip& G, typename OffT<kBuf>::type yo,
-                                        const typename OffT<kBuf>::type (&R)[3], C (&fAa)[9], C (&fAb)[9],
-                                        C (&fBa)[9], C (&fBb)[9], C (&gAa)[9], C (&gAb)[9], Dens2<C>& dm,
-                                        Dens2<C>& dc, Dens2<C>& dp) {
+                                        const typename OffT<kBuf>::type (&R)[4], C (&fAa)[9], C (&fAb)[9],
+                                        C (&fBa)[9], C (&fBb)[9], C (&rCa)[9], C (&rCb)[9], C& hC, C (&gAa)[9],
+                                        C (&gAb)[9], C (&rGa)[9], C (&rGb)[9], C& hG, Dens2<C>& dm, Dens2<C>& dc,
+                                        Dens2<C>& dp) {
     const int lane = threadIdx.x & 63;
-    C rfa[9], rfb[9], hf, rga[9], rgb[9], hg;
-    if (kLoad) {
-        load_target_row2<S, C, kBuf>(in, 0, G, R[2], R[1], R[0], true, P.ref_f, rfa, rfb, hf);
-        load_target_row2<S, C, kBuf>(in, 9, G, R[1], R[0], yo, false, P.ref_g, rga, rgb, hg);
+    C rDa[9], rDb[9], hD, rHa[9], rHb[9], hH;
+    if (kStage == 2) {
+        load_target_row2<S, C, kBuf>(in, 9, G, R[2], R[1], R[0], false, P.ref_g, rHa, rHb, hH);  // g(y+2)
+        load_target_row2<S, C, kBuf>(in, 0, G, R[3], R[2], R[1], true, P.ref_f, rDa, rDb, hD);   // f(y+3)
     }
     C wc = dpp_from_west(dc.b), ec = dpp_from_east(dc.a);
     C wm = dpp_from_west(dm.b), em = dpp_from_east(dm.a);
@@ -929,7 +933,7 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
             st2<S, C>(out, 9 + i, o, goa[i], gob[i], P.ref_g[i], G.owner);
         }
     }
-    if (kRotate) {
+    if (kStage >= 1) {
         dm = dc;
         dc = dp;
 #pragma unroll
@@ -937,8 +941,19 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
             fAa[i] = fBa[i];
             fAb[i] = fBb[i];
         }
-        finish_f2(G, rfa, rfb, hf, fBa, fBb, dp);
-        finish_g2(G, rga, rgb, hg, gAa, gAb);
+        finish_f2(G, rCa, rCb, hC, fBa, fBb, dp);
+        finish_g2(G, rGa, rGb, hG, gAa, gAb);
+        if (kStage == 2) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                rCa[i] = rDa[i];
+                rCb[i] = rDb[i];
+                rGa[i] = rHa[i];
+                rGb[i] = rHb[i];
+            }
+            hC = hD;
+            hG = hH;
+        }
     }
 }
 
@@ -987,13 +1002,13 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
     const int y0 = chunk * rows, y1 = min(ny, y0 + rows);
     const Off blk = (Off)18 * G.rowb;
     const Off tot = (Off)total;
-    Off ro[5];  // row blocks of rows y0-2 .. y0+2
+    Off ro[6];  // row blocks of rows y0-2 .. y0+3
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
         const int yy = __builtin_amdgcn_readfirstlane(wrap_row(y0 - 2 + k, ny));
         ro[k] = (Off)yy * blk;
     }
-    C fAa[9], fAb[9], fBa[9], fBb[9], gAa[9], gAb[9];
+    C fAa[9], fAb[9], fBa[9], fBb[9], gAa[9], gAb[9], rCa[9], rCb[9], hC, rGa[9], rGb[9], hG;
     Dens2<C> dm, dc, dp;
     {
         C ra[9], rb[9], h, ta[9], tb[9];
@@ -1006,17 +1021,31 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
         load_target_row2<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, ra, rb, h);  // g(y0)
         finish_g2(G, ra, rb, h, gAa, gAb);
     }
-    Off R[3] = {ro[3], ro[4], next_row<Off>(ro[4], blk, tot)};  // rows y+1 .. y+3
+    load_target_row2<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rGa, rGb, hG);  // g(y0+1)
+    load_target_row2<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rCa, rCb, hC);   // f(y0+2)
+    // let the prologue's loads land before the loop (as in the one-column form)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(rGa[i]), "v"(rGb[i]), "v"(rCa[i]), "v"(rCb[i]));
+    asm volatile("" ::"v"(hG), "v"(hC));
+    Off R[4] = {ro[3], ro[4], ro[5], next_row<Off>(ro[5], blk, tot)};  // rows y+1 .. y+4
     Off yo = ro[2];
     int y = y0;
-    for (; y < y1 - 1; ++y) {
-        ab_row2<true, true, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, gAa, gAb, dm, dc, dp);
+    for (; y < y1 - 2; ++y) {
+        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, rCa, rCb, hC, gAa, gAb, rGa, rGb, hG, dm,
+                               dc, dp);
         yo = R[0];
         R[0] = R[1];
         R[1] = R[2];
-        R[2] = next_row<Off>(R[2], blk, tot);
+        R[2] = R[3];
+        R[3] = next_row<Off>(R[3], blk, tot);
     }
-    ab_row2<false, false, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, gAa, gAb, dm, dc, dp);
+    if (y < y1 - 1) {
+        ab_row2<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, rCa, rCb, hC, gAa, gAb, rGa, rGb, hG, dm,
+                               dc, dp);
+        yo = R[0];
+    }
+    ab_row2<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, rCa, rCb, hC, gAa, gAb, rGa, rGb, hG, dm, dc,
+                           dp);
 }
 
 template <typename S, typename C, int WPB, bool kBuf>
