@@ -98,7 +98,8 @@ typedef struct {
                              <= 0: rho = (rho_v + rho_l)/2 and T = T0                   */
     int32_t precision;    /* LBM_F64, LBM_F32, LBM_F16, LBM_BF16                        */
     int32_t scheme;       /* LBM_SCHEME_AB or LBM_SCHEME_AA                             */
-    int32_t rows_per_wave;/* rows one wavefront marches through per launch; 0 = auto    */
+    int32_t rows_per_wave;/* rows one wavefront marches through per launch; 0 = auto
+                             (128; 64 for LBM_F16/LBM_BF16 storage)                   */
     int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = auto                                 */
     int32_t columns_per_lane;/* two-buffer kernel: columns per lane, 1 or 2; 0 = auto
                                 (2 for 4- and 2-byte storage with an even nx, else 1);

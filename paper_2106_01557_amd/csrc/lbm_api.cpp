@@ -312,7 +312,10 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     fill_consts(c, &c->c64);
     fill_consts(c, &c->c32);
     c->consts = p->precision == LBM_F64 ? (const void*)&c->c64 : (const void*)&c->c32;
-    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : 128;
+    // 16-bit storage halves the bytes per node but not the arithmetic, so it wants two
+    // resident wavefronts per SIMD (shorter strips, twice the work items) to hide latency
+    const bool half = p->precision == LBM_F16 || p->precision == LBM_BF16;
+    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : (half ? 64 : 128);
     c->shape.waves_per_block = p->waves_per_block > 0 ? p->waves_per_block : 4;
     {
         // two columns per lane: 4- and 2-byte storage, even rows, two-buffer scheme

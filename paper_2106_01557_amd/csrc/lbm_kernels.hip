@@ -331,6 +331,12 @@ __device__ inline int wrap_row(int v, int n) {
 // and no component offset wraps around.  That needs buffer_bytes + 17 * row_bytes +
 // 32 < 2^32 (checked by fits_32bit); larger lattices use 64-bit addresses and
 // branches instead.
+//
+// Stores carry the non-temporal cache policy: a step writes every byte of the output
+// state once and no kernel of the same step reads it again, so the stores should not
+// displace the input lines that the neighbouring strips' halo gathers still reuse.
+constexpr int kStreamStore = 2;  // cache-policy operand of the buffer stores: nt
+
 template <typename S>
 struct Bits;
 template <>
@@ -339,7 +345,7 @@ struct Bits<float> {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
     }
     __device__ static void st(float x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, kStreamStore);
     }
 };
 template <>
@@ -349,7 +355,7 @@ struct Bits<double> {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
     }
     __device__ static void st(double x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, v, s, kStreamStore);
     }
 };
 template <>
@@ -358,7 +364,7 @@ struct Bits<__half> {
         return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
     }
     __device__ static void st(__half x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, kStreamStore);
     }
 };
 template <>
@@ -367,7 +373,7 @@ struct Bits<__hip_bfloat16> {
         return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
     }
     __device__ static void st(__hip_bfloat16 x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, kStreamStore);
     }
 };
 
@@ -411,6 +417,19 @@ struct Planes<S, true> {
     }
 };
 
+// Non-temporal store of one value through a plain pointer (64-bit address path).
+template <typename S, typename C>
+__device__ inline void stream_store(S* p, C v, C ref) {
+    S t;
+    Io<S, C>::st(&t, 0, v, ref);
+    if constexpr (sizeof(S) == 8)
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, t), reinterpret_cast<unsigned long long*>(p));
+    else if constexpr (sizeof(S) == 4)
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned, t), reinterpret_cast<unsigned*>(p));
+    else
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, t), reinterpret_cast<unsigned short*>(p));
+}
+
 template <typename S>
 struct Planes<S, false> {
     char* base;
@@ -427,7 +446,7 @@ struct Planes<S, false> {
     }
     template <typename C>
     __device__ void st(int i, size_t off, C v, C ref, bool valid) const {
-        if (valid) Io<S, C>::st(reinterpret_cast<S*>(base + ps * i + off), 0, v, ref);
+        if (valid) stream_store(reinterpret_cast<S*>(base + ps * i + off), v, ref);
     }
 };
 
@@ -496,6 +515,22 @@ __device__ inline void pin(C& v) {
     asm volatile("" : "+v"(v));
 }
 
+// A copy of a landed load into a register of its own (early clobber: never the source's).
+// Without it the register allocator lets a population that passes straight from a raw
+// load into the row arrays share the load's register, and the next load of that array
+// then has to go elsewhere, which costs a rotation of copies of in-flight loads at the
+// loop's back edge (each such copy waits for its load).
+__device__ inline float fresh(float v) {
+    float t;
+    asm("v_mov_b32 %0, %1" : "=&v"(t) : "v"(v));
+    return t;
+}
+__device__ inline double fresh(double v) {
+    double t;
+    asm("v_mov_b64 %0, %1" : "=&v"(t) : "v"(v));
+    return t;
+}
+
 template <typename C>
 __device__ inline void finish_f(const Strip& G, const C* raw, C gth, C* f, C& rho, C& rhoL, C& rhoR) {
     const int lane = threadIdx.x & 63;
@@ -505,9 +540,9 @@ __device__ inline void finish_f(const Strip& G, const C* raw, C gth, C* f, C& rh
     const C g6 = lane_value(gth, 6), g7 = lane_value(gth, 7), g8 = lane_value(gth, 8);
     const C g15 = lane_value(gth, 15), g16 = lane_value(gth, 16), g17 = lane_value(gth, 17);
     const bool first = lane == 0, lastl = lane == G.last;
-    f[0] = raw[0];
-    f[2] = raw[2];
-    f[4] = raw[4];
+    f[0] = fresh(raw[0]);
+    f[2] = fresh(raw[2]);
+    f[4] = fresh(raw[4]);
     f[1] = first ? g6 : w1;
     f[5] = first ? g7 : w5;
     f[8] = first ? g8 : w8;
@@ -547,9 +582,9 @@ __device__ inline void finish_g(const Strip& G, const C* raw, C gth, C* g) {
     const C g0 = lane_value(gth, 0), g1 = lane_value(gth, 1), g2 = lane_value(gth, 2);
     const C g3 = lane_value(gth, 3), g4 = lane_value(gth, 4), g5 = lane_value(gth, 5);
     const bool first = lane == 0, lastl = lane == G.last;
-    g[0] = raw[0];
-    g[2] = raw[2];
-    g[4] = raw[4];
+    g[0] = fresh(raw[0]);
+    g[2] = fresh(raw[2]);
+    g[4] = fresh(raw[4]);
     g[1] = first ? g0 : w1;
     g[5] = first ? g1 : w5;
     g[8] = first ? g2 : w8;
@@ -563,21 +598,24 @@ struct Dens {
     C v, L, R;  // the lane's density and the two halo columns' densities (uniform)
 };
 
-// One row of the marching update.  kStage = 2: issue the loads for later rows
-// (g of row y+2, f of row y+3), collide row y, finish and rotate; kStage = 1: collide,
-// finish and rotate without new loads; kStage = 0: collide only (last row).
+// One row of the marching update.  kStage = 2: issue the loads for later rows (g of row
+// y+2 into lg, f of row y+3 into lf), collide row y (f in fa, g in ga), store, then
+// rotate the densities and finish the loads issued one row earlier: f of row y+2 from
+// rf into fa (free once row y is collided; row y+1 sits in the caller's other array)
+// and g of row y+1 from rg into ga; kStage = 1: the same without new loads; kStage = 0:
+// collide and store only (last row).  The caller swaps the roles of the load targets
+// and the finish sources every row, so no register holding a load in flight is copied.
 // R[0..3] hold the byte offsets of rows y+1 .. y+4 (periodic); yo that of row y.
 template <int kStage, typename S, typename C, bool kBuf>
 __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
                                        const Strip& G, typename OffT<kBuf>::type yo,
-                                       typename OffT<kBuf>::type (&R)[4], C (&fA)[9], C (&fB)[9],
-                                       C (&rC)[9], C& hC, C (&gA)[9], C (&rgB)[9], C& hgB, Dens<C>& dm,
-                                       Dens<C>& dc, Dens<C>& dp) {
+                                       const typename OffT<kBuf>::type (&R)[4], C (&fa)[9], const C (&rf)[9],
+                                       const C& rfh, C (&lf)[9], C& lfh, C (&ga)[9], const C (&rg)[9],
+                                       const C& rgh, C (&lg)[9], C& lgh, Dens<C>& dm, Dens<C>& dc, Dens<C>& dp) {
     const int lane = threadIdx.x & 63;
-    C rD[9], hD, rgC[9], hgC;
     if (kStage == 2) {
-        load_target_row<S, C, kBuf>(in, 9, G, R[2], R[1], R[0], false, P.ref_g, rgC, hgC);
-        load_target_row<S, C, kBuf>(in, 0, G, R[3], R[2], R[1], true, P.ref_f, rD, hD);
+        load_target_row<S, C, kBuf>(in, 9, G, R[2], R[1], R[0], false, P.ref_g, lg, lgh);
+        load_target_row<S, C, kBuf>(in, 0, G, R[3], R[2], R[1], true, P.ref_f, lf, lfh);
     }
     // neighbour densities: lane L-1 is x-1 (west), lane L+1 is x+1 (east); the
     // shifts run on the whole wavefront before the halo lanes are patched
@@ -592,7 +630,7 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
     C sx, sy;
     stencil(rE, dp.v, rW, dm.v, rNE, rNW, rSW, rSE, sx, sy);
     C fo[9], go[9];
-    collide(P, fA, gA, dc.v, sx, sy, fo, go);
+    collide(P, fa, ga, dc.v, sx, sy, fo, go);
     const typename OffT<kBuf>::type o = yo + G.xc * G.esz;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -602,19 +640,8 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
     if (kStage >= 1) {
         dm = dc;
         dc = dp;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) fA[i] = fB[i];
-        finish_f(G, rC, hC, fB, dp.v, dp.L, dp.R);
-        finish_g(G, rgB, hgB, gA);
-        if (kStage == 2) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                rC[i] = rD[i];
-                rgB[i] = rgC[i];
-            }
-            hC = hD;
-            hgB = hgC;
-        }
+        finish_f(G, rf, rfh, fa, dp.v, dp.L, dp.R);
+        finish_g(G, rg, rgh, ga);
     }
 }
 
@@ -670,9 +697,10 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
     const Off blk = (Off)18 * G.rowb;  // bytes of one row block (all 18 slots of a row)
     const Off tot = (Off)total;
 
-    // register ring: streamed f of rows y, y+1 and raw loads of row y+2; streamed g of
-    // row y and raw loads of row y+1; densities of rows y-1, y, y+1
-    C fA[9], fB[9], rC[9], hC, gA[9], rgB[9], hgB;
+    // f of two consecutive rows in X and Y, g of the current row in gA; raw loads in
+    // flight in C/D (f) and G/H (g), whose roles swap every row; densities of rows
+    // y-1, y, y+1
+    C fX[9], fY[9], gA[9], rC[9], hC, rD[9], hD, rG[9], hG, rH[9], hH;
     Dens<C> dm, dc, dp;
     // byte offsets of the row blocks of rows y0-2 .. y0+3 (periodic)
     Off ro[6];
@@ -682,40 +710,67 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
         ro[k] = (Off)yy * blk;
     }
     {
-        C r[9], h, t[9];
-        load_target_row<S, C, kBuf>(Pin, 0, G, ro[2], ro[1], ro[0], true, P.ref_f, r, h);
-        finish_f(G, r, h, t, dm.v, dm.L, dm.R);
-        load_target_row<S, C, kBuf>(Pin, 0, G, ro[3], ro[2], ro[1], true, P.ref_f, r, h);
-        finish_f(G, r, h, fA, dc.v, dc.L, dc.R);
-        load_target_row<S, C, kBuf>(Pin, 0, G, ro[4], ro[3], ro[2], true, P.ref_f, r, h);
-        finish_f(G, r, h, fB, dp.v, dp.L, dp.R);
-        load_target_row<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, r, h);
-        finish_g(G, r, h, gA);
+        // all six prologue rows in flight at once (60 loads): one memory round trip
+        // instead of one per row
+        C r0[9], h0, r1[9], h1, r2[9], h2, r3[9], h3, t[9];
+        load_target_row<S, C, kBuf>(Pin, 0, G, ro[2], ro[1], ro[0], true, P.ref_f, r0, h0);   // f(y0-1)
+        load_target_row<S, C, kBuf>(Pin, 0, G, ro[3], ro[2], ro[1], true, P.ref_f, r1, h1);   // f(y0)
+        load_target_row<S, C, kBuf>(Pin, 0, G, ro[4], ro[3], ro[2], true, P.ref_f, r2, h2);   // f(y0+1)
+        load_target_row<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, r3, h3);  // g(y0)
+        load_target_row<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rG, hG);  // g(y0+1)
+        load_target_row<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rC, hC);   // f(y0+2)
+        finish_f(G, r0, h0, t, dm.v, dm.L, dm.R);
+        finish_f(G, r1, h1, fX, dc.v, dc.L, dc.R);
+        finish_f(G, r2, h2, fY, dp.v, dp.L, dp.R);
+        finish_g(G, r3, h3, gA);
     }
-    load_target_row<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rgB, hgB);
-    load_target_row<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rC, hC);
     // Let the prologue's loads land before the loop: the loop header then sees only
     // the pipelined state, and the memory-counter waits inside the loop cover just the
     // loads issued in earlier rows (not the stores of the previous row).
 #pragma unroll
-    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(rgB[i]), "v"(rC[i]));
-    asm volatile("" ::"v"(hgB), "v"(hC));
+    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(rG[i]), "v"(rC[i]));
+    asm volatile("" ::"v"(hG), "v"(hC));
     Off R[4] = {ro[3], ro[4], ro[5], next_row<Off>(ro[5], blk, tot)};  // rows y+1 .. y+4
     Off yo = ro[2];
-    int y = y0;
-    for (; y < y1 - 2; ++y) {
-        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
+    auto advance = [&]() {
         yo = R[0];
         R[0] = R[1];
         R[1] = R[2];
         R[2] = R[3];
         R[3] = next_row<Off>(R[3], blk, tot);
+    };
+    int y = y0;
+    for (; y < y1 - 3; y += 2) {
+        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
+        advance();
+        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fY, rD, hD, rC, hC, gA, rH, hH, rG, hG, dm, dc, dp);
+        advance();
+    }
+    // ragged tail (once per strip): moves restore the roles the last rows expect
+    if (y < y1 - 2) {
+        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
+        advance();
+        ++y;
+        // X now holds f(y+1) and Y f(y): swap them
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const C t = fX[i];
+            fX[i] = fY[i];
+            fY[i] = t;
+            rC[i] = rD[i];
+            rG[i] = rH[i];
+        }
+        hC = hD;
+        hG = hH;
     }
     if (y < y1 - 1) {
-        ab_row<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
+        ab_row<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
         yo = R[0];
+        // the last row's f is in Y (X took f(y1), which no row collides)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fX[i] = fY[i];
     }
-    ab_row<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fA, fB, rC, hC, gA, rgB, hgB, dm, dc, dp);
+    ab_row<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
 }
 
 template <typename S, typename C, int WPB, bool kBuf>
@@ -758,7 +813,7 @@ struct Bits2<float> {
         V2 t;
         t.x = __builtin_bit_cast(unsigned, a);
         t.y = __builtin_bit_cast(unsigned, b);
-        __builtin_amdgcn_raw_buffer_store_b64(t, r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, v, s, kStreamStore);
     }
 };
 template <typename H>
@@ -771,7 +826,7 @@ struct Bits2Half {
     __device__ static void st(H a, H b, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
         const unsigned t = (unsigned)__builtin_bit_cast(unsigned short, a) |
                            ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
-        __builtin_amdgcn_raw_buffer_store_b32(t, r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(t, r, v, s, kStreamStore);
     }
 };
 template <>
@@ -804,8 +859,8 @@ template <typename S, typename C>
 __device__ inline void st2(const Planes<S, false>& B, int i, size_t off, C a, C b, C ref, bool valid) {
     if (!valid) return;
     S* q = reinterpret_cast<S*>(B.base + B.ps * i + off);
-    Io<S, C>::st(q, 0, a, ref);
-    Io<S, C>::st(q, 1, b, ref);
+    stream_store(q, a, ref);
+    stream_store(q + 1, b, ref);
 }
 
 // Raw loads of one target row for both columns of the lane, and the gather.
@@ -842,14 +897,14 @@ __device__ inline void finish_f2(const Strip& G, const C* ra, const C* rb, C gth
     const C g6 = lane_value(gth, 6), g7 = lane_value(gth, 7), g8 = lane_value(gth, 8);
     const C g15 = lane_value(gth, 15), g16 = lane_value(gth, 16), g17 = lane_value(gth, 17);
     const bool first = lane == 0, lastl = lane == G.last;
-    fa[0] = ra[0], fa[2] = ra[2], fa[4] = ra[4];
-    fb[0] = rb[0], fb[2] = rb[2], fb[4] = rb[4];
-    fa[1] = first ? g6 : w1, fb[1] = ra[1];
-    fa[5] = first ? g7 : w5, fb[5] = ra[5];
-    fa[8] = first ? g8 : w8, fb[8] = ra[8];
-    fa[3] = rb[3], fb[3] = lastl ? g15 : e3;
-    fa[6] = rb[6], fb[6] = lastl ? g16 : e6;
-    fa[7] = rb[7], fb[7] = lastl ? g17 : e7;
+    fa[0] = fresh(ra[0]), fa[2] = fresh(ra[2]), fa[4] = fresh(ra[4]);
+    fb[0] = fresh(rb[0]), fb[2] = fresh(rb[2]), fb[4] = fresh(rb[4]);
+    fa[1] = first ? g6 : w1, fb[1] = fresh(ra[1]);
+    fa[5] = first ? g7 : w5, fb[5] = fresh(ra[5]);
+    fa[8] = first ? g8 : w8, fb[8] = fresh(ra[8]);
+    fa[3] = fresh(rb[3]), fb[3] = lastl ? g15 : e3;
+    fa[6] = fresh(rb[6]), fb[6] = lastl ? g16 : e6;
+    fa[7] = fresh(rb[7]), fb[7] = lastl ? g17 : e7;
     d.a = sum9(fa);
     d.b = sum9(fb);
     C h[9];
@@ -884,33 +939,37 @@ __device__ inline void finish_g2(const Strip& G, const C* ra, const C* rb, C gth
     const C g0 = lane_value(gth, 0), g1 = lane_value(gth, 1), g2 = lane_value(gth, 2);
     const C g3 = lane_value(gth, 3), g4 = lane_value(gth, 4), g5 = lane_value(gth, 5);
     const bool first = lane == 0, lastl = lane == G.last;
-    ga[0] = ra[0], ga[2] = ra[2], ga[4] = ra[4];
-    gb[0] = rb[0], gb[2] = rb[2], gb[4] = rb[4];
-    ga[1] = first ? g0 : w1, gb[1] = ra[1];
-    ga[5] = first ? g1 : w5, gb[5] = ra[5];
-    ga[8] = first ? g2 : w8, gb[8] = ra[8];
-    ga[3] = rb[3], gb[3] = lastl ? g3 : e3;
-    ga[6] = rb[6], gb[6] = lastl ? g4 : e6;
-    ga[7] = rb[7], gb[7] = lastl ? g5 : e7;
+    ga[0] = fresh(ra[0]), ga[2] = fresh(ra[2]), ga[4] = fresh(ra[4]);
+    gb[0] = fresh(rb[0]), gb[2] = fresh(rb[2]), gb[4] = fresh(rb[4]);
+    ga[1] = first ? g0 : w1, gb[1] = fresh(ra[1]);
+    ga[5] = first ? g1 : w5, gb[5] = fresh(ra[5]);
+    ga[8] = first ? g2 : w8, gb[8] = fresh(ra[8]);
+    ga[3] = fresh(rb[3]), gb[3] = lastl ? g3 : e3;
+    ga[6] = fresh(rb[6]), gb[6] = lastl ? g4 : e6;
+    ga[7] = fresh(rb[7]), gb[7] = lastl ? g5 : e7;
 }
 
-// One row of the two-column march.  kStage = 2: issue the raw loads of f(y+3) and
-// g(y+2), collide row y for both columns, store, then rotate (densities, f(y+1) ->
-// f(y), finish the raw loads of f(y+2) and g(y+1) issued one row earlier); kStage = 1:
-// the same without new loads; kStage = 0: collide and store only (last row).
+// One row of the two-column march.  kStage = 2: issue the raw loads of f(y+3) into lf and
+// of g(y+2) into lg, collide row y (f in fa/fb, g in ga/gb) for both columns, store, then
+// rotate the densities and finish the raw loads issued one row earlier: f(y+2) from rf
+// into fa/fb (free once row y is collided; row y+1 sits in the caller's other pair) and
+// g(y+1) from rg into ga/gb; kStage = 1: the same without new loads; kStage = 0: collide
+// and store only (last row).  The load targets and the finish sources are separate
+// arrays and the caller swaps their roles every row, so no register holding a load in
+// flight is ever copied: a copy would stall the wavefront until that load lands.
 // R[0..3]: byte offsets of the row blocks of rows y+1 .. y+4; yo: row y.
 template <int kStage, typename S, typename C, bool kBuf>
 __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
                                         const Strip& G, typename OffT<kBuf>::type yo,
-                                        const typename OffT<kBuf>::type (&R)[4], C (&fAa)[9], C (&fAb)[9],
-                                        C (&fBa)[9], C (&fBb)[9], C (&rCa)[9], C (&rCb)[9], C& hC, C (&gAa)[9],
-                                        C (&gAb)[9], C (&rGa)[9], C (&rGb)[9], C& hG, Dens2<C>& dm, Dens2<C>& dc,
-                                        Dens2<C>& dp) {
+                                        const typename OffT<kBuf>::type (&R)[4], C (&fa)[9], C (&fb)[9],
+                                        const C (&rfa)[9], const C (&rfb)[9], const C& rfh, C (&lfa)[9],
+                                        C (&lfb)[9], C& lfh, C (&ga)[9], C (&gb)[9], const C (&rga)[9],
+                                        const C (&rgb)[9], const C& rgh, C (&lga)[9], C (&lgb)[9], C& lgh,
+                                        Dens2<C>& dm, Dens2<C>& dc, Dens2<C>& dp) {
     const int lane = threadIdx.x & 63;
-    C rDa[9], rDb[9], hD, rHa[9], rHb[9], hH;
     if (kStage == 2) {
-        load_target_row2<S, C, kBuf>(in, 9, G, R[2], R[1], R[0], false, P.ref_g, rHa, rHb, hH);  // g(y+2)
-        load_target_row2<S, C, kBuf>(in, 0, G, R[3], R[2], R[1], true, P.ref_f, rDa, rDb, hD);   // f(y+3)
+        load_target_row2<S, C, kBuf>(in, 9, G, R[2], R[1], R[0], false, P.ref_g, lga, lgb, lgh);  // g(y+2)
+        load_target_row2<S, C, kBuf>(in, 0, G, R[3], R[2], R[1], true, P.ref_f, lfa, lfb, lfh);   // f(y+3)
     }
     C wc = dpp_from_west(dc.b), ec = dpp_from_east(dc.a);
     C wm = dpp_from_west(dm.b), em = dpp_from_east(dm.a);
@@ -925,8 +984,8 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
     const typename OffT<kBuf>::type o = yo + G.xc * G.esz;
     {
         C foa[9], goa[9], fob[9], gob[9];
-        collide(P, fAa, gAa, dc.a, sxa, sya, foa, goa);
-        collide(P, fAb, gAb, dc.b, sxb, syb, fob, gob);
+        collide(P, fa, ga, dc.a, sxa, sya, foa, goa);
+        collide(P, fb, gb, dc.b, sxb, syb, fob, gob);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             st2<S, C>(out, i, o, foa[i], fob[i], P.ref_f[i], G.owner);
@@ -936,24 +995,8 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
     if (kStage >= 1) {
         dm = dc;
         dc = dp;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            fAa[i] = fBa[i];
-            fAb[i] = fBb[i];
-        }
-        finish_f2(G, rCa, rCb, hC, fBa, fBb, dp);
-        finish_g2(G, rGa, rGb, hG, gAa, gAb);
-        if (kStage == 2) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                rCa[i] = rDa[i];
-                rCb[i] = rDb[i];
-                rGa[i] = rHa[i];
-                rGb[i] = rHb[i];
-            }
-            hC = hD;
-            hG = hH;
-        }
+        finish_f2(G, rfa, rfb, rfh, fa, fb, dp);
+        finish_g2(G, rga, rgb, rgh, ga, gb);
     }
 }
 
@@ -1008,44 +1051,83 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
         const int yy = __builtin_amdgcn_readfirstlane(wrap_row(y0 - 2 + k, ny));
         ro[k] = (Off)yy * blk;
     }
-    C fAa[9], fAb[9], fBa[9], fBb[9], gAa[9], gAb[9], rCa[9], rCb[9], hC, rGa[9], rGb[9], hG;
+    // f of two consecutive rows in the pairs X and Y, g of the current row in gA; raw
+    // loads in flight in C/D (f) and G/H (g), whose roles swap every row
+    C fXa[9], fXb[9], fYa[9], fYb[9], gAa[9], gAb[9];
+    C rCa[9], rCb[9], hC, rDa[9], rDb[9], hD, rGa[9], rGb[9], hG, rHa[9], rHb[9], hH;
     Dens2<C> dm, dc, dp;
     {
-        C ra[9], rb[9], h, ta[9], tb[9];
-        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[2], ro[1], ro[0], true, P.ref_f, ra, rb, h);  // f(y0-1)
-        finish_f2(G, ra, rb, h, ta, tb, dm);
-        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[3], ro[2], ro[1], true, P.ref_f, ra, rb, h);  // f(y0)
-        finish_f2(G, ra, rb, h, fAa, fAb, dc);
-        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[4], ro[3], ro[2], true, P.ref_f, ra, rb, h);  // f(y0+1)
-        finish_f2(G, ra, rb, h, fBa, fBb, dp);
-        load_target_row2<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, ra, rb, h);  // g(y0)
-        finish_g2(G, ra, rb, h, gAa, gAb);
+        // all six prologue rows in flight at once (60 loads): one memory round trip
+        // instead of one per row
+        C a0[9], b0[9], h0, a1[9], b1[9], h1, a2[9], b2[9], h2, a3[9], b3[9], h3, ta[9], tb[9];
+        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[2], ro[1], ro[0], true, P.ref_f, a0, b0, h0);   // f(y0-1)
+        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[3], ro[2], ro[1], true, P.ref_f, a1, b1, h1);   // f(y0)
+        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[4], ro[3], ro[2], true, P.ref_f, a2, b2, h2);   // f(y0+1)
+        load_target_row2<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, a3, b3, h3);  // g(y0)
+        load_target_row2<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rGa, rGb, hG);  // g(y0+1)
+        load_target_row2<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rCa, rCb, hC);   // f(y0+2)
+        finish_f2(G, a0, b0, h0, ta, tb, dm);
+        finish_f2(G, a1, b1, h1, fXa, fXb, dc);
+        finish_f2(G, a2, b2, h2, fYa, fYb, dp);
+        finish_g2(G, a3, b3, h3, gAa, gAb);
     }
-    load_target_row2<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rGa, rGb, hG);  // g(y0+1)
-    load_target_row2<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rCa, rCb, hC);   // f(y0+2)
     // let the prologue's loads land before the loop (as in the one-column form)
 #pragma unroll
     for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(rGa[i]), "v"(rGb[i]), "v"(rCa[i]), "v"(rCb[i]));
     asm volatile("" ::"v"(hG), "v"(hC));
     Off R[4] = {ro[3], ro[4], ro[5], next_row<Off>(ro[5], blk, tot)};  // rows y+1 .. y+4
     Off yo = ro[2];
-    int y = y0;
-    for (; y < y1 - 2; ++y) {
-        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, rCa, rCb, hC, gAa, gAb, rGa, rGb, hG, dm,
-                               dc, dp);
+    auto advance = [&]() {
         yo = R[0];
         R[0] = R[1];
         R[1] = R[2];
         R[2] = R[3];
         R[3] = next_row<Off>(R[3], blk, tot);
+    };
+    int y = y0;
+    for (; y < y1 - 3; y += 2) {
+        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
+                               rHa, rHb, hH, dm, dc, dp);
+        advance();
+        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fYa, fYb, rDa, rDb, hD, rCa, rCb, hC, gAa, gAb, rHa, rHb, hH,
+                               rGa, rGb, hG, dm, dc, dp);
+        advance();
+    }
+    // ragged tail (once per strip): moves restore the roles the last rows expect
+    if (y < y1 - 2) {
+        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
+                               rHa, rHb, hH, dm, dc, dp);
+        advance();
+        ++y;
+        // X now holds f(y+1) and Y f(y): swap them
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const C ta = fXa[i], tb = fXb[i];
+            fXa[i] = fYa[i];
+            fXb[i] = fYb[i];
+            fYa[i] = ta;
+            fYb[i] = tb;
+            rCa[i] = rDa[i];
+            rCb[i] = rDb[i];
+            rGa[i] = rHa[i];
+            rGb[i] = rHb[i];
+        }
+        hC = hD;
+        hG = hH;
     }
     if (y < y1 - 1) {
-        ab_row2<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, rCa, rCb, hC, gAa, gAb, rGa, rGb, hG, dm,
-                               dc, dp);
+        ab_row2<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
+                               rHa, rHb, hH, dm, dc, dp);
         yo = R[0];
+        // the last row's f is in Y (X took f(y1), which no row collides)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            fXa[i] = fYa[i];
+            fXb[i] = fYb[i];
+        }
     }
-    ab_row2<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fAa, fAb, fBa, fBb, rCa, rCb, hC, gAa, gAb, rGa, rGb, hG, dm, dc,
-                           dp);
+    ab_row2<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG, rHa,
+                           rHb, hH, dm, dc, dp);
 }
 
 template <typename S, typename C, int WPB, bool kBuf>
