@@ -45,10 +45,21 @@ struct Io<float, float> {
     __device__ static float ld(const float* p, int k, float) { return p[k]; }
     __device__ static void st(float* p, int k, float v, float) { p[k] = v; }
 };
+// FP16 deviation v - ref, rounded once from the exact difference to FP16 (the
+// mixed-precision FMA v * 1 + (-ref) with an FP16 result).  Every FP16 store of the
+// library goes through this conversion or its pair form below, so all kernel forms
+// round alike.
+__device__ inline unsigned short f16_dev(float v, float ref) {
+    unsigned t;
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2" : "=v"(t) : "v"(v), "v"(ref));
+    return (unsigned short)(t & 0xffffu);
+}
 template <>
 struct Io<__half, float> {
     __device__ static float ld(const __half* p, int k, float ref) { return __half2float(p[k]) + ref; }
-    __device__ static void st(__half* p, int k, float v, float ref) { p[k] = __float2half(v - ref); }
+    __device__ static void st(__half* p, int k, float v, float ref) {
+        p[k] = __builtin_bit_cast(__half, f16_dev(v, ref));
+    }
 };
 template <>
 struct Io<__hip_bfloat16, float> {
@@ -285,22 +296,24 @@ __device__ constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
+// Wave-wide one-lane shifts.  The lane with no source (0 for west, 63 for east) reads
+// zero (bound_ctrl); callers replace that lane's value with a gathered one.
 __device__ inline float dpp_from_west(float v) {  // lane L receives lane L-1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
 }
 __device__ inline float dpp_from_east(float v) {  // lane L receives lane L+1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
 }
 __device__ inline double dpp_from_west(double v) {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 __device__ inline double dpp_from_east(double v) {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 __device__ inline float lane_value(float v, int l) {
@@ -409,6 +422,12 @@ struct Planes<S, true> {
         const S v = Bits<S>::ld(r, on ? ps * slot + off : drop, 0u);
         return Io<S, C>::ld(&v, 0, ref);
     }
+    // 16-bit storage: the gathered bits, converted later (unpack_gather)
+    template <typename C>
+    __device__ C gather_raw(unsigned slot, unsigned off, bool on) const {
+        const S v = Bits<S>::ld(r, on ? ps * slot + off : drop, 0u);
+        return __builtin_bit_cast(C, (unsigned)__builtin_bit_cast(unsigned short, v));
+    }
     template <typename C>
     __device__ void st(int i, unsigned off, C v, C ref, bool valid) const {
         S t;
@@ -445,6 +464,11 @@ struct Planes<S, false> {
         return on ? Io<S, C>::ld(reinterpret_cast<const S*>(base + ps * slot + off), 0, ref) : C(0);
     }
     template <typename C>
+    __device__ C gather_raw(unsigned slot, size_t off, bool on) const {
+        const S v = *reinterpret_cast<const S*>(base + ps * slot + off);
+        return on ? __builtin_bit_cast(C, (unsigned)__builtin_bit_cast(unsigned short, v)) : C(0);
+    }
+    template <typename C>
     __device__ void st(int i, size_t off, C v, C ref, bool valid) const {
         if (valid) stream_store(reinterpret_cast<S*>(base + ps * i + off), v, ref);
     }
@@ -467,7 +491,17 @@ struct Strip {
     bool fon, gon;
     unsigned fplane, gplane, fcol, gcol;
     int fdy, gdy;
+    float fref, gref;  // 16-bit storage: deviation references of the gather slots' populations
 };
+
+// ref[k] for a per-lane k in [0, 9) by selects (no indexed memory access)
+template <typename C>
+__device__ inline C pick9(const C* ref, unsigned k) {
+    C r = ref[0];
+#pragma unroll
+    for (unsigned i = 1; i < 9; ++i) r = k == i ? ref[i] : r;
+    return r;
+}
 
 // Raw loads for one target row: slot i at source row y - e_iy, aligned, and the
 // gather.  up/mid/dn are the byte offsets of the row blocks of source rows y+1, y,
@@ -530,8 +564,17 @@ __device__ inline double fresh(double v) {
     asm("v_mov_b64 %0, %1" : "=&v"(t) : "v"(v));
     return t;
 }
+// 16-bit storage converts every loaded value, which already gives it a register of
+// its own: the copy is needed only where raw loads feed the arrays directly.
+template <bool kCopy, typename C>
+__device__ inline C pass(C v) {
+    if constexpr (kCopy)
+        return fresh(v);
+    else
+        return v;
+}
 
-template <typename C>
+template <bool kCopy, typename C>
 __device__ inline void finish_f(const Strip& G, const C* raw, C gth, C* f, C& rho, C& rhoL, C& rhoR) {
     const int lane = threadIdx.x & 63;
     C w1 = dpp_from_west(raw[1]), w5 = dpp_from_west(raw[5]), w8 = dpp_from_west(raw[8]);
@@ -540,9 +583,9 @@ __device__ inline void finish_f(const Strip& G, const C* raw, C gth, C* f, C& rh
     const C g6 = lane_value(gth, 6), g7 = lane_value(gth, 7), g8 = lane_value(gth, 8);
     const C g15 = lane_value(gth, 15), g16 = lane_value(gth, 16), g17 = lane_value(gth, 17);
     const bool first = lane == 0, lastl = lane == G.last;
-    f[0] = fresh(raw[0]);
-    f[2] = fresh(raw[2]);
-    f[4] = fresh(raw[4]);
+    f[0] = pass<kCopy>(raw[0]);
+    f[2] = pass<kCopy>(raw[2]);
+    f[4] = pass<kCopy>(raw[4]);
     f[1] = first ? g6 : w1;
     f[5] = first ? g7 : w5;
     f[8] = first ? g8 : w8;
@@ -573,7 +616,7 @@ __device__ inline void finish_f(const Strip& G, const C* raw, C gth, C* f, C& rh
     rhoR = sum9(h);
 }
 
-template <typename C>
+template <bool kCopy, typename C>
 __device__ inline void finish_g(const Strip& G, const C* raw, C gth, C* g) {
     const int lane = threadIdx.x & 63;
     C w1 = dpp_from_west(raw[1]), w5 = dpp_from_west(raw[5]), w8 = dpp_from_west(raw[8]);
@@ -582,9 +625,9 @@ __device__ inline void finish_g(const Strip& G, const C* raw, C gth, C* g) {
     const C g0 = lane_value(gth, 0), g1 = lane_value(gth, 1), g2 = lane_value(gth, 2);
     const C g3 = lane_value(gth, 3), g4 = lane_value(gth, 4), g5 = lane_value(gth, 5);
     const bool first = lane == 0, lastl = lane == G.last;
-    g[0] = fresh(raw[0]);
-    g[2] = fresh(raw[2]);
-    g[4] = fresh(raw[4]);
+    g[0] = pass<kCopy>(raw[0]);
+    g[2] = pass<kCopy>(raw[2]);
+    g[4] = pass<kCopy>(raw[4]);
     g[1] = first ? g0 : w1;
     g[5] = first ? g1 : w5;
     g[8] = first ? g2 : w8;
@@ -612,6 +655,7 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
                                        const typename OffT<kBuf>::type (&R)[4], C (&fa)[9], const C (&rf)[9],
                                        const C& rfh, C (&lf)[9], C& lfh, C (&ga)[9], const C (&rg)[9],
                                        const C& rgh, C (&lg)[9], C& lgh, Dens<C>& dm, Dens<C>& dc, Dens<C>& dp) {
+    constexpr bool kCopy = sizeof(S) >= 4;  // pass-through copies (see pass())
     const int lane = threadIdx.x & 63;
     if (kStage == 2) {
         load_target_row<S, C, kBuf>(in, 9, G, R[2], R[1], R[0], false, P.ref_g, lg, lgh);
@@ -640,8 +684,8 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
     if (kStage >= 1) {
         dm = dc;
         dc = dp;
-        finish_f(G, rf, rfh, fa, dp.v, dp.L, dp.R);
-        finish_g(G, rg, rgh, ga);
+        finish_f<kCopy>(G, rf, rfh, fa, dp.v, dp.L, dp.R);
+        finish_g<kCopy>(G, rg, rgh, ga);
     }
 }
 
@@ -650,6 +694,7 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
 template <typename S, typename C, bool kBuf>
 __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict__ out, const Consts<C>& P,
                                          const int w, const int nstrips, const int rows) {
+    constexpr bool kCopy = sizeof(S) >= 4;  // pass-through copies (see pass())
     const int lane = threadIdx.x & 63;
     const int strip = w % nstrips, chunk = w / nstrips;
     const int nx = P.nx, ny = P.ny;
@@ -719,10 +764,10 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
         load_target_row<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, r3, h3);  // g(y0)
         load_target_row<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rG, hG);  // g(y0+1)
         load_target_row<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rC, hC);   // f(y0+2)
-        finish_f(G, r0, h0, t, dm.v, dm.L, dm.R);
-        finish_f(G, r1, h1, fX, dc.v, dc.L, dc.R);
-        finish_f(G, r2, h2, fY, dp.v, dp.L, dp.R);
-        finish_g(G, r3, h3, gA);
+        finish_f<kCopy>(G, r0, h0, t, dm.v, dm.L, dm.R);
+        finish_f<kCopy>(G, r1, h1, fX, dc.v, dc.L, dc.R);
+        finish_f<kCopy>(G, r2, h2, fY, dp.v, dp.L, dp.R);
+        finish_g<kCopy>(G, r3, h3, gA);
     }
     // Let the prologue's loads land before the loop: the loop header then sees only
     // the pipelined state, and the memory-counter waits inside the loop cover just the
@@ -828,32 +873,104 @@ struct Bits2Half {
                            ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
         __builtin_amdgcn_raw_buffer_store_b32(t, r, v, s, kStreamStore);
     }
+    __device__ static unsigned ldw(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+    }
+    __device__ static void stw(unsigned t, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b32(t, r, v, s, kStreamStore);
+    }
 };
 template <>
 struct Bits2<__half> : Bits2Half<__half> {};
 template <>
 struct Bits2<__hip_bfloat16> : Bits2Half<__hip_bfloat16> {};
 
+// Conversions of one 32-bit word holding a pair of 16-bit deviations (first column in
+// the low half) with a uniform reference.  They give bitwise the same values as the
+// per-value conversions of Io: FP16 to FP32 is exact, so f32(h) + ref and the fused
+// h * 1 + ref round alike; the FP16 stores round once as in f16_dev; BF16 rounds to
+// nearest even per value in both.
+template <typename S>
+struct Pair16;
+template <>
+struct Pair16<__half> {
+    __device__ static void unpack(unsigned w, float ref, float& a, float& b) {
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(a) : "v"(w), "s"(ref));
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(b) : "v"(w), "s"(ref));
+    }
+    __device__ static unsigned pack(float a, float b, float ref) {
+        unsigned t;
+        asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2" : "=v"(t) : "v"(a), "s"(ref));
+        asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2" : "+v"(t) : "v"(b), "s"(ref));
+        return t;
+    }
+};
+template <>
+struct Pair16<__hip_bfloat16> {
+    __device__ static void unpack(unsigned w, float ref, float& a, float& b) {
+        a = __builtin_bit_cast(float, w << 16) + ref;
+        b = __builtin_bit_cast(float, w & 0xffff0000u) + ref;
+    }
+    __device__ static unsigned pack(float a, float b, float ref) {
+        using F2 = float __attribute__((ext_vector_type(2)));
+        using B2 = __bf16 __attribute__((ext_vector_type(2)));
+        const F2 v = {a - ref, b - ref};
+        return __builtin_bit_cast(unsigned, __builtin_convertvector(v, B2));
+    }
+};
+
 // pair access on top of Planes: slot i, byte offset of the pair's first column
+// For 16-bit storage the pair stays packed in a (b is unused) until the row is
+// finished (unpack2): converting right after the load would make the wavefront wait
+// for the load there.
 template <typename S, typename C>
 __device__ inline void ld2(const Planes<S, true>& B, int i, unsigned off, C ref, C& a, C& b) {
-    S u, v;
-    Bits2<S>::ld(B.r, off, B.ps * (unsigned)i, u, v);
-    a = Io<S, C>::ld(&u, 0, ref);
-    b = Io<S, C>::ld(&v, 0, ref);
+    if constexpr (sizeof(S) == 2) {
+        a = __builtin_bit_cast(C, Bits2<S>::ldw(B.r, off, B.ps * (unsigned)i));
+        b = C(0);
+    } else {
+        S u, v;
+        Bits2<S>::ld(B.r, off, B.ps * (unsigned)i, u, v);
+        a = Io<S, C>::ld(&u, 0, ref);
+        b = Io<S, C>::ld(&v, 0, ref);
+    }
 }
 template <typename S, typename C>
 __device__ inline void ld2(const Planes<S, false>& B, int i, size_t off, C ref, C& a, C& b) {
-    const S* q = reinterpret_cast<const S*>(B.base + B.ps * i + off);
-    a = Io<S, C>::ld(q, 0, ref);
-    b = Io<S, C>::ld(q, 1, ref);
+    if constexpr (sizeof(S) == 2) {
+        a = __builtin_bit_cast(C, *reinterpret_cast<const unsigned*>(B.base + B.ps * i + off));
+        b = C(0);
+    } else {
+        const S* q = reinterpret_cast<const S*>(B.base + B.ps * i + off);
+        a = Io<S, C>::ld(q, 0, ref);
+        b = Io<S, C>::ld(q, 1, ref);
+    }
+}
+
+// Values of a finished row from the raw pair loads: 16-bit storage unpacks the words
+// kept by ld2, wider storage takes the loaded values as they are.
+template <typename S, typename C>
+__device__ inline void unpack2(const C* ra, const C* rb, const C* ref, C* a, C* b) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if constexpr (sizeof(S) == 2) {
+            Pair16<S>::unpack(__builtin_bit_cast(unsigned, ra[i]), ref[i], a[i], b[i]);
+        } else {
+            a[i] = ra[i];
+            b[i] = rb[i];
+        }
+    }
 }
 template <typename S, typename C>
 __device__ inline void st2(const Planes<S, true>& B, int i, unsigned off, C a, C b, C ref, bool valid) {
-    S u, v;
-    Io<S, C>::st(&u, 0, a, ref);
-    Io<S, C>::st(&v, 0, b, ref);
-    Bits2<S>::st(u, v, B.r, valid ? off : B.drop, B.ps * (unsigned)i);
+    if constexpr (sizeof(S) == 2) {
+        Bits2<S>::stw(Pair16<S>::pack(a, b, ref), B.r, valid ? off : B.drop, B.ps * (unsigned)i);
+    } else {
+        S u, v;
+        Io<S, C>::st(&u, 0, a, ref);
+        Io<S, C>::st(&v, 0, b, ref);
+        Bits2<S>::st(u, v, B.r, valid ? off : B.drop, B.ps * (unsigned)i);
+    }
 }
 template <typename S, typename C>
 __device__ inline void st2(const Planes<S, false>& B, int i, size_t off, C a, C b, C ref, bool valid) {
@@ -880,7 +997,23 @@ __device__ inline void load_target_row2(const Planes<S, kBuf>& B, int first, con
     const int dy = is_f ? G.fdy : G.gdy;
     const bool on = is_f ? G.fon : G.gon;
     const Off r = dy > 0 ? up : (dy < 0 ? dn : mid);
-    gth = B.template gather<C>(first + plane, r + col * G.esz, on, ref[plane]);
+    if constexpr (sizeof(S) == 2)
+        gth = B.template gather_raw<C>(first + plane, r + col * G.esz, on);
+    else
+        gth = B.template gather<C>(first + plane, r + col * G.esz, on, ref[plane]);
+}
+
+// The gathered value of a finished row: 16-bit storage converts the bits kept by
+// gather_raw with the reference of the lane's gather slot (a disabled slot read zero
+// bits, as the converting gather does).
+template <typename S, typename C>
+__device__ inline C unpack_gather(C gth, C ref) {
+    if constexpr (sizeof(S) == 2) {
+        const S v = __builtin_bit_cast(S, (unsigned short)__builtin_bit_cast(unsigned, gth));
+        return Io<S, C>::ld(&v, 0, ref);
+    } else {
+        return gth;
+    }
 }
 
 template <typename C>
@@ -888,8 +1021,13 @@ struct Dens2 {
     C a, b, L, R;  // the lane's two densities and the two halo columns' densities (uniform)
 };
 
-template <typename C>
-__device__ inline void finish_f2(const Strip& G, const C* ra, const C* rb, C gth, C* fa, C* fb, Dens2<C>& d) {
+template <typename S, typename C>
+__device__ inline void finish_f2(const Strip& G, const C* rawa, const C* rawb, C rawg, const C* ref, C* fa, C* fb,
+                                 Dens2<C>& d) {
+    constexpr bool kCopy = sizeof(S) >= 4;
+    C ra[9], rb[9];
+    unpack2<S>(rawa, rawb, ref, ra, rb);
+    const C gth = unpack_gather<S>(rawg, C(G.fref));
     const int lane = threadIdx.x & 63;
     C w1 = dpp_from_west(rb[1]), w5 = dpp_from_west(rb[5]), w8 = dpp_from_west(rb[8]);
     C e3 = dpp_from_east(ra[3]), e6 = dpp_from_east(ra[6]), e7 = dpp_from_east(ra[7]);
@@ -897,14 +1035,14 @@ __device__ inline void finish_f2(const Strip& G, const C* ra, const C* rb, C gth
     const C g6 = lane_value(gth, 6), g7 = lane_value(gth, 7), g8 = lane_value(gth, 8);
     const C g15 = lane_value(gth, 15), g16 = lane_value(gth, 16), g17 = lane_value(gth, 17);
     const bool first = lane == 0, lastl = lane == G.last;
-    fa[0] = fresh(ra[0]), fa[2] = fresh(ra[2]), fa[4] = fresh(ra[4]);
-    fb[0] = fresh(rb[0]), fb[2] = fresh(rb[2]), fb[4] = fresh(rb[4]);
-    fa[1] = first ? g6 : w1, fb[1] = fresh(ra[1]);
-    fa[5] = first ? g7 : w5, fb[5] = fresh(ra[5]);
-    fa[8] = first ? g8 : w8, fb[8] = fresh(ra[8]);
-    fa[3] = fresh(rb[3]), fb[3] = lastl ? g15 : e3;
-    fa[6] = fresh(rb[6]), fb[6] = lastl ? g16 : e6;
-    fa[7] = fresh(rb[7]), fb[7] = lastl ? g17 : e7;
+    fa[0] = pass<kCopy>(ra[0]), fa[2] = pass<kCopy>(ra[2]), fa[4] = pass<kCopy>(ra[4]);
+    fb[0] = pass<kCopy>(rb[0]), fb[2] = pass<kCopy>(rb[2]), fb[4] = pass<kCopy>(rb[4]);
+    fa[1] = first ? g6 : w1, fb[1] = pass<kCopy>(ra[1]);
+    fa[5] = first ? g7 : w5, fb[5] = pass<kCopy>(ra[5]);
+    fa[8] = first ? g8 : w8, fb[8] = pass<kCopy>(ra[8]);
+    fa[3] = pass<kCopy>(rb[3]), fb[3] = lastl ? g15 : e3;
+    fa[6] = pass<kCopy>(rb[6]), fb[6] = lastl ? g16 : e6;
+    fa[7] = pass<kCopy>(rb[7]), fb[7] = lastl ? g17 : e7;
     d.a = sum9(fa);
     d.b = sum9(fb);
     C h[9];
@@ -930,8 +1068,12 @@ __device__ inline void finish_f2(const Strip& G, const C* ra, const C* rb, C gth
     d.R = sum9(h);
 }
 
-template <typename C>
-__device__ inline void finish_g2(const Strip& G, const C* ra, const C* rb, C gth, C* ga, C* gb) {
+template <typename S, typename C>
+__device__ inline void finish_g2(const Strip& G, const C* rawa, const C* rawb, C rawg, const C* ref, C* ga, C* gb) {
+    constexpr bool kCopy = sizeof(S) >= 4;
+    C ra[9], rb[9];
+    unpack2<S>(rawa, rawb, ref, ra, rb);
+    const C gth = unpack_gather<S>(rawg, C(G.gref));
     const int lane = threadIdx.x & 63;
     C w1 = dpp_from_west(rb[1]), w5 = dpp_from_west(rb[5]), w8 = dpp_from_west(rb[8]);
     C e3 = dpp_from_east(ra[3]), e6 = dpp_from_east(ra[6]), e7 = dpp_from_east(ra[7]);
@@ -939,14 +1081,14 @@ __device__ inline void finish_g2(const Strip& G, const C* ra, const C* rb, C gth
     const C g0 = lane_value(gth, 0), g1 = lane_value(gth, 1), g2 = lane_value(gth, 2);
     const C g3 = lane_value(gth, 3), g4 = lane_value(gth, 4), g5 = lane_value(gth, 5);
     const bool first = lane == 0, lastl = lane == G.last;
-    ga[0] = fresh(ra[0]), ga[2] = fresh(ra[2]), ga[4] = fresh(ra[4]);
-    gb[0] = fresh(rb[0]), gb[2] = fresh(rb[2]), gb[4] = fresh(rb[4]);
-    ga[1] = first ? g0 : w1, gb[1] = fresh(ra[1]);
-    ga[5] = first ? g1 : w5, gb[5] = fresh(ra[5]);
-    ga[8] = first ? g2 : w8, gb[8] = fresh(ra[8]);
-    ga[3] = fresh(rb[3]), gb[3] = lastl ? g3 : e3;
-    ga[6] = fresh(rb[6]), gb[6] = lastl ? g4 : e6;
-    ga[7] = fresh(rb[7]), gb[7] = lastl ? g5 : e7;
+    ga[0] = pass<kCopy>(ra[0]), ga[2] = pass<kCopy>(ra[2]), ga[4] = pass<kCopy>(ra[4]);
+    gb[0] = pass<kCopy>(rb[0]), gb[2] = pass<kCopy>(rb[2]), gb[4] = pass<kCopy>(rb[4]);
+    ga[1] = first ? g0 : w1, gb[1] = pass<kCopy>(ra[1]);
+    ga[5] = first ? g1 : w5, gb[5] = pass<kCopy>(ra[5]);
+    ga[8] = first ? g2 : w8, gb[8] = pass<kCopy>(ra[8]);
+    ga[3] = pass<kCopy>(rb[3]), gb[3] = lastl ? g3 : e3;
+    ga[6] = pass<kCopy>(rb[6]), gb[6] = lastl ? g4 : e6;
+    ga[7] = pass<kCopy>(rb[7]), gb[7] = lastl ? g5 : e7;
 }
 
 // One row of the two-column march.  kStage = 2: issue the raw loads of f(y+3) into lf and
@@ -995,8 +1137,8 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
     if (kStage >= 1) {
         dm = dc;
         dc = dp;
-        finish_f2(G, rfa, rfb, rfh, fa, fb, dp);
-        finish_g2(G, rga, rgb, rgh, ga, gb);
+        finish_f2<S>(G, rfa, rfb, rfh, P.ref_f, fa, fb, dp);
+        finish_g2<S>(G, rga, rgb, rgh, P.ref_g, ga, gb);
     }
 }
 
@@ -1039,6 +1181,10 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
         G.gcol = grp == 0 ? l1 : r1;
         G.gdy = pg == 5 || pg == 6 ? -1 : (pg == 7 || pg == 8 ? 1 : 0);
     }
+    if constexpr (sizeof(S) == 2) {
+        G.fref = pick9(P.ref_f, G.fplane);
+        G.gref = pick9(P.ref_g, G.gplane);
+    }
     const size_t total = (size_t)18 * nx * ny * sizeof(S);
     const Planes<S, kBuf> Pin(in, total, G.rowb);
     const Planes<S, kBuf> Pout(out, total, G.rowb);
@@ -1066,10 +1212,10 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
         load_target_row2<S, C, kBuf>(Pin, 9, G, ro[3], ro[2], ro[1], false, P.ref_g, a3, b3, h3);  // g(y0)
         load_target_row2<S, C, kBuf>(Pin, 9, G, ro[4], ro[3], ro[2], false, P.ref_g, rGa, rGb, hG);  // g(y0+1)
         load_target_row2<S, C, kBuf>(Pin, 0, G, ro[5], ro[4], ro[3], true, P.ref_f, rCa, rCb, hC);   // f(y0+2)
-        finish_f2(G, a0, b0, h0, ta, tb, dm);
-        finish_f2(G, a1, b1, h1, fXa, fXb, dc);
-        finish_f2(G, a2, b2, h2, fYa, fYb, dp);
-        finish_g2(G, a3, b3, h3, gAa, gAb);
+        finish_f2<S>(G, a0, b0, h0, P.ref_f, ta, tb, dm);
+        finish_f2<S>(G, a1, b1, h1, P.ref_f, fXa, fXb, dc);
+        finish_f2<S>(G, a2, b2, h2, P.ref_f, fYa, fYb, dp);
+        finish_g2<S>(G, a3, b3, h3, P.ref_g, gAa, gAb);
     }
     // let the prologue's loads land before the loop (as in the one-column form)
 #pragma unroll
