@@ -50,6 +50,15 @@ __device__ __forceinline__ uint4 pack8(const float* f) {
 }
 
 __device__ __forceinline__ bf16x8 as_frag(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Logical index of workgroup b of nb: the hardware deals workgroups to the 8 XCDs
+// round-robin (b mod 8), and this gives each XCD a contiguous range of logical
+// indices, so workgroups that read the same rows (neighbouring pixel tiles, the
+// tiles of one pixel slab) share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, slot = b >> 3;
+    return x * q + min(x, r) + slot;
+}
 __device__ __forceinline__ uint4 sel(bool keep, uint4 v) {
     return keep ? v : make_uint4(0u, 0u, 0u, 0u);
 }
@@ -185,6 +194,118 @@ __global__ void __launch_bounds__(256) k_conv3x3(const ConvArgs a) {
     }
 }
 
+// LDS-staged form of the same convolution for C_in % 32 == 0, P % BM == 0 and
+// C_out % BN == 0.  A workgroup owns BM pixels x BN output channels and walks the
+// reduction in 32-wide chunks (one tap, 32 input channels).  Each chunk's pixel rows
+// (periodically shifted for the tap) and weight rows are loaded once per workgroup
+// with 16-byte loads, stored to LDS, and read back by the four wavefronts as MFMA
+// fragments; the next chunk's global loads are in flight while the current chunk's
+// MFMAs run (two LDS buffers, one barrier per chunk).  Wavefronts are arranged
+// WM x WN over the tile.  The LDS rows hold 32 channels plus 8 of padding (80 bytes):
+// the 16-byte fragment reads of 8 consecutive rows then hit 8 distinct 16-byte bank
+// groups.  The accumulation order per output is the chunk order (tap, channel
+// block), as in k_conv3x3.
+constexpr int kConvPad = 40;
+
+template <int BM, int BN, int WM, int WN, bool kF32>
+__global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
+    static_assert(WM * WN == 4, "four wavefronts");
+    constexpr int WTM = BM / WM, WTN = BN / WN, MT = WTM / 16, NT = WTN / 16;
+    constexpr int AV = BM / 64;              // 16-byte A vectors per thread per chunk
+    constexpr int BV = (BN + 63) / 64;       // B vectors per thread (some threads idle for BN = 32)
+    __shared__ __attribute__((aligned(16))) bf16_t As[2][BM][kConvPad];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN][kConvPad];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // flat grid: the column tiles of one pixel tile are adjacent, pixel tiles follow in order
+    const int ctiles = a.Cout / BN, L = xcd_block(blockIdx.x, gridDim.x);
+    const int p0 = (L / ctiles) * BM, co0 = (L % ctiles) * BN;
+    const int Hm = (1 << a.lh) - 1, Wm = (1 << a.lw) - 1;
+    const int K = 9 * a.Cin, cpt = a.Cin >> 5, nch = 9 * cpt;
+    // loader roles: channels 8 lv .. 8 lv + 7 of the chunk, rows lr + 64 j
+    const int lv = t & 3, lr = t >> 2;
+    int pimg[AV], py[AV], px[AV];
+#pragma unroll
+    for (int j = 0; j < AV; ++j) {
+        const int p = p0 + lr + 64 * j;
+        px[j] = p & Wm;
+        py[j] = (p >> a.lw) & Hm;
+        pimg[j] = (p >> (a.lw + a.lh)) << (a.lw + a.lh);
+    }
+    const bf16_t* wrow[BV];
+    bool bon[BV];
+#pragma unroll
+    for (int j = 0; j < BV; ++j) {
+        const int r = lr + 64 * j;
+        bon[j] = r < BN;
+        wrow[j] = a.w + (size_t)(co0 + (bon[j] ? r : 0)) * K + 8 * lv;
+    }
+    uint4 ra[AV], rb[BV];
+    auto load = [&](int ch) {
+        const int tap = ch / cpt, c0 = (ch - tap * cpt) << 5;
+        const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
+#pragma unroll
+        for (int j = 0; j < AV; ++j) {
+            const int ys = (py[j] + dy) & Hm, xs = (px[j] + dx) & Wm;
+            ra[j] = ld16(a.x + (size_t)(pimg[j] + (ys << a.lw) + xs) * a.ldx + c0 + 8 * lv);
+        }
+#pragma unroll
+        for (int j = 0; j < BV; ++j)
+            if (bon[j]) rb[j] = ld16(wrow[j] + tap * a.Cin + c0);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < AV; ++j) *reinterpret_cast<uint4*>(&As[buf][lr + 64 * j][8 * lv]) = ra[j];
+#pragma unroll
+        for (int j = 0; j < BV; ++j)
+            if (bon[j]) *reinterpret_cast<uint4*>(&Bs[buf][lr + 64 * j][8 * lv]) = rb[j];
+    };
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int wm = (wave % WM) * WTM, wn = (wave / WM) * WTN;
+    const int r16 = lane & 15, k8 = 8 * (lane >> 4);
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) load(ch + 1);
+        uint4 A[MT], B[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) A[m] = *reinterpret_cast<const uint4*>(&As[buf][wm + 16 * m + r16][k8]);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) B[n] = *reinterpret_cast<const uint4*>(&Bs[buf][wn + 16 * n + r16][k8]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]), acc[m][n], 0, 0, 0);
+        // the other buffer was last read before the previous barrier
+        if (ch + 1 < nch) store(buf ^ 1);
+        __syncthreads();
+    }
+    const int g4 = 4 * (lane >> 4);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = co0 + wn + 16 * n + r16;
+        const float b = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = p0 + wm + 16 * m + g4 + r;
+                float v = acc[m][n][r] + b;
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.mask && !(bf2f(a.mask[(size_t)p * a.ldm + co]) > 0.f)) v = 0.f;
+                if (kF32) static_cast<float*>(a.y)[(size_t)p * a.ldy + co] = v;
+                else static_cast<bf16_t*>(a.y)[(size_t)p * a.ldy + co] = (bf16_t)f2bf(v);
+            }
+        }
+    }
+}
+
 // wf[i][t][o] = w[o][8-t][i]
 __global__ void k_flip(const bf16_t* __restrict__ w, bf16_t* __restrict__ wf, int Cout, int Cin) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,6 +330,7 @@ struct WgArgs {
     float* part;          // [slabs][Cout][Kt]
     int ldx, ldg;
     int lh, lw, P, Cin, Cout, K, Kt, slab;
+    int ktiles, ctiles;   // k_wgrad_tr's flat grid: ktiles x ctiles x slabs
 };
 
 constexpr int kLdsPad = 40;  // 32 pixels + 8: rows stay 16-byte aligned
@@ -293,6 +415,133 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) part[(size_t)co * a.Kt + kb + wk + 16 * i + g4 + r] = acc[i][j][r];
     }
+}
+
+// Weight gradient with the transposing LDS read of gfx950 (ds_read_b64_tr_b16), for
+// C_out % 32 == 0.  MFMA rows are output channels, columns im2col columns k, the
+// reduction runs over pixels.  Chunks of PC pixels of g ([pixel][channel]) and of the
+// im2col rows X ([pixel][k]) are stored to LDS as loaded (16-byte vectors, no
+// transposition on the way in).  An MFMA operand needs 8 consecutive pixels of one
+// row: within each group of 16 lanes, the transposing read hands lane l element
+// l mod 4 of the 8-byte chunk addressed by lane 4j + l/4 (j = 0..3), so when lane
+// 4j + q addresses row p + j, columns c + 4q .. c + 4q + 3, lane l receives rows
+// p .. p+3 of column c + l; two such reads give the 8 pixels of a fragment.  The row
+// pitches (BO + 16 and BK + 16 elements) put the 4 rows of one read at distinct
+// 32-byte bank groups.  Two LDS buffers, one barrier per chunk; 2 x 2 wavefronts of
+// (BO/2) x (BK/2).  The partial sums per pixel slab are stored as by k_wgrad.
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+template <int PITCH>
+__device__ __forceinline__ bf16x8 tr_frag(const bf16_t (*T)[PITCH], int p0, int c0, int lane) {
+    const int g = lane >> 4, i = lane & 15;
+    const bf16_t* q = &T[p0 + 8 * g + (i >> 2)][c0 + 4 * (i & 3)];
+    typedef __attribute__((address_space(3))) v4s lds_v4s;
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q));
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q + 4 * PITCH));
+    uint4 u;
+    u.x = (uint32_t)(uint16_t)lo[0] | ((uint32_t)(uint16_t)lo[1] << 16);
+    u.y = (uint32_t)(uint16_t)lo[2] | ((uint32_t)(uint16_t)lo[3] << 16);
+    u.z = (uint32_t)(uint16_t)hi[0] | ((uint32_t)(uint16_t)hi[1] << 16);
+    u.w = (uint32_t)(uint16_t)hi[2] | ((uint32_t)(uint16_t)hi[3] << 16);
+    return as_frag(u);
+}
+
+template <int BO, int BK, int PC>
+__global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
+    constexpr int PO = BO + 16, PK = BK + 16;
+    constexpr int WO = BO / 2, WK = BK / 2, MT = WO / 16, NT = WK / 16;
+    constexpr int GVR = BO / 8, XVR = BK / 8;            // vectors per LDS row
+    constexpr int GV = PC * GVR / 256, XV = PC * XVR / 256;  // vectors per thread per chunk
+    static_assert(GV >= 1 && XV >= 1, "tile too small for the loader");
+    __shared__ __attribute__((aligned(16))) bf16_t Gs[2][PC][PO];
+    __shared__ __attribute__((aligned(16))) bf16_t Xs[2][PC][PK];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // flat grid: the k and channel tiles of one pixel slab are adjacent
+    const int L = xcd_block(blockIdx.x, gridDim.x);
+    const int kt = L % a.ktiles, rest = L / a.ktiles, ct = rest % a.ctiles, z = rest / a.ctiles;
+    const int kb = kt * BK, cb = ct * BO;
+    const int pbeg = z * a.slab;
+    const int pend = min(a.P, pbeg + a.slab);
+    const int Hm = (1 << a.lh) - 1, Wm = (1 << a.lw) - 1;
+    // loaders: g rows t / GVR + j 256 / GVR, channels cb + 8 (t % GVR); X rows likewise,
+    // columns kb + 8 (t % XVR)
+    const int gcol = 8 * (t % GVR), grow = t / GVR;
+    const int xcol = 8 * (t % XVR), xrow = t / XVR;
+    const int kx = kb + xcol;
+    const int mode = kx < a.K ? 0 : (kx == a.K ? 1 : 2);  // data, bias column, zero
+    const int tap = mode == 0 ? kx / a.Cin : 0;
+    const int ci = mode == 0 ? kx - tap * a.Cin : 0;
+    const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
+    uint4 gv[GV], xv[XV];
+    auto load = [&](int pc) {
+#pragma unroll
+        for (int j = 0; j < GV; ++j) {
+            const int pp = pc + grow + j * (256 / GVR);
+            const bool ok = pp < pend;
+            gv[j] = sel(ok, ld16(a.g + (size_t)(ok ? pp : pbeg) * a.ldg + cb + gcol));
+        }
+#pragma unroll
+        for (int j = 0; j < XV; ++j) {
+            const int pp = pc + xrow + j * (256 / XVR);
+            const bool ok = pp < pend;
+            const int q = ok ? pp : pbeg;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (mode == 0) {
+                const int base = (q >> (a.lw + a.lh)) << (a.lw + a.lh);
+                const int ys = ((q >> a.lw) + dy) & Hm, xs = ((q & Wm) + dx) & Wm;
+                v = ld16(a.x + (size_t)(base + (ys << a.lw) + xs) * a.ldx + ci);
+            } else if (mode == 1) {
+                v.x = 0x3f80u;  // bfloat16 1.0 in column K: the bias gradient
+            }
+            xv[j] = sel(ok, v);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < GV; ++j) *reinterpret_cast<uint4*>(&Gs[buf][grow + j * (256 / GVR)][gcol]) = gv[j];
+#pragma unroll
+        for (int j = 0; j < XV; ++j) *reinterpret_cast<uint4*>(&Xs[buf][xrow + j * (256 / XVR)][xcol]) = xv[j];
+    };
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int wo = (wave & 1) * WO, wk = (wave >> 1) * WK;
+    load(pbeg);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int pc = pbeg; pc < pend; pc += PC) {
+        const bool more = pc + PC < pend;
+        if (more) load(pc + PC);
+#pragma unroll
+        for (int ks = 0; ks < PC; ks += 32) {
+            bf16x8 A[MT], B[NT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) A[m] = tr_frag<PO>(Gs[buf], ks, wo + 16 * m, lane);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) B[n] = tr_frag<PK>(Xs[buf], ks, wk + 16 * n, lane);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m], B[n], acc[m][n], 0, 0, 0);
+        }
+        // the other buffer was last read before the previous barrier
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    float* part = a.part + (size_t)z * a.Cout * a.Kt;
+    const int i16 = lane & 15, g4 = 4 * (lane >> 4);
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                part[(size_t)(cb + wo + 16 * m + g4 + r) * a.Kt + kb + wk + 16 * n + i16] = acc[m][n][r];
 }
 
 // dw[o][k] = sum_s part[s][o][k] (k < K), db[o] = sum_s part[s][o][K]; slabs in order
@@ -650,8 +899,31 @@ void launch_conv(const ConvArgs& a, bool tap_outer, bool f32, hipStream_t s) {
     }
 }
 
+template <int BM, int BN, int WM, int WN>
+void launch_lds(const ConvArgs& a, bool f32, hipStream_t s) {
+    const dim3 grid((a.P / BM) * (a.Cout / BN));
+    if (f32) hipLaunchKernelGGL((k_conv_lds<BM, BN, WM, WN, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_conv_lds<BM, BN, WM, WN, false>), grid, dim3(256), 0, s, a);
+}
+
+// The LDS-staged kernel where its shape conditions hold; false: use k_conv3x3.
+bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
+    if (a.Cin % 32) return false;
+    if (a.Cout % 128 == 0 && a.P % 128 == 0) {
+        launch_lds<128, 128, 2, 2>(a, f32, s);
+    } else if (a.Cout % 64 == 0 && a.P % 256 == 0) {
+        launch_lds<256, 64, 4, 1>(a, f32, s);
+    } else if (a.Cout % 32 == 0 && a.P % 256 == 0) {
+        launch_lds<256, 32, 4, 1>(a, f32, s);
+    } else {
+        return false;
+    }
+    return true;
+}
+
 struct WgPlan {
     int ktiles, ctiles, CT, slabs, slab, Kt;
+    bool tr;  // k_wgrad_tr (C_out % 32 == 0), else k_wgrad
 };
 
 WgPlan wgrad_plan(int P, int Cin, int Cout) {
@@ -661,12 +933,13 @@ WgPlan wgrad_plan(int P, int Cin, int Cout) {
     w.Kt = 64 * w.ktiles;
     w.CT = Cout % 64 == 0 ? 64 : 32;
     w.ctiles = (Cout + w.CT - 1) / w.CT;
+    w.tr = Cout % 32 == 0;
     const int want = 1024;  // workgroups to aim for: four per CU; longer slabs keep the partials small
     int slabs = (want + w.ktiles * w.ctiles - 1) / (w.ktiles * w.ctiles);
     const int max_slabs = (P + 255) / 256;  // at least 256 pixels per slab
     if (slabs > max_slabs) slabs = max_slabs;
     if (slabs < 1) slabs = 1;
-    w.slab = ((P + slabs - 1) / slabs + 31) / 32 * 32;
+    w.slab = ((P + slabs - 1) / slabs + 63) / 64 * 64;  // whole 64-pixel chunks
     w.slabs = (P + w.slab - 1) / w.slab;
     return w;
 }
@@ -708,8 +981,10 @@ int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, co
     a.relu = (flags & UNET_RELU) ? 1 : 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool tap_outer = C_in % 32 == 0;
-    if (C_out % 64 == 0) launch_conv<2, 4>(a, tap_outer, f32, s);
-    else launch_conv<4, 2>(a, tap_outer, f32, s);
+    if (!launch_conv_lds(a, f32, s)) {
+        if (C_out % 64 == 0) launch_conv<2, 4>(a, tap_outer, f32, s);
+        else launch_conv<4, 2>(a, tap_outer, f32, s);
+    }
     return launched("conv3x3 launch");
 }
 
@@ -757,10 +1032,18 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
     a.K = 9 * C_in;
     a.Kt = p.Kt;
     a.slab = p.slab;
+    a.ktiles = p.ktiles;
+    a.ctiles = p.ctiles;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const dim3 grid(p.ktiles, p.ctiles, p.slabs);
-    if (p.CT == 64) hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_wgrad<32>), grid, dim3(256), 0, s, a);
+    if (p.tr) {
+        const dim3 flat(p.ktiles * p.ctiles * p.slabs);
+        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_tr<64, 64, 64>), flat, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_wgrad_tr<32, 64, 64>), flat, dim3(256), 0, s, a);
+    } else {
+        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_wgrad<32>), grid, dim3(256), 0, s, a);
+    }
     if ((r = launched("wgrad launch"))) return r;
     const int n = C_out * (a.K + 1);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, a.part, dw, db, p.slabs, C_out, a.K,

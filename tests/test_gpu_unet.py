@@ -66,10 +66,13 @@ def ck(code):
 
 CONV_CASES = [  # N, H, W, Cin, Cout
     (3, 4, 8, 8, 16),      # generic reduction path (C_in = 8), ragged pixel tail, partial channel tile
-    (2, 8, 16, 32, 32),
+    (2, 8, 16, 32, 32),    # LDS-staged form, 256 x 32 tiles
     (1, 16, 8, 40, 64),    # C_in not a multiple of 32: chunks straddle taps
-    (2, 8, 8, 96, 96),     # C_out = 96: three 32-wide tiles
-    (1, 32, 32, 64, 128),
+    (2, 8, 8, 96, 96),     # C_out = 96: three 32-wide tiles (pixel count below the LDS tile)
+    (1, 32, 32, 64, 128),  # LDS-staged form, 128 x 128 tiles
+    (1, 16, 16, 64, 64),   # LDS-staged form, 256 x 64 tiles
+    (1, 16, 16, 32, 96),   # LDS-staged form, three 32-wide column tiles
+    (1, 16, 16, 128, 256), # LDS-staged form, four channel blocks per tap, two column tiles
 ]
 
 
@@ -114,7 +117,7 @@ def test_conv3x3_relu_mask_bf16_and_strided_output():
     assert (got[..., 16:48][ref == 0] == 0).all()
 
 
-@pytest.mark.parametrize("case", [(2, 8, 16, 32, 32), (1, 16, 16, 96, 32), (2, 8, 8, 64, 128)],
+@pytest.mark.parametrize("case", [(2, 8, 16, 32, 32), (1, 16, 16, 96, 32), (2, 8, 8, 64, 128), (2, 16, 16, 64, 128)],
                          ids=lambda c: "x".join(map(str, c)))
 def test_conv3x3_input_gradient_by_flipped_weights(case):
     import torch
