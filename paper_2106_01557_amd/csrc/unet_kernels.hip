@@ -34,6 +34,12 @@ __device__ __forceinline__ uint32_t f2bf(float f) {
     return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
+// round to nearest even with the gfx950 conversion instruction (same result as f2bf
+// for every finite value)
+__device__ __forceinline__ uint32_t f2bf_hw(float f) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)f);
+}
+
 __device__ __forceinline__ uint4 ld16(const bf16_t* p) { return *reinterpret_cast<const uint4*>(p); }
 __device__ __forceinline__ void st16(bf16_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
 
@@ -201,11 +207,13 @@ __global__ void __launch_bounds__(256) k_conv3x3(const ConvArgs a) {
 // with 16-byte loads, stored to LDS, and read back by the four wavefronts as MFMA
 // fragments; the next chunk's global loads are in flight while the current chunk's
 // MFMAs run (two LDS buffers, one barrier per chunk).  Wavefronts are arranged
-// WM x WN over the tile.  The LDS rows hold 32 channels plus 8 of padding (80 bytes):
-// the 16-byte fragment reads of 8 consecutive rows then hit 8 distinct 16-byte bank
+// WM x WN over the tile.  An LDS row holds the 32 channels of one pixel (or weight
+// row) as four 16-byte pieces, piece j stored at slot j ^ ((row >> 1) & 3): the
+// 16-byte accesses of 8 consecutive lanes (8 rows of one piece for the fragment
+// reads, 2 rows of 4 pieces for the stores) then fall in 8 distinct 16-byte bank
 // groups.  The accumulation order per output is the chunk order (tap, channel
 // block), as in k_conv3x3.
-constexpr int kConvPad = 40;
+__device__ __forceinline__ int swz(int row, int piece) { return 8 * (piece ^ ((row >> 1) & 3)); }
 
 template <int BM, int BN, int WM, int WN, bool kF32>
 __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
@@ -213,8 +221,12 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     constexpr int WTM = BM / WM, WTN = BN / WN, MT = WTM / 16, NT = WTN / 16;
     constexpr int AV = BM / 64;              // 16-byte A vectors per thread per chunk
     constexpr int BV = (BN + 63) / 64;       // B vectors per thread (some threads idle for BN = 32)
-    __shared__ __attribute__((aligned(16))) bf16_t As[2][BM][kConvPad];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN][kConvPad];
+    constexpr int AS = BM * 32, BS = BN * 32;
+    constexpr int OP = BN + 8;               // pitch of the bf16 output tile staged at the end
+    constexpr int SM = 2 * (AS + BS) > BM * OP ? 2 * (AS + BS) : BM * OP;
+    __shared__ __attribute__((aligned(16))) bf16_t sm[SM];
+    bf16_t(*As)[BM][32] = reinterpret_cast<bf16_t(*)[BM][32]>(sm);
+    bf16_t(*Bs)[BN][32] = reinterpret_cast<bf16_t(*)[BN][32]>(sm + 2 * AS);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     // flat grid: the column tiles of one pixel tile are adjacent, pixel tiles follow in order
     const int ctiles = a.Cout / BN, L = xcd_block(blockIdx.x, gridDim.x);
@@ -254,10 +266,15 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int j = 0; j < AV; ++j) *reinterpret_cast<uint4*>(&As[buf][lr + 64 * j][8 * lv]) = ra[j];
+        for (int j = 0; j < AV; ++j) {
+            const int r = lr + 64 * j;
+            *reinterpret_cast<uint4*>(&As[buf][r][swz(r, lv)]) = ra[j];
+        }
 #pragma unroll
-        for (int j = 0; j < BV; ++j)
-            if (bon[j]) *reinterpret_cast<uint4*>(&Bs[buf][lr + 64 * j][8 * lv]) = rb[j];
+        for (int j = 0; j < BV; ++j) {
+            const int r = lr + 64 * j;
+            if (bon[j]) *reinterpret_cast<uint4*>(&Bs[buf][r][swz(r, lv)]) = rb[j];
+        }
     };
     f32x4 acc[MT][NT];
 #pragma unroll
@@ -265,7 +282,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int wm = (wave % WM) * WTM, wn = (wave / WM) * WTN;
-    const int r16 = lane & 15, k8 = 8 * (lane >> 4);
+    const int r16 = lane & 15, k4 = lane >> 4;
     load(0);
     store(0);
     __syncthreads();
@@ -274,9 +291,15 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
         if (ch + 1 < nch) load(ch + 1);
         uint4 A[MT], B[NT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) A[m] = *reinterpret_cast<const uint4*>(&As[buf][wm + 16 * m + r16][k8]);
+        for (int m = 0; m < MT; ++m) {
+            const int r = wm + 16 * m + r16;
+            A[m] = *reinterpret_cast<const uint4*>(&As[buf][r][swz(r, k4)]);
+        }
 #pragma unroll
-        for (int n = 0; n < NT; ++n) B[n] = *reinterpret_cast<const uint4*>(&Bs[buf][wn + 16 * n + r16][k8]);
+        for (int n = 0; n < NT; ++n) {
+            const int r = wn + 16 * n + r16;
+            B[n] = *reinterpret_cast<const uint4*>(&Bs[buf][r][swz(r, k4)]);
+        }
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -287,21 +310,61 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
         __syncthreads();
     }
     const int g4 = 4 * (lane >> 4);
+    if constexpr (kF32) {
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        const int co = co0 + wn + 16 * n + r16;
-        const float b = a.bias ? a.bias[co] : 0.f;
+        for (int n = 0; n < NT; ++n) {
+            const int co = co0 + wn + 16 * n + r16;
+            const float b = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
+            for (int m = 0; m < MT; ++m) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int p = p0 + wm + 16 * m + g4 + r;
-                float v = acc[m][n][r] + b;
-                if (a.relu) v = fmaxf(v, 0.f);
-                if (a.mask && !(bf2f(a.mask[(size_t)p * a.ldm + co]) > 0.f)) v = 0.f;
-                if (kF32) static_cast<float*>(a.y)[(size_t)p * a.ldy + co] = v;
-                else static_cast<bf16_t*>(a.y)[(size_t)p * a.ldy + co] = (bf16_t)f2bf(v);
+                for (int r = 0; r < 4; ++r) {
+                    const int p = p0 + wm + 16 * m + g4 + r;
+                    float v = acc[m][n][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    if (a.mask && !(bf2f(a.mask[(size_t)p * a.ldm + co]) > 0.f)) v = 0.f;
+                    static_cast<float*>(a.y)[(size_t)p * a.ldy + co] = v;
+                }
             }
+        }
+    } else {
+        // bf16 output: bias and ReLU into a tile in LDS (the staging buffers are free
+        // after the last barrier), then 16-byte stores of 8 channels with the mask
+        // applied per vector; zeroing after rounding equals rounding after zeroing
+        bf16_t* Os = sm;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int c = wn + 16 * n + r16;
+            const float b = a.bias ? a.bias[co0 + c] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[m][n][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    Os[(wm + 16 * m + g4 + r) * OP + c] = (bf16_t)f2bf_hw(v);
+                }
+            }
+        }
+        __syncthreads();
+        constexpr int VR = BN / 8;
+        for (int v = t; v < BM * VR; v += 256) {
+            const int row = v / VR, cv = v - row * VR;
+            const size_t p = (size_t)(p0 + row);
+            const int co = co0 + 8 * cv;
+            uint4 o = *reinterpret_cast<const uint4*>(&Os[row * OP + 8 * cv]);
+            if (a.mask) {
+                const uint4 mk = ld16(a.mask + p * a.ldm + co);
+                const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+                uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t keep = (lo(mw[j]) > 0.f ? 0xffffu : 0u) | (hi(mw[j]) > 0.f ? 0xffff0000u : 0u);
+                    ow[j] &= keep;
+                }
+                o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+            }
+            st16(static_cast<bf16_t*>(a.y) + p * a.ldy + co, o);
         }
     }
 }
@@ -907,14 +970,16 @@ void launch_lds(const ConvArgs& a, bool f32, hipStream_t s) {
 }
 
 // The LDS-staged kernel where its shape conditions hold; false: use k_conv3x3.
+// bf16 output is written in 16-byte vectors: it needs an aligned output and stride.
 bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
     if (a.Cin % 32) return false;
+    if (!f32 && (!aligned16(a.y) || a.ldy % 8)) return false;
     if (a.Cout % 128 == 0 && a.P % 128 == 0) {
         launch_lds<128, 128, 2, 2>(a, f32, s);
     } else if (a.Cout % 64 == 0 && a.P % 256 == 0) {
         launch_lds<256, 64, 4, 1>(a, f32, s);
-    } else if (a.Cout % 32 == 0 && a.P % 256 == 0) {
-        launch_lds<256, 32, 4, 1>(a, f32, s);
+    } else if (a.Cout % 32 == 0 && a.P % 128 == 0) {
+        launch_lds<128, 32, 4, 1>(a, f32, s);
     } else {
         return false;
     }
