@@ -10,6 +10,7 @@
 // channels of one pixel: one 16-byte load.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -490,8 +491,9 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgArgs a) {
 // 4j + q addresses row p + j, columns c + 4q .. c + 4q + 3, lane l receives rows
 // p .. p+3 of column c + l; two such reads give the 8 pixels of a fragment.  The row
 // pitches (BO + 16 and BK + 16 elements) put the 4 rows of one read at distinct
-// 32-byte bank groups.  Two LDS buffers, one barrier per chunk; 2 x 2 wavefronts of
-// (BO/2) x (BK/2).  The partial sums per pixel slab are stored as by k_wgrad.
+// 32-byte bank groups.  Two LDS buffers, one barrier per chunk; WOW x (4 / WOW)
+// wavefronts of (BO / WOW) x (BK / (4 / WOW)).  The partial sums per pixel slab are
+// stored as by k_wgrad.
 typedef short v4s __attribute__((ext_vector_type(4)));
 
 template <int PITCH>
@@ -509,10 +511,11 @@ __device__ __forceinline__ bf16x8 tr_frag(const bf16_t (*T)[PITCH], int p0, int 
     return as_frag(u);
 }
 
-template <int BO, int BK, int PC>
+template <int BO, int BK, int PC, int WOW>
 __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
     constexpr int PO = BO + 16, PK = BK + 16;
-    constexpr int WO = BO / 2, WK = BK / 2, MT = WO / 16, NT = WK / 16;
+    constexpr int WKW = 4 / WOW;
+    constexpr int WO = BO / WOW, WK = BK / WKW, MT = WO / 16, NT = WK / 16;
     constexpr int GVR = BO / 8, XVR = BK / 8;            // vectors per LDS row
     constexpr int GV = PC * GVR / 256, XV = PC * XVR / 256;  // vectors per thread per chunk
     static_assert(GV >= 1 && XV >= 1, "tile too small for the loader");
@@ -570,7 +573,7 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int wo = (wave & 1) * WO, wk = (wave >> 1) * WK;
+    const int wo = (wave % WOW) * WO, wk = (wave / WOW) * WK;
     load(pbeg);
     store(0);
     __syncthreads();
@@ -607,25 +610,35 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
                 part[(size_t)(cb + wo + 16 * m + g4 + r) * a.Kt + kb + wk + 16 * n + i16] = acc[m][n][r];
 }
 
-// dw[o][k] = sum_s part[s][o][k] (k < K), db[o] = sum_s part[s][o][K]; slabs in order
-__global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, float* __restrict__ db,
-                               int slabs, int Cout, int K, int Kt) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Cout * (K + 1)) return;
-    const int o = idx / (K + 1), k = idx - o * (K + 1);
+// dw[o][k] = sum_s part[s][o][k] (k < K), db[o] = sum_s part[s][o][K].  A workgroup
+// takes 64 consecutive outputs (one per lane) and its four wavefronts take slabs
+// w, w + 4, w + 8, ... each with four running sums (slab index mod 16), which are
+// combined in a fixed order, then the four wavefronts' sums in a fixed order:
+// deterministic for a given slab count.
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw,
+                                                      float* __restrict__ db, int slabs, int Cout, int K, int Kt) {
+    __shared__ float sm[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int idx = blockIdx.x * 64 + lane;
+    const bool on = idx < Cout * (K + 1);
+    const int o = on ? idx / (K + 1) : 0, k = on ? idx - o * (K + 1) : 0;
     const size_t stride = (size_t)Cout * Kt;
     const float* q = part + (size_t)o * Kt + k;
-    // four independent chains (z mod 4), combined in a fixed order: deterministic
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    int z = 0;
-    for (; z + 4 <= slabs; z += 4) {
-        a0 += q[(size_t)z * stride];
-        a1 += q[(size_t)(z + 1) * stride];
-        a2 += q[(size_t)(z + 2) * stride];
-        a3 += q[(size_t)(z + 3) * stride];
+    if (on) {
+        int z = wave;
+        for (; z + 12 < slabs; z += 16) {
+            a0 += q[(size_t)z * stride];
+            a1 += q[(size_t)(z + 4) * stride];
+            a2 += q[(size_t)(z + 8) * stride];
+            a3 += q[(size_t)(z + 12) * stride];
+        }
+        for (; z < slabs; z += 4) a0 += q[(size_t)z * stride];
     }
-    for (; z < slabs; ++z) a0 += q[(size_t)z * stride];
-    const float s = (a0 + a1) + (a2 + a3);
+    sm[wave][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (wave != 0 || !on) return;
+    const float s = (sm[0][lane] + sm[1][lane]) + (sm[2][lane] + sm[3][lane]);
     if (k < K) dw[(size_t)o * K + k] = s;
     else if (db) db[o] = s;
 }
@@ -824,34 +837,62 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// part: [blocks * 4 wavefronts][K (C + 1)]: per-wavefront sums of dout_k d[., c] and of dout_k
+// part: [blocks * 4 wavefronts][K (C + 1)]: per-wavefront sums of dout_k d[., c] and of
+// dout_k.  Grid-stride over pixels (thread t takes pixels t, t + nt, ...), one pass
+// per 8-channel group: the input gradient of those channels is stored, and the
+// thread's products are summed in registers, then reduced across the wavefront once
+// per group (a fixed assignment and order, so the sums are deterministic).
+constexpr int kHeadBwdBlocks = 1024;
+
 __global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ldd, const float* hw,
                                                          const float* dout, bf16_t* g, float* part, int C, int K,
                                                          int P) {
-    const int p = blockIdx.x * kHeadBlock + threadIdx.x;
+    const int t = blockIdx.x * kHeadBlock + threadIdx.x, nt = gridDim.x * kHeadBlock;
     const int lane = threadIdx.x & 63;
-    float dp[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < K; ++k) dp[k] = p < P ? dout[(size_t)k * P + p] : 0.f;
     const size_t row = ((size_t)blockIdx.x * (kHeadBlock / 64) + (threadIdx.x >> 6)) * K * (C + 1);
     for (int c = 0; c < C; c += 8) {
-        float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, o[8];
-        if (p < P) unpack8(ld16(d + (size_t)p * ldd + c), v);
+        float acc[4][8], w[4][8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            float s = 0.f;
-            for (int k = 0; k < K; ++k) s += dp[k] * hw[k * C + c + j];
-            o[j] = v[j] > 0.f ? s : 0.f;
-        }
-        if (p < P) st16(g + (size_t)p * C + c, pack8(o));
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const float b = wave_sum(dp[k] * v[j]);
+                acc[k][j] = 0.f;
+                w[k][j] = k < K ? hw[k * C + c + j] : 0.f;
+            }
+        for (int p = t; p < P; p += nt) {
+            float dp[4], v[8], o[8];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dp[k] = k < K ? dout[(size_t)k * P + p] : 0.f;
+            unpack8(ld16(d + (size_t)p * ldd + c), v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                float s = 0.f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < K) s += dp[k] * w[k][j];
+                o[j] = v[j] > 0.f ? s : 0.f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k][j] += dp[k] * v[j];
+            }
+            st16(g + (size_t)p * C + c, pack8(o));
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k >= K) break;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float b = wave_sum(acc[k][j]);
                 if (lane == 0) part[row + (size_t)k * (C + 1) + c + j] = b;
             }
+        }
     }
+    float bs[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int p = t; p < P; p += nt)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < K) bs[k] += dout[(size_t)k * P + p];
     for (int k = 0; k < K; ++k) {
-        const float b = wave_sum(dp[k]);
+        const float b = wave_sum(bs[k]);
         if (lane == 0) part[row + (size_t)k * (C + 1) + C] = b;
     }
 }
@@ -994,11 +1035,12 @@ struct WgPlan {
 WgPlan wgrad_plan(int P, int Cin, int Cout) {
     WgPlan w;
     const int K = 9 * Cin;
-    w.ktiles = (K + 1 + 63) / 64;
-    w.Kt = 64 * w.ktiles;
+    w.tr = Cout % 32 == 0;
+    const int BK = w.tr ? 128 : 64;  // k columns per workgroup
+    w.ktiles = (K + 1 + BK - 1) / BK;
+    w.Kt = BK * w.ktiles;
     w.CT = Cout % 64 == 0 ? 64 : 32;
     w.ctiles = (Cout + w.CT - 1) / w.CT;
-    w.tr = Cout % 32 == 0;
     const int want = 1024;  // workgroups to aim for: four per CU; longer slabs keep the partials small
     int slabs = (want + w.ktiles * w.ctiles - 1) / (w.ktiles * w.ctiles);
     const int max_slabs = (P + 255) / 256;  // at least 256 pixels per slab
@@ -1103,15 +1145,15 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
     const dim3 grid(p.ktiles, p.ctiles, p.slabs);
     if (p.tr) {
         const dim3 flat(p.ktiles * p.ctiles * p.slabs);
-        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_tr<64, 64, 64>), flat, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_wgrad_tr<32, 64, 64>), flat, dim3(256), 0, s, a);
+        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_tr<64, 128, 64, 2>), flat, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_wgrad_tr<32, 128, 64, 1>), flat, dim3(256), 0, s, a);
     } else {
         if (p.CT == 64) hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_wgrad<32>), grid, dim3(256), 0, s, a);
     }
     if ((r = launched("wgrad launch"))) return r;
     const int n = C_out * (a.K + 1);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, a.part, dw, db, p.slabs, C_out, a.K,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 63) / 64), dim3(256), 0, s, a.part, dw, db, p.slabs, C_out, a.K,
                        p.Kt);
     return launched("wgrad reduce launch");
 }
@@ -1244,7 +1286,9 @@ int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout
     if ((r = check_tensor("d", d, ldd, 0, C, false)) || (r = check_tensor("g", g, C, 0, C, false))) return r;
     if (!hw || !dout || !dhw || !dhb || !partials || partial_bytes < need)
         return fail(UNET_EINVAL, "head bwd: NULL argument or partials below %zu bytes", need);
-    const int P = N * H * W, blocks = (P + kHeadBlock - 1) / kHeadBlock;
+    const int P = N * H * W;
+    // no more workgroups than the forward pass uses, so its partials buffer suffices
+    const int blocks = std::min((P + kHeadBlock - 1) / kHeadBlock, kHeadBwdBlocks);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(kHeadBlock), 0, s, static_cast<const bf16_t*>(d), ldd, hw, dout,
                        static_cast<bf16_t*>(g), static_cast<float*>(partials), C, K, P);

@@ -124,16 +124,30 @@ class UNet:
         return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
 
     def load_params(self, p: dict):
+        """Parameters, Adam moments, gradients and bfloat16 copies are views into flat
+        buffers (each tensor starts at a multiple of 16 elements, so every view stays
+        16-byte aligned and the padding stays zero), so that one Adam launch updates
+        them all."""
         torch = self.torch
+        offs, total = {}, 0
+        for k, v in p.items():
+            n = int(np.asarray(v).size)
+            offs[k] = (total, n)
+            total += (n + 15) // 16 * 16
+        self._offs, self._total = offs, total
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
-            self.p = {k: self._f32(v).reshape(-1) for k, v in p.items()}
-            self.m = {k: torch.zeros_like(v) for k, v in self.p.items()}
-            self.v = {k: torch.zeros_like(v) for k, v in self.p.items()}
+            z = lambda dt: torch.zeros(total, dtype=dt, device=self.device)  # noqa: E731
+            self.flat, self.mflat, self.vflat, self.gflat = (z(torch.float32) for _ in range(4))
+            self.w16flat = z(torch.bfloat16)
+            view = lambda buf: {k: buf[o:o + n] for k, (o, n) in offs.items()}  # noqa: E731
+            self.p, self.m, self.v, self.g = view(self.flat), view(self.mflat), view(self.vflat), view(self.gflat)
+            for k, v in p.items():
+                self.p[k].copy_(self._f32(v).reshape(-1))
+            w16 = view(self.w16flat)
             self.w16, self.wf16 = {}, {}
             for name, ci, co in self.layers:
-                w = self.p[name + ".w"]
-                self.w16[name] = torch.empty(w.numel(), dtype=torch.bfloat16, device=self.device)
-                self.wf16[name] = torch.empty(w.numel(), dtype=torch.bfloat16, device=self.device)
+                self.w16[name] = w16[name + ".w"]
+                self.wf16[name] = torch.empty(self.w16[name].numel(), dtype=torch.bfloat16, device=self.device)
             self._refresh_copies()
         self.t = 0
 
@@ -198,7 +212,6 @@ class UNet:
             b["wpart"] = torch.empty(need, dtype=torch.uint8, device=self.device)
             b["hpart"] = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
             b["loss"] = f32(1)
-            self.g = {k: torch.zeros_like(v) for k, v in self.p.items()}
         self.buf = b
         self._shape = (N, H, W)
 
@@ -312,11 +325,9 @@ class UNet:
         torch = self.torch
         self.t += 1
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
-            for k, p in self.p.items():
-                name = k[:-2]
-                p16 = self.w16[name] if (k.endswith(".w") and name in self.w16) else None
-                _ck(_lib.unet_adam(ptr(p), ptr(self.g[k]), ptr(self.m[k]), ptr(self.v[k]), ptr(p16), p.numel(), lr,
-                                   b1, b2, eps, self.t, self.s))
+            # one launch over the flat buffers; it also refreshes every bfloat16 copy
+            _ck(_lib.unet_adam(ptr(self.flat), ptr(self.gflat), ptr(self.mflat), ptr(self.vflat), ptr(self.w16flat),
+                               self._total, lr, b1, b2, eps, self.t, self.s))
             for name, ci, co in self.layers:
                 _ck(_lib.unet_flip_weights(ptr(self.w16[name]), ptr(self.wf16[name]), co, ci, self.s))
 

@@ -448,3 +448,74 @@ def test_unet_end_to_end_against_reference(widths, hw, bars):
     for k in gref:
         gg = got[k].reshape(gref[k].shape)
         assert _rel(gg, gref[k]) < grad_bar and _cos(gg, gref[k]) > cos_bar, (k, _rel(gg, gref[k]))
+
+
+LARGE_CONV = [  # N, H, W, Cin, Cout: thousands of pixels, every LDS tile shape, XCD-ordered grids
+    (2, 64, 64, 32, 32),
+    (1, 64, 64, 64, 64),
+    (1, 32, 64, 128, 128),
+    (1, 64, 64, 32, 96),
+]
+
+
+@pytest.mark.parametrize("case", LARGE_CONV, ids=lambda c: "x".join(map(str, c)))
+def test_conv3x3_large_bf16_epilogue(case):
+    """bfloat16 output with bias, ReLU and a mask at thousands of pixels: the staged
+    epilogue's 16-byte stores against the reference rounded to bfloat16."""
+    import torch
+    N, H, W, ci, co = case
+    say(f"case: conv3x3 large bf16 {case}")
+    u = lib()
+    x, w, b = bf((N, H, W, ci), 21), bf((co, 3, 3, ci), 22, 0.2), bf(co, 23)
+    m = bf((N, H, W, co), 24)
+    pre = U.conv3x3(x, w, b)
+    ref = np.where(m > 0, np.maximum(pre, 0), 0.0)
+    bound = gamma(9 * ci + 1) * (U.conv3x3(np.abs(x), np.abs(w)) + np.abs(b))
+    y = torch.zeros((N, H, W, co), dtype=torch.bfloat16, device="cuda")
+    xd, wd, bd, md = dev_bf16(x), dev_bf16(w), dev_f32(b), dev_bf16(m)
+    ck(u.library().unet_conv3x3_fwd(u.ptr(xd), ci, 0, u.ptr(wd), u.ptr(bd), u.ptr(y), co, 0, u.ptr(md), co, 0, N, H,
+                                    W, ci, co, u.RELU, None))
+    got = host(y)
+    want = U.bf16_round(ref)
+    # one bfloat16 step, plus the accumulation bound where the FP32 sum may sit on the
+    # other side of a rounding boundary or of the ReLU
+    tol = np.abs(want) * 2.0 ** -7 + bound * (1 + 2.0 ** -7) + 1e-30
+    assert (np.abs(got - want) <= tol).all(), float((np.abs(got - want) / tol).max())
+    assert (got[m <= 0] == 0).all()
+
+
+@pytest.mark.parametrize("case", [(1, 64, 64, 96, 32), (1, 64, 64, 64, 64), (2, 32, 32, 128, 128)],
+                         ids=lambda c: "x".join(map(str, c)))
+def test_conv3x3_large_input_and_weight_gradients(case):
+    """Input gradient (flipped weights) and weight gradient at thousands of pixels: the
+    weight gradient then spans several 128-column tiles and many pixel slabs."""
+    import ctypes
+    import torch
+    N, H, W, ci, co = case
+    say(f"case: conv3x3 large gradients {case}")
+    u = lib()
+    x, g, w = bf((N, H, W, ci), 25), bf((N, H, W, co), 26), bf((co, 3, 3, ci), 27, 0.2)
+    gi_ref = U.conv3x3_grad_input(g, w)
+    gi_bound = gamma(9 * co) * U.conv3x3_grad_input(np.abs(g), np.abs(w))
+    wd = dev_bf16(w)
+    wf = torch.empty_like(wd)
+    ck(u.library().unet_flip_weights(u.ptr(wd), u.ptr(wf), co, ci, None))
+    dx = torch.zeros((N, H, W, ci), dtype=torch.float32, device="cuda")
+    gd, xd = dev_bf16(g), dev_bf16(x)
+    ck(u.library().unet_conv3x3_fwd(u.ptr(gd), co, 0, u.ptr(wf), None, u.ptr(dx), ci, 0, None, 0, 0, N, H, W, co, ci,
+                                    u.OUT_F32, None))
+    err = np.abs(host(dx) - gi_ref)
+    assert (err <= gi_bound + 1e-30).all(), float((err / (gi_bound + 1e-30)).max())
+    dw_ref, db_ref = U.conv3x3_grad_weight(x, g)
+    bw, bb = U.conv3x3_grad_weight(np.abs(x), np.abs(g))
+    P = N * H * W
+    nb = ctypes.c_size_t()
+    ck(u.library().unet_wgrad_partial_bytes(N, H, W, ci, co, ctypes.byref(nb)))
+    part = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    dw = torch.zeros(co * 9 * ci, dtype=torch.float32, device="cuda")
+    db = torch.zeros(co, dtype=torch.float32, device="cuda")
+    ck(u.library().unet_conv3x3_wgrad(u.ptr(xd), ci, 0, u.ptr(gd), co, 0, u.ptr(dw), u.ptr(db), u.ptr(part), nb.value,
+                                      N, H, W, ci, co, None))
+    got_w = host(dw).reshape(co, 3, 3, ci)
+    assert (np.abs(got_w - dw_ref) <= gamma(P) * bw + 1e-30).all()
+    assert (np.abs(host(db) - db_ref) <= gamma(P) * bb + 1e-30).all()
