@@ -349,6 +349,47 @@ def run_warmstart(args) -> dict:
     }
 
 
+def run_unet_step(args) -> dict:
+    """Timed U-Net training steps alone (forward, backward, Adam; the same step as the
+    warm-start workload's training) on a batch of seeded 256 x 256 droplet problems,
+    each its own target: the kernels do the same work whatever the values."""
+    import torch
+    from paper_2106_01557_amd import unet, warmstart as ws
+
+    torch.cuda.set_device(0)
+    specs = ws.sample_specs(args.batch, seed=3, side=256)
+    run = ws.Runner(specs)
+    rho0, T0f = run.initial_density(), run.uniform_T()
+    net = unet.UNet(seed=0, stream=torch.cuda.current_stream())
+    a = [rho0, T0f, rho0, T0f, run.rho_v, run.rho_l, run.T0, run.cond]
+    for _ in range(args.warmup):
+        net.train_step(*a, lr=args.lr)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        net.train_step(*a, lr=args.lr)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / args.steps
+    run.close()
+    flops = unet_step_flops(net.widths, net.in_channels, args.batch, 256, 256)
+    achieved = flops / (step_ms * 1e-3) / 1e12
+    return {
+        "metric": "U-Net training samples/s (256x256, fwd+bwd+Adam)",
+        "value": round(args.batch / (step_ms * 1e-3), 2), "unit": "samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 (FP32 accumulate, FP32 master weights)", "data": "synthetic",
+        "config": {"workload": f"U-Net widths {list(net.widths)} on {args.batch} seeded 256x256 droplet problems",
+                   "batch": args.batch},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(achieved / 2500.0, 4), "traffic": None,
+                     "kernel": "one training step (all 3x3 convolution kernels, dense FLOPs)",
+                     "flops_per_step": flops},
+    }
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
     """A plain device copy of known size: read nbytes + write nbytes per launch.  Profiling
     it with the same HBM counters gives the factor that turns counter readings into bytes."""
@@ -369,7 +410,7 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="droplet4096", choices=["droplet4096", "batch64", "warmstart"])
+    ap.add_argument("--workload", default="droplet4096", choices=["droplet4096", "batch64", "warmstart", "unet_step"])
     ap.add_argument("--train-runs", type=int, default=2000)
     ap.add_argument("--test-runs", type=int, default=64)
     ap.add_argument("--horizon", type=int, default=5000)
@@ -399,8 +440,8 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the update would shard by slabs with halo exchange, which is not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the update would shard by slabs with halo exchange, which is not implemented)", file=sys.stderr)
         return 2
 
     if args.workload == "batch64":
@@ -408,6 +449,9 @@ def main() -> int:
         return 0
     if args.workload == "warmstart":
         print(json.dumps(run_warmstart(args)), flush=True)
+        return 0
+    if args.workload == "unet_step":
+        print(json.dumps(run_unet_step(args)), flush=True)
         return 0
 
     import torch
