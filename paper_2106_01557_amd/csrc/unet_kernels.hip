@@ -370,6 +370,135 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     }
 }
 
+// Halo-tile form for C_in == 32 (H, W multiples of 16): a workgroup owns a 16 x 16
+// pixel tile and BN = 32 output channels.  It loads the 18 x 18 pixels of the tile
+// and its one-pixel periodic halo (all 32 channels) and the weights of all nine taps
+// once, every load issued together, then runs the nine taps out of LDS: the A
+// fragment of tile pixel (ty, tx) for tap (dy, dx) is halo pixel
+// (ty + dy + 1) * 18 + (tx + dx + 1).  Pixels are reused across taps from LDS instead
+// of being re-read from L2 per tap (324 pixels loaded per 256 computed).  LDS rows
+// hold 4 x 16-byte pieces swizzled as in k_conv_lds (the 16 lanes of a fragment read
+// 16 consecutive halo pixels); the bf16 epilogue is the same.  Accumulation order:
+// taps in order, as in the other forms (C_in = 32 is one chunk per tap).
+constexpr int kHalo = 18 * 18;
+
+template <bool kF32>
+__global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
+    constexpr int BM = 256, BN = 32, WTM = 64, MT = 4, NT = 2;
+    constexpr int OP = BN + 8;
+    static_assert(BM * OP <= kHalo * 32, "output tile fits the halo buffer");
+    __shared__ __attribute__((aligned(16))) bf16_t Ah[kHalo * 32];
+    __shared__ __attribute__((aligned(16))) bf16_t Bh[9 * BN * 32];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int ctiles = a.Cout / BN, L = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = L / ctiles, co0 = (L % ctiles) * BN;
+    const int W = 1 << a.lw, Hm = (1 << a.lh) - 1, Wm = W - 1;
+    const int txs = a.lw - 4, tys = a.lh - 4;  // log2 of the tiles per row and per column
+    const int tx0 = (tile & ((1 << txs) - 1)) << 4;
+    const int ty0 = ((tile >> txs) & ((1 << tys) - 1)) << 4;
+    const int img = (tile >> (txs + tys)) << (a.lw + a.lh);
+    for (int v = t; v < kHalo * 4; v += 256) {
+        const int h = v >> 2, piece = v & 3;
+        const int hr = h / 18, hc = h - 18 * hr;
+        const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
+        const uint4 d = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + 8 * piece);
+        *reinterpret_cast<uint4*>(&Ah[h * 32 + swz(h, piece)]) = d;
+    }
+    const int K = 9 * 32;
+    for (int v = t; v < 9 * BN * 4; v += 256) {
+        const int r = v >> 2, piece = v & 3;
+        const int tap = r / BN, n = r - tap * BN;
+        const uint4 d = ld16(a.w + (size_t)(co0 + n) * K + tap * 32 + 8 * piece);
+        *reinterpret_cast<uint4*>(&Bh[r * 32 + swz(r, piece)]) = d;
+    }
+    __syncthreads();
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int wm = wave * WTM;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap - 3 * (tap / 3);  // offsets into the halo (0..2)
+        uint4 A[MT], B[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            // tile pixel wm + 16 m + r16: row (wm >> 4) + m, column r16
+            const int h = ((wm >> 4) + m + dy) * 18 + r16 + dx;
+            A[m] = *reinterpret_cast<const uint4*>(&Ah[h * 32 + swz(h, k4)]);
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int r = tap * BN + 16 * n + r16;
+            B[n] = *reinterpret_cast<const uint4*>(&Bh[r * 32 + swz(r, k4)]);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]), acc[m][n], 0, 0, 0);
+    }
+    // image pixel of tile pixel q (row q >> 4, column q & 15)
+    auto pixel = [&](int q) { return (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15)); };
+    const int g4 = 4 * (lane >> 4);
+    if constexpr (kF32) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int co = co0 + 16 * n + r16;
+            const float b = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const size_t p = pixel(wm + 16 * m + g4 + r);
+                    float v = acc[m][n][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    if (a.mask && !(bf2f(a.mask[p * a.ldm + co]) > 0.f)) v = 0.f;
+                    static_cast<float*>(a.y)[p * a.ldy + co] = v;
+                }
+            }
+        }
+    } else {
+        __syncthreads();  // every wavefront is done with the halo tile
+        bf16_t* Os = Ah;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int c = 16 * n + r16;
+            const float b = a.bias ? a.bias[co0 + c] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[m][n][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    Os[(wm + 16 * m + g4 + r) * OP + c] = (bf16_t)f2bf_hw(v);
+                }
+            }
+        }
+        __syncthreads();
+        constexpr int VR = BN / 8;
+        for (int v = t; v < BM * VR; v += 256) {
+            const int row = v / VR, cv = v - row * VR;
+            const size_t p = pixel(row);
+            const int co = co0 + 8 * cv;
+            uint4 o = *reinterpret_cast<const uint4*>(&Os[row * OP + 8 * cv]);
+            if (a.mask) {
+                const uint4 mk = ld16(a.mask + p * a.ldm + co);
+                const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+                uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t keep = (lo(mw[j]) > 0.f ? 0xffffu : 0u) | (hi(mw[j]) > 0.f ? 0xffff0000u : 0u);
+                    ow[j] &= keep;
+                }
+                o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+            }
+            st16(static_cast<bf16_t*>(a.y) + p * a.ldy + co, o);
+        }
+    }
+}
+
 // wf[i][t][o] = w[o][8-t][i]
 __global__ void k_flip(const bf16_t* __restrict__ w, bf16_t* __restrict__ wf, int Cout, int Cin) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1015,6 +1144,13 @@ void launch_lds(const ConvArgs& a, bool f32, hipStream_t s) {
 bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
     if (a.Cin % 32) return false;
     if (!f32 && (!aligned16(a.y) || a.ldy % 8)) return false;
+    // 16 x 16 pixel tiles: H and W multiples of 16
+    if (a.Cin == 32 && a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
+        const dim3 grid((a.P / 256) * (a.Cout / 32));
+        if (f32) hipLaunchKernelGGL((k_conv_halo<true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv_halo<false>), grid, dim3(256), 0, s, a);
+        return true;
+    }
     if (a.Cout % 128 == 0 && a.P % 128 == 0) {
         launch_lds<128, 128, 2, 2>(a, f32, s);
     } else if (a.Cout % 64 == 0 && a.P % 256 == 0) {

@@ -451,10 +451,13 @@ def test_unet_end_to_end_against_reference(widths, hw, bars):
 
 
 LARGE_CONV = [  # N, H, W, Cin, Cout: thousands of pixels, every LDS tile shape, XCD-ordered grids
-    (2, 64, 64, 32, 32),
+    (2, 64, 64, 32, 32),     # halo-tile form (C_in = 32), four image rows per tile
     (1, 64, 64, 64, 64),
     (1, 32, 64, 128, 128),
-    (1, 64, 64, 32, 96),
+    (1, 64, 64, 32, 96),     # halo-tile form, three column tiles
+    (1, 16, 256, 32, 32),    # halo-tile form at the network's widest rows (one row per tile)
+    (2, 32, 128, 32, 64),    # halo-tile form, two rows per tile, two column tiles
+    (2, 2, 64, 32, 32),      # 128-pixel images: a 256-pixel tile would cross images, LDS-staged form instead
 ]
 
 
@@ -484,7 +487,7 @@ def test_conv3x3_large_bf16_epilogue(case):
     assert (got[m <= 0] == 0).all()
 
 
-@pytest.mark.parametrize("case", [(1, 64, 64, 96, 32), (1, 64, 64, 64, 64), (2, 32, 32, 128, 128)],
+@pytest.mark.parametrize("case", [(1, 64, 64, 96, 32), (1, 64, 64, 64, 64), (2, 32, 32, 128, 128), (1, 16, 256, 32, 32)],
                          ids=lambda c: "x".join(map(str, c)))
 def test_conv3x3_large_input_and_weight_gradients(case):
     """Input gradient (flipped weights) and weight gradient at thousands of pixels: the
