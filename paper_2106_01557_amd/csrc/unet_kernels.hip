@@ -370,16 +370,17 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     }
 }
 
-// Halo-tile form for C_in == 32 (H, W multiples of 16): a workgroup owns a 16 x 16
-// pixel tile and BN = 32 output channels.  It loads the 18 x 18 pixels of the tile
-// and its one-pixel periodic halo (all 32 channels) and the weights of all nine taps
-// once, every load issued together, then runs the nine taps out of LDS: the A
-// fragment of tile pixel (ty, tx) for tap (dy, dx) is halo pixel
+// Halo-tile form for C_in % 32 == 0 (H, W multiples of 16): a workgroup owns a 16 x 16
+// pixel tile and BN = 32 output channels.  Per block of 32 input channels it loads
+// the 18 x 18 pixels of the tile and its one-pixel periodic halo and the weights of
+// all nine taps, every load issued together, then runs the nine taps out of LDS: the
+// A fragment of tile pixel (ty, tx) for tap (dy, dx) is halo pixel
 // (ty + dy + 1) * 18 + (tx + dx + 1).  Pixels are reused across taps from LDS instead
-// of being re-read from L2 per tap (324 pixels loaded per 256 computed).  LDS rows
-// hold 4 x 16-byte pieces swizzled as in k_conv_lds (the 16 lanes of a fragment read
-// 16 consecutive halo pixels); the bf16 epilogue is the same.  Accumulation order:
-// taps in order, as in the other forms (C_in = 32 is one chunk per tap).
+// of being re-read from L2 per tap (324 pixels loaded per 256 computed).  One LDS
+// buffer (39 KB): four workgroups per CU overlap each other's loads.  LDS rows hold
+// 4 x 16-byte pieces swizzled as in k_conv_lds (the 16 lanes of a fragment read 16
+// consecutive halo pixels); the bf16 epilogue is the same.  Accumulation order: per
+// output, channel block outer, taps inner.
 constexpr int kHalo = 18 * 18;
 
 template <bool kF32>
@@ -397,21 +398,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
     const int tx0 = (tile & ((1 << txs) - 1)) << 4;
     const int ty0 = ((tile >> txs) & ((1 << tys) - 1)) << 4;
     const int img = (tile >> (txs + tys)) << (a.lw + a.lh);
-    for (int v = t; v < kHalo * 4; v += 256) {
-        const int h = v >> 2, piece = v & 3;
-        const int hr = h / 18, hc = h - 18 * hr;
-        const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
-        const uint4 d = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + 8 * piece);
-        *reinterpret_cast<uint4*>(&Ah[h * 32 + swz(h, piece)]) = d;
-    }
-    const int K = 9 * 32;
-    for (int v = t; v < 9 * BN * 4; v += 256) {
-        const int r = v >> 2, piece = v & 3;
-        const int tap = r / BN, n = r - tap * BN;
-        const uint4 d = ld16(a.w + (size_t)(co0 + n) * K + tap * 32 + 8 * piece);
-        *reinterpret_cast<uint4*>(&Bh[r * 32 + swz(r, piece)]) = d;
-    }
-    __syncthreads();
+    const int K = 9 * a.Cin;
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -419,6 +406,22 @@ __global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int wm = wave * WTM;
     const int r16 = lane & 15, k4 = lane >> 4;
+    for (int c0 = 0; c0 < a.Cin; c0 += 32) {
+    if (c0 > 0) __syncthreads();  // the previous channel block's fragments have been read
+    for (int v = t; v < kHalo * 4; v += 256) {
+        const int h = v >> 2, piece = v & 3;
+        const int hr = h / 18, hc = h - 18 * hr;
+        const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
+        const uint4 d = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + c0 + 8 * piece);
+        *reinterpret_cast<uint4*>(&Ah[h * 32 + swz(h, piece)]) = d;
+    }
+    for (int v = t; v < 9 * BN * 4; v += 256) {
+        const int r = v >> 2, piece = v & 3;
+        const int tap = r / BN, n = r - tap * BN;
+        const uint4 d = ld16(a.w + (size_t)(co0 + n) * K + tap * a.Cin + c0 + 8 * piece);
+        *reinterpret_cast<uint4*>(&Bh[r * 32 + swz(r, piece)]) = d;
+    }
+    __syncthreads();
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - 3 * (tap / 3);  // offsets into the halo (0..2)
         uint4 A[MT], B[NT];
@@ -438,6 +441,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
 #pragma unroll
             for (int n = 0; n < NT; ++n)
                 acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]), acc[m][n], 0, 0, 0);
+    }
     }
     // image pixel of tile pixel q (row q >> 4, column q & 15)
     auto pixel = [&](int q) { return (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15)); };
@@ -1145,7 +1149,7 @@ bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
     if (a.Cin % 32) return false;
     if (!f32 && (!aligned16(a.y) || a.ldy % 8)) return false;
     // 16 x 16 pixel tiles: H and W multiples of 16
-    if (a.Cin == 32 && a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
+    if (a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
         const dim3 grid((a.P / 256) * (a.Cout / 32));
         if (f32) hipLaunchKernelGGL((k_conv_halo<true>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_conv_halo<false>), grid, dim3(256), 0, s, a);
