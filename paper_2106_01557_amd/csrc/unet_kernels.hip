@@ -1176,12 +1176,14 @@ WgPlan wgrad_plan(int P, int Cin, int Cout) {
     WgPlan w;
     const int K = 9 * Cin;
     w.tr = Cout % 32 == 0;
-    const int BK = w.tr ? 128 : 64;  // k columns per workgroup
+    const int BK = w.tr ? (Cout % 64 == 0 ? 256 : 128) : 64;  // k columns per workgroup
     w.ktiles = (K + 1 + BK - 1) / BK;
     w.Kt = BK * w.ktiles;
     w.CT = Cout % 64 == 0 ? 64 : 32;
     w.ctiles = (Cout + w.CT - 1) / w.CT;
-    const int want = 1024;  // workgroups to aim for: four per CU; longer slabs keep the partials small
+    // workgroups to aim for: fewer, longer slabs keep the FP32 partials (slabs x C_out x Kt)
+    // and their reduction small
+    const int want = w.tr ? 512 : 1024;
     int slabs = (want + w.ktiles * w.ctiles - 1) / (w.ktiles * w.ctiles);
     const int max_slabs = (P + 255) / 256;  // at least 256 pixels per slab
     if (slabs > max_slabs) slabs = max_slabs;
@@ -1285,7 +1287,7 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
     const dim3 grid(p.ktiles, p.ctiles, p.slabs);
     if (p.tr) {
         const dim3 flat(p.ktiles * p.ctiles * p.slabs);
-        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_tr<64, 128, 64, 2>), flat, dim3(256), 0, s, a);
+        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_tr<64, 256, 32, 2>), flat, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_wgrad_tr<32, 128, 64, 1>), flat, dim3(256), 0, s, a);
     } else {
         if (p.CT == 64) hipLaunchKernelGGL((k_wgrad<64>), grid, dim3(256), 0, s, a);
