@@ -51,6 +51,13 @@ int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, co
  * (dx = conv3x3_fwd(g, wf) with C_in and C_out exchanged). */
 int unet_flip_weights(const void* w, void* wf, int32_t C_out, int32_t C_in, void* stream);
 
+/* The same for n <= 64 layers in one launch: w[l], wf[l] (device, bfloat16, 16-byte
+ * aligned) with C_out[l], C_in[l] >= 1; the four arrays are host memory, read before
+ * the call returns.  UNET_EINVAL for n outside [1, 64] or a bad entry (nothing is
+ * launched then). */
+int unet_flip_weights_many(const void* const* w, void* const* wf, const int32_t* C_out, const int32_t* C_in,
+                           int32_t n, void* stream);
+
 /* Weight and bias gradients: dw[o,t,i] = sum_{n,p} g[n,p,o] x[n,p+off_t,i] and
  * db[o] = sum g[n,p,o] (FP32, overwritten).  The pixel sum is split over slabs whose
  * FP32 partial sums go to `partials` and are then added in a fixed order
@@ -107,7 +114,8 @@ int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, 
                   size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, int32_t K, void* stream);
 
 /* Head gradient: g[n,p,c] = sum_k dout[k][n,p] hw[k][c] (gated by d > 0), dhw[k][c] =
- * sum dout[k] d[.,c], dhb[k] = sum dout[k] (FP32, deterministic block partials). */
+ * sum dout[k] d[.,c], dhb[k] = sum dout[k] (FP32, deterministic block partials).
+ * C / 8 must divide 256 (C in {8, 16, 32, 64, 128, 256}); UNET_EINVAL otherwise. */
 int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout, void* g, float* dhw,
                   float* dhb, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W,
                   int32_t C, int32_t K, void* stream);

@@ -503,6 +503,26 @@ __global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
     }
 }
 
+// several layers in one launch: workgroup b works on the layer whose element range
+// [first[l], first[l + 1]) (in units of 256) contains b
+constexpr int kFlipMax = 64;
+struct FlipSet {
+    const bf16_t* w[kFlipMax];
+    bf16_t* wf[kFlipMax];
+    int cout[kFlipMax], cin[kFlipMax], first[kFlipMax + 1];
+    int n;
+};
+
+__global__ void k_flip_many(const FlipSet f) {
+    int l = 0;
+    while (l + 1 < f.n && (int)blockIdx.x >= f.first[l + 1]) ++l;
+    const int idx = (blockIdx.x - f.first[l]) * blockDim.x + threadIdx.x;
+    const int Cout = f.cout[l], Cin = f.cin[l];
+    if (idx >= Cout * 9 * Cin) return;
+    const int o = idx % Cout, t = (idx / Cout) % 9, i = idx / (9 * Cout);
+    f.wf[l][idx] = f.w[l][((size_t)o * 9 + (8 - t)) * Cin + i];
+}
+
 // wf[i][t][o] = w[o][8-t][i]
 __global__ void k_flip(const bf16_t* __restrict__ w, bf16_t* __restrict__ wf, int Cout, int Cin) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1089,63 +1109,69 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// part: [blocks * 4 wavefronts][K (C + 1)]: per-wavefront sums of dout_k d[., c] and of
-// dout_k.  Grid-stride over pixels (thread t takes pixels t, t + nt, ...), one pass
-// per 8-channel group: the input gradient of those channels is stored, and the
-// thread's products are summed in registers, then reduced across the wavefront once
-// per group (a fixed assignment and order, so the sums are deterministic).
-constexpr int kHeadBwdBlocks = 1024;
+// part: [blocks][K (C + 1)]: per-workgroup sums of dout_k d[., c] and of dout_k.  The
+// C / 8 channel groups of a pixel sit on consecutive threads (16-byte accesses of whole
+// pixel rows); thread t takes pixels t / G, t / G + (threads / G), ... (G = C / 8) and
+// sums its products in registers; the workgroup then combines the threads' sums in
+// thread order through LDS (deterministic).  C / 8 must divide the workgroup size.
+constexpr int kHeadBwdBlocks = 2048;
 
 __global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ldd, const float* hw,
                                                          const float* dout, bf16_t* g, float* part, int C, int K,
                                                          int P) {
-    const int t = blockIdx.x * kHeadBlock + threadIdx.x, nt = gridDim.x * kHeadBlock;
-    const int lane = threadIdx.x & 63;
-    const size_t row = ((size_t)blockIdx.x * (kHeadBlock / 64) + (threadIdx.x >> 6)) * K * (C + 1);
-    for (int c = 0; c < C; c += 8) {
-        float acc[4][8], w[4][8];
+    __shared__ float red[kHeadBlock * 9];
+    const int G = C >> 3, t = threadIdx.x;
+    const int cg = t % G, c = 8 * cg;
+    const int per_block = kHeadBlock / G;            // pixels per workgroup per sweep
+    const int p0 = blockIdx.x * per_block + t / G, stride = gridDim.x * per_block;
+    float w[4][8], acc[4][8], bs[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
+        bs[k] = 0.f;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                acc[k][j] = 0.f;
-                w[k][j] = k < K ? hw[k * C + c + j] : 0.f;
-            }
-        for (int p = t; p < P; p += nt) {
-            float dp[4], v[8], o[8];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) dp[k] = k < K ? dout[(size_t)k * P + p] : 0.f;
-            unpack8(ld16(d + (size_t)p * ldd + c), v);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                float s = 0.f;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (k < K) s += dp[k] * w[k][j];
-                o[j] = v[j] > 0.f ? s : 0.f;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k][j] += dp[k] * v[j];
-            }
-            st16(g + (size_t)p * C + c, pack8(o));
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (k >= K) break;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float b = wave_sum(acc[k][j]);
-                if (lane == 0) part[row + (size_t)k * (C + 1) + c + j] = b;
-            }
+        for (int j = 0; j < 8; ++j) {
+            acc[k][j] = 0.f;
+            w[k][j] = k < K ? hw[k * C + c + j] : 0.f;
         }
     }
-    float bs[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int p = t; p < P; p += nt)
+    for (int p = p0; p < P; p += stride) {
+        float dp[4], v[8], o[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (k < K) bs[k] += dout[(size_t)k * P + p];
+        for (int k = 0; k < 4; ++k) dp[k] = k < K ? dout[(size_t)k * P + p] : 0.f;
+        unpack8(ld16(d + (size_t)p * ldd + c), v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s += dp[k] * w[k][j];
+            o[j] = v[j] > 0.f ? s : 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k][j] += dp[k] * v[j];
+        }
+        st16(g + (size_t)p * C + c, pack8(o));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bs[k] += dp[k];
+    }
+    // combine: for each k, entry (channel c + j) sums the threads of group cg, and the
+    // bias entry sums the group-0 threads (one per pixel)
+    const int m = K * (C + 1);
+    float* row = part + (size_t)blockIdx.x * m;
     for (int k = 0; k < K; ++k) {
-        const float b = wave_sum(bs[k]);
-        if (lane == 0) part[row + (size_t)k * (C + 1) + C] = b;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[t * 9 + j] = acc[k][j];
+        red[t * 9 + 8] = bs[k];
+        __syncthreads();
+        for (int e = t; e < C + 1; e += kHeadBlock) {
+            float s = 0.f;
+            if (e < C) {
+                const int eg = e >> 3, ej = e & 7;
+                for (int u = eg; u < kHeadBlock; u += G) s += red[u * 9 + ej];
+            } else {
+                for (int u = 0; u < kHeadBlock; u += G) s += red[u * 9 + 8];
+            }
+            row[k * (C + 1) + e] = s;
+        }
     }
 }
 
@@ -1382,6 +1408,27 @@ int unet_flip_weights(const void* w, void* wf, int32_t C_out, int32_t C_in, void
     return launched("flip launch");
 }
 
+int unet_flip_weights_many(const void* const* w, void* const* wf, const int32_t* C_out, const int32_t* C_in,
+                           int32_t n, void* stream) {
+    if (!w || !wf || !C_out || !C_in || n < 1 || n > kFlipMax) return fail(UNET_EINVAL, "flip many: bad arguments");
+    FlipSet f;
+    f.n = n;
+    int blocks = 0;
+    for (int l = 0; l < n; ++l) {
+        if (!w[l] || !wf[l] || C_out[l] < 1 || C_in[l] < 1 || (int64_t)C_out[l] * 9 * C_in[l] >= (1 << 30))
+            return fail(UNET_EINVAL, "flip many: bad entry %d", l);
+        f.w[l] = static_cast<const bf16_t*>(w[l]);
+        f.wf[l] = static_cast<bf16_t*>(wf[l]);
+        f.cout[l] = C_out[l];
+        f.cin[l] = C_in[l];
+        f.first[l] = blocks;
+        blocks += (C_out[l] * 9 * C_in[l] + 255) / 256;
+    }
+    f.first[n] = blocks;
+    hipLaunchKernelGGL(k_flip_many, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), f);
+    return launched("flip many launch");
+}
+
 int unet_wgrad_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, size_t* bytes) {
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
@@ -1567,6 +1614,7 @@ int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout
     if ((r = check_tensor("d", d, ldd, 0, C, false)) || (r = check_tensor("g", g, C, 0, C, false))) return r;
     if (!hw || !dout || !dhw || !dhb || !partials || partial_bytes < need)
         return fail(UNET_EINVAL, "head bwd: NULL argument or partials below %zu bytes", need);
+    if (kHeadBlock % (C / 8) != 0) return fail(UNET_EINVAL, "head bwd: C / 8 must divide %d (got C = %d)", kHeadBlock, C);
     const int P = N * H * W;
     // no more workgroups than the forward pass uses, so its partials buffer suffices
     const int blocks = std::min((P + kHeadBlock - 1) / kHeadBlock, kHeadBwdBlocks);
@@ -1575,8 +1623,8 @@ int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout
                        static_cast<bf16_t*>(g), static_cast<float*>(partials), C, K, P);
     if ((r = launched("head bwd launch"))) return r;
     const int m = K * (C + 1);
-    hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(256), 0, s, static_cast<const float*>(partials),
-                       blocks * (kHeadBlock / 64), m, 1.0f, dhw, dhb, C + 1);
+    hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(256), 0, s, static_cast<const float*>(partials), blocks, m,
+                       1.0f, dhw, dhb, C + 1);
     return launched("head reduce launch");
 }
 

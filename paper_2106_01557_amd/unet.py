@@ -26,7 +26,8 @@ from . import lbm as _lbm
 _lib = _lbm.library()
 _P, _I, _F, _V, _S = ctypes.POINTER, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
 
-EXPORTED = ["unet_conv3x3_fwd", "unet_flip_weights", "unet_wgrad_partial_bytes", "unet_conv3x3_wgrad",
+EXPORTED = ["unet_conv3x3_fwd", "unet_flip_weights", "unet_flip_weights_many", "unet_wgrad_partial_bytes",
+            "unet_conv3x3_wgrad",
             "unet_maxpool2_fwd", "unet_maxpool2_bwd", "unet_upsample2_fwd", "unet_upsample2_bwd",
             "unet_prepare_input", "unet_output_fields", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd", "unet_adam",
             "unet_to_bf16", "unet_to_f32", "unet_last_error"]
@@ -35,6 +36,8 @@ RELU, OUT_F32 = 1, 2
 
 _lib.unet_conv3x3_fwd.argtypes = [_V, _I, _I, _V, _V, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_flip_weights.argtypes = [_V, _V, _I, _I, _V]
+_lib.unet_flip_weights_many.argtypes = [ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.POINTER(_I),
+                                        ctypes.POINTER(_I), _I, _V]
 _lib.unet_wgrad_partial_bytes.argtypes = [_I, _I, _I, _I, _I, _P(_S)]
 _lib.unet_conv3x3_wgrad.argtypes = [_V, _I, _I, _V, _I, _I, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
 _lib.unet_maxpool2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
@@ -148,6 +151,11 @@ class UNet:
             for name, ci, co in self.layers:
                 self.w16[name] = w16[name + ".w"]
                 self.wf16[name] = torch.empty(self.w16[name].numel(), dtype=torch.bfloat16, device=self.device)
+            # descriptors of every layer for the one-launch flip after each Adam step
+            n = len(self.layers)
+            self._flip = ((_V * n)(*[ptr(self.w16[nm]) for nm, _, _ in self.layers]),
+                          (_V * n)(*[ptr(self.wf16[nm]) for nm, _, _ in self.layers]),
+                          (_I * n)(*[co for _, _, co in self.layers]), (_I * n)(*[ci for _, ci, _ in self.layers]), n)
             self._refresh_copies()
         self.t = 0
 
@@ -328,8 +336,7 @@ class UNet:
             # one launch over the flat buffers; it also refreshes every bfloat16 copy
             _ck(_lib.unet_adam(ptr(self.flat), ptr(self.gflat), ptr(self.mflat), ptr(self.vflat), ptr(self.w16flat),
                                self._total, lr, b1, b2, eps, self.t, self.s))
-            for name, ci, co in self.layers:
-                _ck(_lib.unet_flip_weights(ptr(self.w16[name]), ptr(self.wf16[name]), co, ci, self.s))
+            _ck(_lib.unet_flip_weights_many(*self._flip, self.s))
 
     def train_step(self, rho0, T0f, rhoT, TT, rho_v, rho_l, T0, cond, lr=1e-3):
         _, loss = self.forward(rho0, T0f, rho_v, rho_l, T0, cond, rhoT, TT)

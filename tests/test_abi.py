@@ -62,6 +62,19 @@ def test_network_calls_validate_before_launching(lbm):
     assert lib.unet_conv3x3_wgrad(buf, 32, 0, buf, 32, 0, buf, buf, buf, nb.value - 1, 2, 64, 64, 32, 32, None) == -1
     assert lib.unet_adam(buf, buf, buf, buf, None, 10, ctypes.c_float(1e-3), ctypes.c_float(0.9),
                          ctypes.c_float(0.999), ctypes.c_float(1e-8), 0, None) == -1
+    # the one-launch flip: n outside [1, 64], a NULL entry, a bad channel count
+    ptrs, outs = (V * 65)(*([buf] * 65)), (V * 65)(*([buf] * 65))
+    co, ci = (ctypes.c_int32 * 65)(*([16] * 65)), (ctypes.c_int32 * 65)(*([8] * 65))
+    assert lib.unet_flip_weights_many(ptrs, outs, co, ci, 0, None) == -1
+    assert lib.unet_flip_weights_many(ptrs, outs, co, ci, 65, None) == -1
+    holes = (V * 2)(buf, None)
+    assert lib.unet_flip_weights_many(holes, outs, co, ci, 2, None) == -1
+    assert "entry 1" in lib.unet_last_error().decode()
+    co[0] = 0
+    assert lib.unet_flip_weights_many(ptrs, outs, co, ci, 1, None) == -1
+    # head gradient: C / 8 must divide the 256-thread workgroup
+    assert lib.unet_head_bwd(buf, 24, buf, buf, buf, buf, buf, buf, 1 << 30, 1, 8, 8, 24, 2, None) == -1
+    assert "C / 8" in lib.unet_last_error().decode()
 
 
 @pytest.mark.parametrize("eos_kind", ["cs", "vdw"])

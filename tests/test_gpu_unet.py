@@ -522,3 +522,26 @@ def test_conv3x3_large_input_and_weight_gradients(case):
     got_w = host(dw).reshape(co, 3, 3, ci)
     assert (np.abs(got_w - dw_ref) <= gamma(P) * bw + 1e-30).all()
     assert (np.abs(host(db) - db_ref) <= gamma(P) * bb + 1e-30).all()
+
+
+def test_flip_many_equals_per_layer_flips():
+    """The one-launch flip of several layers (workgroup ranges per layer) is bitwise the
+    per-layer flip."""
+    import ctypes
+    import torch
+    say("case: flip many")
+    u = lib()
+    shapes = [(32, 8), (32, 32), (64, 96), (16, 40), (128, 64)]  # (C_out, C_in)
+    ws = [dev_bf16(bf((co, 3, 3, ci), 40 + i)) for i, (co, ci) in enumerate(shapes)]
+    one = [torch.empty_like(w) for w in ws]
+    many = [torch.zeros_like(w) for w in ws]
+    for w, o, (co, ci) in zip(ws, one, shapes):
+        ck(u.library().unet_flip_weights(u.ptr(w), u.ptr(o), co, ci, None))
+    n = len(shapes)
+    V, I = ctypes.c_void_p, ctypes.c_int32
+    ck(u.library().unet_flip_weights_many((V * n)(*[u.ptr(w) for w in ws]), (V * n)(*[u.ptr(m) for m in many]),
+                                          (I * n)(*[co for co, _ in shapes]), (I * n)(*[ci for _, ci in shapes]), n,
+                                          None))
+    torch.cuda.synchronize()
+    for o, m in zip(one, many):
+        assert torch.equal(o, m)
