@@ -526,7 +526,9 @@ def main() -> int:
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_step_ab (fused f+g update)" if args.scheme == "ab" else "k_density + k_step_aa",
+            "kernel": (("k_step_ab2 (fused f+g update, two columns per lane)" if shape[2] == 2 else
+                        "k_step_ab (fused f+g update, one column per lane)")
+                       if args.scheme == "ab" else "k_density + k_step_aa"),
             "kernel_ms": round(kernel_ms, 5),
         },
         "checks": {
