@@ -175,9 +175,13 @@ void fill_consts(const lbm_ctx* c, Consts<C>* k) {
         const double T_ref = c->p.T_ref > 0 ? c->p.T_ref : d[2];
         double f[9], g[9];
         rest_populations(c, rho_ref, T_ref, f, g);
+        // at rest the populations depend only on the speed class (rest, axis, diagonal);
+        // the references are made exactly class-uniform, so kernels may read the class
+        // entry (0, 1 or 5) for every direction of the class
         for (int i = 0; i < 9; ++i) {
-            k->ref_f[i] = (C)f[i];
-            k->ref_g[i] = (C)g[i];
+            const int cls = i == 0 ? 0 : (i < 5 ? 1 : 5);
+            k->ref_f[i] = (C)f[cls];
+            k->ref_g[i] = (C)g[cls];
         }
     }
 }

@@ -947,6 +947,11 @@ __device__ inline void ld2(const Planes<S, false>& B, int i, size_t off, C ref, 
     }
 }
 
+// Speed class of direction i (rest, axis, diagonal) as the index of the class's first
+// direction: the 16-bit deviation references are class-uniform (set so on the host),
+// and reading one entry per class keeps 6 instead of 18 of them live.
+__device__ constexpr int kCls[9] = {0, 1, 1, 1, 1, 5, 5, 5, 5};
+
 // Values of a finished row from the raw pair loads: 16-bit storage unpacks the words
 // kept by ld2, wider storage takes the loaded values as they are.
 template <typename S, typename C>
@@ -954,7 +959,7 @@ __device__ inline void unpack2(const C* ra, const C* rb, const C* ref, C* a, C* 
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         if constexpr (sizeof(S) == 2) {
-            Pair16<S>::unpack(__builtin_bit_cast(unsigned, ra[i]), ref[i], a[i], b[i]);
+            Pair16<S>::unpack(__builtin_bit_cast(unsigned, ra[i]), ref[kCls[i]], a[i], b[i]);
         } else {
             a[i] = ra[i];
             b[i] = rb[i];
@@ -1130,8 +1135,8 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
         collide(P, fb, gb, dc.b, sxb, syb, fob, gob);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            st2<S, C>(out, i, o, foa[i], fob[i], P.ref_f[i], G.owner);
-            st2<S, C>(out, 9 + i, o, goa[i], gob[i], P.ref_g[i], G.owner);
+            st2<S, C>(out, i, o, foa[i], fob[i], P.ref_f[kCls[i]], G.owner);
+            st2<S, C>(out, 9 + i, o, goa[i], gob[i], P.ref_g[kCls[i]], G.owner);
         }
     }
     if (kStage >= 1) {
