@@ -274,23 +274,24 @@ __device__ inline void collide(const Consts<C>& P, const C* f, const C* g, C rho
 }
 
 // ---------------------------------------------------------------------------
-// fused two-buffer step (pull streaming, 64-column aligned strips)
+// fused two-buffer step (pull streaming, aligned strips)
 // ---------------------------------------------------------------------------
 // State convention of the two-buffer scheme: a buffer holds the post-collision
 // populations at the node where they were computed, not yet streamed; step t
 // reads f_i(x, t) = f_bar_i(x - e_i, t - dt) (Eq. (12a) applied on read) and
 // writes f_bar(x, t) at x.
 //
-// A wavefront owns 64 aligned columns x0..x0+63 of a strip and marches through
-// `rows` rows.  For the populations of target row y it loads, for each i, the
-// aligned row y - e_iy of plane i (one full 256-byte segment per instruction) and
-// moves the values e_ix columns across lanes with a wave-wide DPP shift.  The one
-// value per shifted population that comes from outside the strip (for lane 0 or
-// the last owned lane) and the populations of the two halo columns (whose
-// densities the force stencil needs) arrive through one gather load per row in
-// which each of 18 lanes fetches one value.  Stores are aligned, at the node.
-// Densities of the rows y-1, y, y+1 live in registers; their x-neighbours come
-// from DPP shifts as well.  Every population is read from HBM once per step.
+// A wavefront owns an aligned strip of 64 columns (one per lane; k_step_ab) or 128
+// columns (two adjacent columns per lane; k_step_ab2) and marches through `rows`
+// rows.  For the populations of target row y it loads, for each i, the aligned row
+// y - e_iy of slot i (one contiguous segment per instruction) and moves the values
+// e_ix columns across lanes with a wave-wide DPP shift.  The one value per shifted
+// population that comes from outside the strip (for lane 0 or the last owned lane)
+// and the populations of the two halo columns (whose densities the force stencil
+// needs) arrive through one gather load per row in which each of 18 lanes fetches
+// one value.  Stores are aligned, at the node.  Densities of the rows y-1, y, y+1
+// live in registers; their x-neighbours come from DPP shifts as well.  Every
+// population is read from HBM once per step.
 
 __device__ constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
