@@ -1,0 +1,79 @@
+"""Physics of the whole update on the GPU (not parity with the oracle): the Laplace law
+of an equilibrium droplet, p_in - p_out = sigma / R in 2-D.
+
+The surface tension of the model is fixed by the square-gradient theory of the
+pressure tensor of Eq. (11): sigma_ref = integral sqrt(2 kappa dOmega) d rho over the
+Maxwell densities (oracle/thermo.py; 0.0099999993 at T/Tc = 0.8 for the paper's
+K_EOS, K_INT, whose choice the paragraph before Eq. (20) explains by sigma = 0.01).
+The temperature is not held fixed (the energy equation is solved, and the total
+energy is conserved only to truncation error), and T/Tc drifts from 0.800 to about
+0.786 over 80 000 steps; sigma_ref is therefore taken at the droplet's measured mean
+temperature.  p is p_EOS at the droplet centre and at the far corner, R is the
+equimolar radius.  The paper reports its own droplet measurement 1.7 % above 0.01.
+
+The interface width W is the 5 %-95 % width of the azimuthally averaged profile,
+against the same width of the flat square-gradient profile at the mean temperature of
+the interface band (oracle/thermo.py; 10.00000006 at T/Tc = 0.8, the paper's
+circular fit gave 9.961104).
+"""
+import numpy as np
+import pytest
+
+from oracle import thermo
+from tests.parity_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _width_5_95(phi):
+    """5 %-95 % width of the azimuthal average of the normalised density about its centroid."""
+    n = phi.shape[0]
+    y, x = np.mgrid[0:n, 0:n]
+    cx, cy = (phi * x).sum() / phi.sum(), (phi * y).sum() / phi.sum()
+    r, p = np.hypot(x - cx, y - cy).ravel(), phi.ravel()
+    idx = np.digitize(r, np.arange(0.0, n / 2, 0.25))
+    keep = [i for i in np.unique(idx) if i > 0]
+    rb = np.array([r[idx == i].mean() for i in keep])
+    pb = np.array([p[idx == i].mean() for i in keep])
+
+    def cross(level):
+        k = np.where((pb[:-1] >= level) & (pb[1:] < level))[0][0]
+        return rb[k] + (level - pb[k]) * (rb[k + 1] - rb[k]) / (pb[k + 1] - pb[k])
+    return cross(0.05) - cross(0.95)
+
+
+def test_laplace_law_droplet():
+    import torch
+    from paper_2106_01557_amd import inputs, lbm
+    n, R0, steps = 128, 32, 80000
+    say(f"case: Laplace law, FP64 droplet R={R0} on {n}x{n}, {steps} steps")
+    eos = thermo.paper_cs_eos()
+    s = lbm.Solver(n, n, params={"Tr0": 0.8, "precision": "f64", "rows_per_wave": 8})
+    try:
+        c = s.derived()
+        f = inputs.droplet(n, n, c["rho_l"], c["rho_v"], c["T0"], R0, 4.0, eps=0.0)
+        s.set_fields(*f.as_tuple())
+        s.step(steps)
+        torch.cuda.synchronize()
+        m = s.moments_numpy()
+    finally:
+        s.close()
+    rho, T = m["rho"], m["T"]
+    assert np.isfinite(rho).all() and np.isfinite(T).all()
+    i0 = n // 2
+    rl, rv, Tin, Tout = rho[i0, i0], rho[0, 0], T[i0, i0], T[0, 0]
+    dp = float(thermo.pressure(eos, rl, Tin)) - float(thermo.pressure(eos, rv, Tout))
+    Req = np.sqrt(((rho - rv) / (rl - rv)).sum() / np.pi)
+    sigma = dp * Req
+    d = thermo.derive(eos, thermo.Params(Tr0=0.8))
+    ref = float(thermo.surface_tension(eos, 0.5 * (Tin + Tout), d.kappa))
+    phi = (rho - rv) / (rl - rv)
+    W = _width_5_95(phi)
+    Tband = T[(phi > 0.05) & (phi < 0.95)].mean()
+    Wref = float(thermo.interface_width(eos, Tband, d.kappa))
+    say(f"  W {W:.4f} W_ref(T_band/Tc {Tband / float(d.Tc):.5f}) {Wref:.4f} ({(W / Wref - 1) * 100:+.2f} %)")
+    say(f"  rho_l {rl:.6f} rho_v {rv:.6f} T/Tc in {Tin / float(d.Tc):.5f} out {Tout / float(d.Tc):.5f} "
+        f"R_eq {Req:.3f} dp {dp:.4e} sigma {sigma:.6f} sigma_ref(T) {ref:.6f} ({(sigma / ref - 1) * 100:+.2f} %)")
+    assert abs(Req - R0) < 1.0
+    assert abs(sigma / ref - 1) <= 0.03
+    assert abs(W / Wref - 1) <= 0.03
