@@ -51,8 +51,8 @@ extern "C" {
  *      FP32 otherwise) ------------------------------------------------------ */
 #define LBM_F64  0
 #define LBM_F32  1
-#define LBM_F16  2  /* FP16 deviations from the rest equilibrium of (rho0, T0)      */
-#define LBM_BF16 3  /* BF16 deviations from the rest equilibrium of (rho0, T0)      */
+#define LBM_F16  2  /* FP16 deviations from the rest equilibrium of (rho_ref, T_ref) */
+#define LBM_BF16 3  /* BF16 deviations from the rest equilibrium of (rho_ref, T_ref) */
 
 /* ---- update schemes ------------------------------------------------------- */
 #define LBM_SCHEME_AB 0  /* fused single pass, two state buffers (pull streaming)      */
@@ -95,7 +95,7 @@ typedef struct {
     double accel_x, accel_y; /* external acceleration a of Eq. (14)                     */
     double cs_override;   /* > 0: use this lattice sound speed instead of Eq. (19)      */
     double rho_ref, T_ref;/* deviation reference for LBM_F16/LBM_BF16 storage;
-                             <= 0: rho = (rho_v + rho_l)/2 and T = T0                   */
+                             <= 0: rho_v at T0 (vapour coexistence) and T0            */
     int32_t precision;    /* LBM_F64, LBM_F32, LBM_F16, LBM_BF16                        */
     int32_t scheme;       /* LBM_SCHEME_AB or LBM_SCHEME_AA                             */
     int32_t rows_per_wave;/* rows one wavefront marches through per launch; 0 = auto

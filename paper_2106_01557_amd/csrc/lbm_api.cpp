@@ -171,7 +171,10 @@ void fill_consts(const lbm_ctx* c, Consts<C>* k) {
     k->Qpre = (C)(G2 * dx * dx * dt * dt / 12.0);
     k->Ep_pre = (C)(-0.5 * G2 * dx * dx);
     if (c->p.precision == LBM_F16 || c->p.precision == LBM_BF16) {
-        const double rho_ref = c->p.rho_ref > 0 ? c->p.rho_ref : 0.5 * (d[3] + d[4]);
+        // default: the vapour coexistence state at T0.  Vapour populations are the small
+        // ones, and T = rho e_k / (rho cv) divides by the small vapour density, so the fine
+        // absolute resolution of small deviations belongs there
+        const double rho_ref = c->p.rho_ref > 0 ? c->p.rho_ref : d[3];
         const double T_ref = c->p.T_ref > 0 ? c->p.T_ref : d[2];
         double f[9], g[9];
         rest_populations(c, rho_ref, T_ref, f, g);

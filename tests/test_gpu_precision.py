@@ -1,8 +1,12 @@
 """Precision form: populations stored in 16 bits (FP16 or BF16 deviations from the rest
-equilibrium of one reference state, the mid density at T0), FP32 arithmetic.  Every result
-is reported against the FP64 oracle; the bars are the measured accuracy of each storage
-format (96x80 droplet, 1000 steps: FP16 rho 9.8e-3, T 2.3e-2; BF16 rho 5.2e-2, T 9.1e-2)
-with margin, not a claim of FP32-level parity."""
+equilibrium of one reference state, the vapour coexistence density at T0), FP32
+arithmetic.  Every result is reported against the FP64 oracle; the bars are the measured
+accuracy of each storage format with margin, not a claim of FP32-level parity:
+  96x80 droplet, 1000 steps: FP16 rho 6.8e-3, T 1.1e-2; BF16 rho 4.7e-2, T 5.9e-2
+  64x64 slab, 2000 steps, bulk densities: FP16 rho_l 9.2e-3, rho_v 5.2e-2;
+                                          BF16 rho_l 3.3e-2, rho_v 8.7e-2
+Rounding to nearest is deterministic, so in a nearly steady state each step rounds the
+same values the same way and the errors add up instead of averaging out."""
 import numpy as np
 import pytest
 
@@ -12,7 +16,7 @@ from tests.parity_helpers import assert_close, errors, gpu_moments, oracle_model
 pytestmark = pytest.mark.gpu
 
 # bars per storage format (normalised max errors, see parity_helpers.errors)
-BARS = {"f32": 1e-5, "f16": 5e-2, "bf16": 2e-1}
+BARS = {"f32": 1e-5, "f16": 3e-2, "bf16": 1.5e-1}
 
 
 @pytest.fixture(scope="module")
@@ -37,12 +41,42 @@ def test_16bit_storage_error_vs_fp64_oracle(droplet_case, prec):
 
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
 def test_16bit_storage_keeps_uniform_state_nearly_steady(prec):
-    """A uniform rest state at the reference density is stored exactly (zero deviations)."""
+    """A uniform rest state at the reference state is stored exactly (zero deviations)."""
     model = oracle_model("cs")
     d = model.d
-    rho0 = 0.5 * (d.rho_l + d.rho_v)
+    rho0 = d.rho_v
     say(f"case: {prec} uniform state at the reference density")
     f = inputs.uniform(64, 32, rho0, d.T0)
     g, _ = gpu_moments(64, 32, f, 50, params={"precision": prec})
     assert np.allclose(g["rho"], rho0, rtol=1e-6, atol=0)
     assert np.abs(g["ux"]).max() < 1e-7 and np.abs(g["uy"]).max() < 1e-7
+
+
+@pytest.fixture(scope="module")
+def slab_case():
+    model = oracle_model("cs")
+    d = model.d
+    f = inputs.slab(64, 64, d.rho_l, d.rho_v, d.T0, 16, 47, eps=0.01, seed=0)
+    o, _ = oracle_moments(model, f, 2000)
+    return model, f, o
+
+
+def _bulk(m):
+    """Row-mean densities at the slab centre (between rows 31 and 32) and half a period
+    away in the vapour (between rows 63 and 0)."""
+    r = m["rho"].mean(axis=1)
+    return 0.5 * (r[31] + r[32]), 0.5 * (r[63] + r[0])
+
+
+@pytest.mark.parametrize("prec,bar_l,bar_v", [("f16", 2e-2, 1e-1), ("bf16", 6e-2, 1.5e-1)])
+def test_16bit_storage_coexistence_densities_vs_fp64_oracle(slab_case, prec, bar_l, bar_v):
+    """Flat-slab coexistence with 16-bit storage: the bulk liquid and vapour densities
+    after 2000 steps against the FP64 oracle's, as relative errors."""
+    model, f, o = slab_case
+    say(f"case: {prec} storage AB 64x64 slab, 2000 steps, bulk densities vs FP64 oracle")
+    g, s = gpu_moments(64, 64, f, 2000, params={"precision": prec})
+    assert s.invariants()["bad_nodes"] == 0
+    (lo, vo), (lg, vg) = _bulk(o), _bulk(g)
+    el, ev = abs(lg / lo - 1), abs(vg / vo - 1)
+    say(f"  oracle rho_l {lo:.7f} rho_v {vo:.7f}; {prec} rho_l {lg:.7f} ({el:.2e}) rho_v {vg:.7f} ({ev:.2e})")
+    assert el <= bar_l and ev <= bar_v
