@@ -1,6 +1,7 @@
 """Throughput of the fused liquid-vapour lattice update on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--precision f32|f64|f16|bf16] [--scheme ab|aa]
+                    [--rounding nearest|stochastic]
                     [--n 4096] [--no-cpu-baseline] [--gpus 1]
     python bench.py --workload batch64 [--steps K] [--coexistence STEPS]
     python bench.py --workload warmstart [--train-runs 2000] [--horizon 5000] [--epochs 20]
@@ -428,6 +429,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="f32", choices=list(STORAGE_BYTES))
     ap.add_argument("--scheme", default="ab", choices=["ab", "aa"])
+    ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
+                    help="rounding of the 16-bit stores (f16/bf16 with the ab scheme)")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
@@ -462,6 +465,8 @@ def main() -> int:
     params = {"Tr0": 0.75, "precision": args.precision, "scheme": args.scheme,
               "rows_per_wave": args.rows_per_wave, "waves_per_block": args.waves_per_block,
               "columns_per_lane": args.columns_per_lane}
+    if args.rounding != "nearest":
+        params["rounding"] = args.rounding
     stream = torch.cuda.Stream()
     solver = lbm.Solver(n, n, params=params, stream=stream)
     d = solver.derived()
@@ -515,7 +520,7 @@ def main() -> int:
         "config": {
             "workload": f"static droplet {n}x{n} periodic D2Q9, R=512, tanh W=4, CS EOS (a~=1, b~=4, R=1, "
                         f"K_EOS=0.479820, K_INT=2.294922), T/Tc=0.75, +-0.5% noise seed 1",
-            "nx": n, "ny": n, "precision": args.precision, "scheme": args.scheme,
+            "nx": n, "ny": n, "precision": args.precision, "scheme": args.scheme, "rounding": args.rounding,
             "bytes_per_node_step": 36 * STORAGE_BYTES[args.precision],
             "launch_shape": f"{shape[0]} rows/wave x {shape[1]} waves/block x {shape[2]} columns/lane",
         },

@@ -54,6 +54,10 @@ extern "C" {
 #define LBM_F16  2  /* FP16 deviations from the rest equilibrium of (rho_ref, T_ref) */
 #define LBM_BF16 3  /* BF16 deviations from the rest equilibrium of (rho_ref, T_ref) */
 
+/* ---- rounding of the 16-bit storage formats --------------------------------- */
+#define LBM_ROUND_NEAREST    0  /* round to nearest even (default)                          */
+#define LBM_ROUND_STOCHASTIC 1  /* unbiased stochastic rounding; see lbm_params.rounding    */
+
 /* ---- update schemes ------------------------------------------------------- */
 #define LBM_SCHEME_AB 0  /* fused single pass, two state buffers (pull streaming)      */
 #define LBM_SCHEME_AA 1  /* in-place AA pattern, one state buffer, plus a density pass */
@@ -104,6 +108,18 @@ typedef struct {
     int32_t columns_per_lane;/* two-buffer kernel: columns per lane, 1 or 2; 0 = auto
                                 (2 for 4- and 2-byte storage with an even nx, else 1);
                                 2 is taken only where allowed                           */
+    int32_t rounding;     /* LBM_F16/LBM_BF16 stores of the two-buffer update:
+                             LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC.  Rounding to
+                             nearest is deterministic per value, so in a nearly steady
+                             state the same values round the same way every step and the
+                             errors accumulate into a bias (coexistence densities move by
+                             percents); stochastic rounding rounds up with probability equal
+                             to the discarded fraction, which removes that bias.  Its random
+                             bits are a hash of the step count and the node, so runs stay
+                             deterministic, and restarts (lbm_load_state) and batched
+                             members stay bitwise equal to uninterrupted single runs.
+                             LBM_EINVAL for other precisions or the AA scheme.
+                             lbm_set_fields rounds to nearest.                       */
 } lbm_params;
 
 /* Fills *p with the paper's numerical-test parameters (varpi = 1/6, gamma1 = -2,
@@ -206,7 +222,7 @@ int lbm_maxwell(const lbm_eos* eos, double Tr, double out[4]);
  * lbm_step on that member alone computes.  The members stay usable through the
  * single-lattice calls (moments, invariants, save/load, even lbm_step); the
  * batch notices a member stepped alone and re-reads its buffers.  Members must
- * outlive the batch and share one precision and one stream, and each must keep
+ * outlive the batch and share one precision, one rounding mode and one stream, and each must keep
  * (18 ny + 17) nx bytes-per-value below 4 GiB (32-bit buffer offsets). */
 typedef struct lbm_batch lbm_batch;  /* opaque; owned by the library */
 
@@ -221,7 +237,7 @@ typedef struct {
 } lbm_batch_shape;
 
 /* Device workspace of a batch of n members in this precision (descriptor table,
- * item offsets, queue counters). */
+ * item offsets, queue counters, per-member step counters). */
 int lbm_batch_workspace_bytes(int32_t n, int32_t precision, size_t* bytes);
 
 /* Groups n >= 1 distinct device contexts.  workspace: device memory of at least

@@ -86,6 +86,11 @@ int check_params(const lbm_params* p) {
         return fail(nullptr, LBM_EINVAL, "waves_per_block must be 0, 1, 2, 4 or 8 (got %d)", w);
     if (p->columns_per_lane < 0 || p->columns_per_lane > 2)
         return fail(nullptr, LBM_EINVAL, "columns_per_lane must be 0, 1 or 2 (got %d)", p->columns_per_lane);
+    if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
+        return fail(nullptr, LBM_EINVAL, "unknown rounding %d", p->rounding);
+    if (p->rounding == LBM_ROUND_STOCHASTIC &&
+        ((p->precision != LBM_F16 && p->precision != LBM_BF16) || p->scheme != LBM_SCHEME_AB))
+        return fail(nullptr, LBM_EINVAL, "stochastic rounding needs LBM_F16 or LBM_BF16 storage and LBM_SCHEME_AB");
     return LBM_OK;
 }
 
@@ -388,8 +393,11 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     for (int64_t k = 0; k < n; ++k) {
         hipError_t e;
         if (c->p.scheme == LBM_SCHEME_AB) {
+            // the step count seeds the stochastic-rounding stream (the constants are
+            // copied into the launch's arguments, so they may change afterwards)
+            c->c64.step = c->c32.step = (uint32_t)c->steps;
             e = lbm_dev::launch_step_ab(c->p.precision, c->consts, c->buf[c->cur], c->buf[c->cur ^ 1], c->shape,
-                                        c->stream);
+                                        c->p.rounding == LBM_ROUND_STOCHASTIC, c->stream);
             if (e == hipSuccess) c->cur ^= 1;
         } else {
             e = lbm_dev::launch_step_aa(c->p.precision, c->consts, c->buf[0], c->rho_scratch, (int)(c->steps & 1),

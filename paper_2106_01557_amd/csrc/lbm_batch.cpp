@@ -30,8 +30,12 @@ struct lbm_batch {
     void* desc_dev = nullptr;
     int32_t* starts_dev = nullptr;
     unsigned* queue_dev = nullptr;
+    uint32_t* steps_dev = nullptr;         // 2 step counters per member (launch parity)
     std::vector<unsigned char> desc_host;  // as uploaded
     std::vector<int32_t> starts_host;
+    std::vector<uint32_t> steps_host;
+    std::vector<int64_t> dev_steps;        // each member's step count as the device counters hold it
+    bool sr = false;                       // stochastic rounding of the 16-bit stores
     int parity = 0;          // parity of the next launch; flips every launch
     bool queue_clean[2] = {true, true};
     bool uploaded = false;
@@ -101,7 +105,7 @@ int plan(lbm_batch* b) {
     } else {
         int64_t blocks = b->shape.blocks;
         if (blocks == 0) {
-            const int per_cu = lbm_dev::batch_blocks_per_cu(b->prec, wpb, 1);
+            const int per_cu = lbm_dev::batch_blocks_per_cu(b->prec, wpb, 1, b->sr);
             if (per_cu <= 0) return bfail(b, LBM_EHIP, "occupancy query failed for the batched kernel");
             blocks = (int64_t)b->cus * per_cu;
         }
@@ -136,10 +140,19 @@ int upload(lbm_batch* b) {
     b->desc_host.assign(b->m.size() * b->desc_size, 0);
     if (b->prec == LBM_F64) fill_desc<double>(b, b->desc_host.data());
     else fill_desc<float>(b, b->desc_host.data());
+    b->steps_host.assign(2 * b->m.size(), 0u);
+    b->dev_steps.assign(b->m.size(), 0);
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        b->steps_host[2 * i] = b->steps_host[2 * i + 1] = (uint32_t)b->m[i]->steps;
+        b->dev_steps[i] = b->m[i]->steps;
+    }
     hipError_t e = hipMemcpyAsync(b->desc_dev, b->desc_host.data(), b->desc_host.size(), hipMemcpyHostToDevice,
                                   b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->starts_dev, b->starts_host.data(), b->starts_host.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->steps_dev, b->steps_host.data(), b->steps_host.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bhip(b, e, "descriptor upload");
@@ -147,7 +160,8 @@ int upload(lbm_batch* b) {
     return LBM_OK;
 }
 
-// True when every member's current buffer is the one the next launch will read.
+// True when every member's current buffer is the one the next launch will read and its
+// step count is the one the device counters hold.
 bool descriptors_fresh(const lbm_batch* b) {
     if (!b->uploaded) return false;
     const size_t off = b->prec == LBM_F64 ? offsetof(lbm_dev::BatchDesc<double>, buf)
@@ -157,6 +171,7 @@ bool descriptors_fresh(const lbm_batch* b) {
         std::memcpy(bufs, b->desc_host.data() + i * b->desc_size + off, sizeof bufs);
         const lbm_ctx* c = b->m[i];
         if (bufs[b->parity] != c->buf[c->cur] || bufs[b->parity ^ 1] != c->buf[c->cur ^ 1]) return false;
+        if (c->steps != b->dev_steps[i]) return false;
     }
     return true;
 }
@@ -169,9 +184,11 @@ int ready(lbm_batch* b) {
 }
 
 void advance_members(lbm_batch* b, int64_t n) {
-    for (lbm_ctx* c : b->m) {
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        lbm_ctx* c = b->m[i];
         c->steps += n;
         c->cur ^= (int)(n & 1);
+        b->dev_steps[i] += n;
     }
 }
 
@@ -182,8 +199,8 @@ int launch_one(lbm_batch* b) {
         e = hipMemsetAsync(b->queue_dev + b->parity * 8, 0, 8 * sizeof(unsigned), b->stream);
         if (e != hipSuccess) return bhip(b, e, "queue reset");
     }
-    e = lbm_dev::launch_step_ab_batch(b->prec, b->desc_dev, b->starts_dev, b->queue_dev, (int)b->m.size(),
-                                      (int)b->nitems, b->parity, b->bl, b->stream);
+    e = lbm_dev::launch_step_ab_batch(b->prec, b->desc_dev, b->starts_dev, b->queue_dev, b->steps_dev,
+                                      (int)b->m.size(), (int)b->nitems, b->parity, b->bl, b->sr, b->stream);
     if (e != hipSuccess) return bhip(b, e, "batched step launch");
     if (b->bl.queue) {
         b->queue_clean[b->parity] = false;
@@ -201,8 +218,8 @@ int capture(lbm_batch* b) {
     if (e != hipSuccess) return bhip(b, e, "begin capture");
     hipError_t le = hipSuccess;
     for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k)
-        le = lbm_dev::launch_step_ab_batch(b->prec, b->desc_dev, b->starts_dev, b->queue_dev, (int)b->m.size(),
-                                           (int)b->nitems, k & 1, b->bl, b->stream);
+        le = lbm_dev::launch_step_ab_batch(b->prec, b->desc_dev, b->starts_dev, b->queue_dev, b->steps_dev,
+                                           (int)b->m.size(), (int)b->nitems, k & 1, b->bl, b->sr, b->stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->stream, &g);
     if (le != hipSuccess) {
@@ -279,7 +296,7 @@ int lbm_batch_workspace_bytes(int32_t n, int32_t precision, size_t* bytes) {
     if (n < 1) return bfail(nullptr, LBM_EINVAL, "a batch needs at least one member");
     if (precision < LBM_F64 || precision > LBM_BF16) return bfail(nullptr, LBM_EINVAL, "unknown precision");
     *bytes = round256((size_t)n * lbm_dev::batch_desc_size(precision)) + round256(((size_t)n + 1) * sizeof(int32_t)) +
-             round256(kQueueCounters * sizeof(unsigned));
+             round256(kQueueCounters * sizeof(unsigned)) + round256(2 * (size_t)n * sizeof(uint32_t));
     return LBM_OK;
 }
 
@@ -299,6 +316,8 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* 
         if (c->p.precision != m0->p.precision)
             return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one precision", i);
         if (c->stream != m0->stream) return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one stream", i);
+        if (c->p.rounding != m0->p.rounding)
+            return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one rounding mode", i);
         if (((size_t)18 * c->lat.ny + 17) * c->lat.nx * lbm_dev::storage_bytes(c->p.precision) + 64 >= ((size_t)1 << 32))
             return bfail(nullptr, LBM_EINVAL, "member %d: %d x %d is too large for a batch (its state must stay below 4 GiB)",
                          i, c->lat.nx, c->lat.ny);
@@ -316,6 +335,7 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* 
     if (!b) return bfail(nullptr, LBM_EINVAL, "out of host memory");
     b->m.assign(members, members + n);
     b->prec = m0->p.precision;
+    b->sr = m0->p.rounding == LBM_ROUND_STOCHASTIC;
     b->stream = m0->stream;
     b->desc_size = lbm_dev::batch_desc_size(b->prec);
     char* w = static_cast<char*>(workspace);
@@ -324,6 +344,8 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* 
     b->starts_dev = reinterpret_cast<int32_t*>(w);
     w += round256(((size_t)n + 1) * sizeof(int32_t));
     b->queue_dev = reinterpret_cast<unsigned*>(w);
+    w += round256(kQueueCounters * sizeof(unsigned));
+    b->steps_dev = reinterpret_cast<uint32_t*>(w);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -15,7 +15,7 @@ template <typename C>
 struct Consts {
     int32_t nx, ny;
     int32_t eos_kind;      // 0 CS, 1 vdW
-    int32_t pad_;
+    uint32_t step;         // steps completed before this launch (the stochastic-rounding stream)
     C G2dx;                // G^2 dx: F_pair = G^2 dx rho sum_i w_i rho(x + e_i dx) e_i/c (Eq. (13))
     C inv_dx;              // grad rho = sum_i w_i rho_i (e_i/c) / dx
     C ax, ay;              // external acceleration
@@ -52,7 +52,8 @@ struct LaunchShape {
 // layout of the state (see load_node): 0 AA even parity, 1 AA odd parity, 2 two-buffer pull
 hipError_t launch_init(int prec, const void* c, void* state, const double* rho, const double* ux,
                        const double* uy, const double* T, int layout, hipStream_t stream);
-hipError_t launch_step_ab(int prec, const void* c, const void* in, void* out, LaunchShape shape,
+// stochastic: 16-bit stores round stochastically (random bits from P.step and the node)
+hipError_t launch_step_ab(int prec, const void* c, const void* in, void* out, LaunchShape shape, bool stochastic,
                           hipStream_t stream);
 // In-place AA pattern: `parity` 0 = even step (own-node slots), 1 = odd step.
 hipError_t launch_step_aa(int prec, const void* c, void* state, double* rho_scratch, int parity,
@@ -92,11 +93,14 @@ struct BatchLaunch {
 
 // `queue` holds 2 x 8 unsigned counters (zero before the first launch).  A queue-mode
 // launch of parity p takes items from counters [p*8, p*8+8) and clears the other eight
-// for the next launch.
-hipError_t launch_step_ab_batch(int prec, const void* desc, const int32_t* starts, unsigned* queue, int nlat,
-                                int nitems, int parity, BatchLaunch bl, hipStream_t stream);
+// for the next launch.  `steps` holds 2 counters per lattice: a launch of parity p reads
+// lattice b's step count from steps[2b + p] and writes it plus one to steps[2b + (p ^ 1)]
+// (so graph replays advance the stochastic-rounding stream without host writes).
+hipError_t launch_step_ab_batch(int prec, const void* desc, const int32_t* starts, unsigned* queue,
+                                uint32_t* steps, int nlat, int nitems, int parity, BatchLaunch bl, bool stochastic,
+                                hipStream_t stream);
 // Resident blocks per CU of the batched kernel for the given precision and block size.
-int batch_blocks_per_cu(int prec, int waves_per_block, int queue);
+int batch_blocks_per_cu(int prec, int waves_per_block, int queue, bool stochastic);
 size_t batch_desc_size(int prec);
 size_t consts_size(int prec);
 size_t storage_bytes(int prec);

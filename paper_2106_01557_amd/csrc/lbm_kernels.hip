@@ -71,6 +71,80 @@ struct Io<__hip_bfloat16, float> {
     }
 };
 
+// ---------------------------------------------------------------------------
+// stochastic rounding of the 16-bit stores (lbm_params.rounding)
+// ---------------------------------------------------------------------------
+// gfx950's v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32 add the top 13 (FP16) or 16 (BF16) bits
+// of a 32-bit random word below the kept mantissa bits and truncate, so a value rounds
+// away from zero with probability equal to its discarded fraction (checked on the GPU
+// over all 2^16 high-half words for values of both signs, normal and subnormal).  The
+// random word of a stored value is h ^ salt: h hashes the step count and the node (the
+// byte offset of the node's column pair within the state, which is the same in every
+// kernel form and in batches), and the salt separates the 18 slots and the two columns
+// of a pair.  The hash is a multiply-xorshift finalizer (the constants of C. Wellons'
+// "lowbias32").
+__host__ __device__ constexpr uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+struct SaltTable {
+    uint32_t v[36];  // [column parity * 18 + slot]
+};
+constexpr SaltTable make_salts() {
+    SaltTable t{};
+    for (uint32_t k = 0; k < 36; ++k) t.v[k] = mix32((k + 1u) * 0x9E3779B9u);
+    return t;
+}
+__device__ constexpr SaltTable kSrSalt = make_salts();
+
+__device__ inline uint32_t sr_key(uint32_t step) { return mix32(step * 0x9E3779B9u + 0x632BE5ABu); }
+
+// hash of the column pair at byte offset o under the step key
+template <typename Off>
+__device__ inline uint32_t sr_node(Off o, uint32_t key) {
+    uint32_t lo = (uint32_t)o;
+    if constexpr (sizeof(Off) > 4) lo ^= (uint32_t)((uint64_t)o >> 32);
+    return mix32(lo ^ key);
+}
+
+// deviation v - ref stochastically rounded; pairs put the first column in the low half
+template <typename S>
+struct Sr16;
+template <>
+struct Sr16<__half> {
+    using V2 = _Float16 __attribute__((ext_vector_type(2)));
+    __device__ static unsigned pack(float a, float b, float ref, uint32_t ra, uint32_t rb) {
+        V2 t = {};
+        t = __builtin_amdgcn_cvt_sr_f16_f32(t, a - ref, ra, false);
+        t = __builtin_amdgcn_cvt_sr_f16_f32(t, b - ref, rb, true);
+        return __builtin_bit_cast(unsigned, t);
+    }
+    __device__ static unsigned short one(float v, float ref, uint32_t r) {
+        V2 t = {};
+        t = __builtin_amdgcn_cvt_sr_f16_f32(t, v - ref, r, false);
+        return (unsigned short)(__builtin_bit_cast(unsigned, t) & 0xffffu);
+    }
+};
+template <>
+struct Sr16<__hip_bfloat16> {
+    using V2 = __bf16 __attribute__((ext_vector_type(2)));
+    __device__ static unsigned pack(float a, float b, float ref, uint32_t ra, uint32_t rb) {
+        V2 t = {};
+        t = __builtin_amdgcn_cvt_sr_bf16_f32(t, a - ref, ra, false);
+        t = __builtin_amdgcn_cvt_sr_bf16_f32(t, b - ref, rb, true);
+        return __builtin_bit_cast(unsigned, t);
+    }
+    __device__ static unsigned short one(float v, float ref, uint32_t r) {
+        V2 t = {};
+        t = __builtin_amdgcn_cvt_sr_bf16_f32(t, v - ref, r, false);
+        return (unsigned short)(__builtin_bit_cast(unsigned, t) & 0xffffu);
+    }
+};
+
 __device__ inline double rcp(double x) { return 1.0 / x; }
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -435,6 +509,11 @@ struct Planes<S, true> {
         Io<S, C>::st(&t, 0, v, ref);
         Bits<S>::st(t, r, valid ? off : drop, ps * (unsigned)i);
     }
+    // 16-bit storage, stochastic rounding with the random word rnd
+    template <typename C>
+    __device__ void st_sr(int i, unsigned off, C v, C ref, uint32_t rnd, bool valid) const {
+        Bits<S>::st(__builtin_bit_cast(S, Sr16<S>::one(v, ref, rnd)), r, valid ? off : drop, ps * (unsigned)i);
+    }
 };
 
 // Non-temporal store of one value through a plain pointer (64-bit address path).
@@ -473,6 +552,12 @@ struct Planes<S, false> {
     __device__ void st(int i, size_t off, C v, C ref, bool valid) const {
         if (valid) stream_store(reinterpret_cast<S*>(base + ps * i + off), v, ref);
     }
+    template <typename C>
+    __device__ void st_sr(int i, size_t off, C v, C ref, uint32_t rnd, bool valid) const {
+        if (valid)
+            __builtin_nontemporal_store(Sr16<S>::one(v, ref, rnd),
+                                        reinterpret_cast<unsigned short*>(base + ps * i + off));
+    }
 };
 
 template <typename C>
@@ -493,6 +578,7 @@ struct Strip {
     unsigned fplane, gplane, fcol, gcol;
     int fdy, gdy;
     float fref, gref;  // 16-bit storage: deviation references of the gather slots' populations
+    uint32_t srkey;    // stochastic rounding: key of this step's random stream
 };
 
 // ref[k] for a per-lane k in [0, 9) by selects (no indexed memory access)
@@ -650,7 +736,7 @@ struct Dens {
 // collide and store only (last row).  The caller swaps the roles of the load targets
 // and the finish sources every row, so no register holding a load in flight is copied.
 // R[0..3] hold the byte offsets of rows y+1 .. y+4 (periodic); yo that of row y.
-template <int kStage, typename S, typename C, bool kBuf>
+template <int kStage, typename S, typename C, bool kBuf, bool kSR>
 __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
                                        const Strip& G, typename OffT<kBuf>::type yo,
                                        const typename OffT<kBuf>::type (&R)[4], C (&fa)[9], const C (&rf)[9],
@@ -677,10 +763,23 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
     C fo[9], go[9];
     collide(P, fa, ga, dc.v, sx, sy, fo, go);
     const typename OffT<kBuf>::type o = yo + G.xc * G.esz;
+    if constexpr (kSR && sizeof(S) == 2) {
+        // the random words of the two-column form: hash of the column pair, salt by
+        // slot and by the column's place in the pair
+        const bool odd = (G.xc & 1u) != 0;
+        const uint32_t h = sr_node(yo + (G.xc & ~1u) * G.esz, G.srkey);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        out.template st<C>(i, o, fo[i], P.ref_f[i], G.owner);
-        out.template st<C>(9 + i, o, go[i], P.ref_g[i], G.owner);
+        for (int i = 0; i < 9; ++i) {
+            out.template st_sr<C>(i, o, fo[i], P.ref_f[i], h ^ (odd ? kSrSalt.v[18 + i] : kSrSalt.v[i]), G.owner);
+            out.template st_sr<C>(9 + i, o, go[i], P.ref_g[i], h ^ (odd ? kSrSalt.v[27 + i] : kSrSalt.v[9 + i]),
+                                  G.owner);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            out.template st<C>(i, o, fo[i], P.ref_f[i], G.owner);
+            out.template st<C>(9 + i, o, go[i], P.ref_g[i], G.owner);
+        }
     }
     if (kStage >= 1) {
         dm = dc;
@@ -692,9 +791,9 @@ __device__ __forceinline__ void ab_row(const Consts<C>& P, const Planes<S, kBuf>
 
 // Update of one work item (a strip of up to 64 columns times `rows` rows) of one
 // lattice.  `w` must be uniform across the wavefront.
-template <typename S, typename C, bool kBuf>
+template <typename S, typename C, bool kBuf, bool kSR>
 __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict__ out, const Consts<C>& P,
-                                         const int w, const int nstrips, const int rows) {
+                                         const int w, const int nstrips, const int rows, const uint32_t step) {
     constexpr bool kCopy = sizeof(S) >= 4;  // pass-through copies (see pass())
     const int lane = threadIdx.x & 63;
     const int strip = w % nstrips, chunk = w / nstrips;
@@ -709,6 +808,7 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
     G.owner = lane < owned;
     G.xc = (unsigned)(G.owner ? x0 + lane : nx - 1);
     G.last = __builtin_amdgcn_readfirstlane(owned - 1);  // a lane index for v_readlane: must be uniform
+    G.srkey = kSR ? sr_key(step) : 0u;
     {
         // halo columns (uniform): x0-1, x0-2, x0+n, x0+n+1 modulo nx
         const unsigned l1 = __builtin_amdgcn_readfirstlane(wrap_row(x0 - 1, nx));
@@ -787,14 +887,14 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
     };
     int y = y0;
     for (; y < y1 - 3; y += 2) {
-        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
+        ab_row<2, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
         advance();
-        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fY, rD, hD, rC, hC, gA, rH, hH, rG, hG, dm, dc, dp);
+        ab_row<2, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fY, rD, hD, rC, hC, gA, rH, hH, rG, hG, dm, dc, dp);
         advance();
     }
     // ragged tail (once per strip): moves restore the roles the last rows expect
     if (y < y1 - 2) {
-        ab_row<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
+        ab_row<2, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
         advance();
         ++y;
         // X now holds f(y+1) and Y f(y): swap them
@@ -810,16 +910,16 @@ __device__ __forceinline__ void ab_strip(const S* __restrict__ in, S* __restrict
         hG = hH;
     }
     if (y < y1 - 1) {
-        ab_row<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
+        ab_row<1, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
         yo = R[0];
         // the last row's f is in Y (X took f(y1), which no row collides)
 #pragma unroll
         for (int i = 0; i < 9; ++i) fX[i] = fY[i];
     }
-    ab_row<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
+    ab_row<0, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fX, rC, hC, rD, hD, gA, rG, hG, rH, hH, dm, dc, dp);
 }
 
-template <typename S, typename C, int WPB, bool kBuf>
+template <typename S, typename C, int WPB, bool kBuf, bool kSR>
 __global__ void __launch_bounds__(64 * WPB)
 k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, const int nstrips,
           const int rows, const int nitems) {
@@ -828,7 +928,7 @@ k_step_ab(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, cons
     // of exec masking, which the DPP shifts rely on)
     const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
     if (w >= nitems) return;
-    ab_strip<S, C, kBuf>(in, out, P, w, nstrips, rows);
+    ab_strip<S, C, kBuf, kSR>(in, out, P, w, nstrips, rows, P.step);
 }
 
 // ---------------------------------------------------------------------------
@@ -985,6 +1085,18 @@ __device__ inline void st2(const Planes<S, false>& B, int i, size_t off, C a, C 
     stream_store(q, a, ref);
     stream_store(q + 1, b, ref);
 }
+// 16-bit pair, stochastic rounding with the random words ra, rb
+template <typename S, typename C>
+__device__ inline void st2_sr(const Planes<S, true>& B, int i, unsigned off, C a, C b, C ref, uint32_t ra,
+                              uint32_t rb, bool valid) {
+    Bits2<S>::stw(Sr16<S>::pack(a, b, ref, ra, rb), B.r, valid ? off : B.drop, B.ps * (unsigned)i);
+}
+template <typename S, typename C>
+__device__ inline void st2_sr(const Planes<S, false>& B, int i, size_t off, C a, C b, C ref, uint32_t ra,
+                              uint32_t rb, bool valid) {
+    if (valid)  // the pair's first column is even: a 4-byte aligned word
+        __builtin_nontemporal_store(Sr16<S>::pack(a, b, ref, ra, rb), reinterpret_cast<unsigned*>(B.base + B.ps * i + off));
+}
 
 // Raw loads of one target row for both columns of the lane, and the gather.
 template <typename S, typename C, bool kBuf>
@@ -1106,7 +1218,7 @@ __device__ inline void finish_g2(const Strip& G, const C* rawa, const C* rawb, C
 // arrays and the caller swaps their roles every row, so no register holding a load in
 // flight is ever copied: a copy would stall the wavefront until that load lands.
 // R[0..3]: byte offsets of the row blocks of rows y+1 .. y+4; yo: row y.
-template <int kStage, typename S, typename C, bool kBuf>
+template <int kStage, typename S, typename C, bool kBuf, bool kSR>
 __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf>& in, const Planes<S, kBuf>& out,
                                         const Strip& G, typename OffT<kBuf>::type yo,
                                         const typename OffT<kBuf>::type (&R)[4], C (&fa)[9], C (&fb)[9],
@@ -1134,10 +1246,21 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
         C foa[9], goa[9], fob[9], gob[9];
         collide(P, fa, ga, dc.a, sxa, sya, foa, goa);
         collide(P, fb, gb, dc.b, sxb, syb, fob, gob);
+        if constexpr (kSR && sizeof(S) == 2) {
+            const uint32_t h = sr_node(o, G.srkey);  // G.xc is the pair's (even) first column
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            st2<S, C>(out, i, o, foa[i], fob[i], P.ref_f[kCls[i]], G.owner);
-            st2<S, C>(out, 9 + i, o, goa[i], gob[i], P.ref_g[kCls[i]], G.owner);
+            for (int i = 0; i < 9; ++i) {
+                st2_sr<S, C>(out, i, o, foa[i], fob[i], P.ref_f[kCls[i]], h ^ kSrSalt.v[i], h ^ kSrSalt.v[18 + i],
+                             G.owner);
+                st2_sr<S, C>(out, 9 + i, o, goa[i], gob[i], P.ref_g[kCls[i]], h ^ kSrSalt.v[9 + i],
+                             h ^ kSrSalt.v[27 + i], G.owner);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                st2<S, C>(out, i, o, foa[i], fob[i], P.ref_f[kCls[i]], G.owner);
+                st2<S, C>(out, 9 + i, o, goa[i], gob[i], P.ref_g[kCls[i]], G.owner);
+            }
         }
     }
     if (kStage >= 1) {
@@ -1149,9 +1272,9 @@ __device__ __forceinline__ void ab_row2(const Consts<C>& P, const Planes<S, kBuf
 }
 
 // One work item of the two-column form: a strip of up to 128 columns (nx even).
-template <typename S, typename C, bool kBuf>
+template <typename S, typename C, bool kBuf, bool kSR>
 __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restrict__ out, const Consts<C>& P,
-                                          const int w, const int nstrips, const int rows) {
+                                          const int w, const int nstrips, const int rows, const uint32_t step) {
     using Off = typename OffT<kBuf>::type;
     const int lane = threadIdx.x & 63;
     const int strip = w % nstrips, chunk = w / nstrips;
@@ -1166,6 +1289,7 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
     G.owner = 2 * lane < owned;
     G.xc = (unsigned)(G.owner ? x0 + 2 * lane : nx - 2);  // first column of the lane's pair
     G.last = __builtin_amdgcn_readfirstlane(owned / 2 - 1);
+    G.srkey = kSR ? sr_key(step) : 0u;
     {
         const unsigned l1 = __builtin_amdgcn_readfirstlane(wrap_row(x0 - 1, nx));
         const unsigned l2 = __builtin_amdgcn_readfirstlane(wrap_row(x0 - 2, nx));
@@ -1238,16 +1362,16 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
     };
     int y = y0;
     for (; y < y1 - 3; y += 2) {
-        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
+        ab_row2<2, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
                                rHa, rHb, hH, dm, dc, dp);
         advance();
-        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fYa, fYb, rDa, rDb, hD, rCa, rCb, hC, gAa, gAb, rHa, rHb, hH,
+        ab_row2<2, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fYa, fYb, rDa, rDb, hD, rCa, rCb, hC, gAa, gAb, rHa, rHb, hH,
                                rGa, rGb, hG, dm, dc, dp);
         advance();
     }
     // ragged tail (once per strip): moves restore the roles the last rows expect
     if (y < y1 - 2) {
-        ab_row2<2, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
+        ab_row2<2, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
                                rHa, rHb, hH, dm, dc, dp);
         advance();
         ++y;
@@ -1268,7 +1392,7 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
         hG = hH;
     }
     if (y < y1 - 1) {
-        ab_row2<1, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
+        ab_row2<1, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG,
                                rHa, rHb, hH, dm, dc, dp);
         yo = R[0];
         // the last row's f is in Y (X took f(y1), which no row collides)
@@ -1278,17 +1402,17 @@ __device__ __forceinline__ void ab_strip2(const S* __restrict__ in, S* __restric
             fXb[i] = fYb[i];
         }
     }
-    ab_row2<0, S, C, kBuf>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG, rHa,
+    ab_row2<0, S, C, kBuf, kSR>(P, Pin, Pout, G, yo, R, fXa, fXb, rCa, rCb, hC, rDa, rDb, hD, gAa, gAb, rGa, rGb, hG, rHa,
                            rHb, hH, dm, dc, dp);
 }
 
-template <typename S, typename C, int WPB, bool kBuf>
+template <typename S, typename C, int WPB, bool kBuf, bool kSR>
 __global__ void __launch_bounds__(64 * WPB)
 k_step_ab2(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, const int nstrips, const int rows,
            const int nitems) {
     const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
     if (w >= nitems) return;
-    ab_strip2<S, C, kBuf>(in, out, P, w, nstrips, rows);
+    ab_strip2<S, C, kBuf, kSR>(in, out, P, w, nstrips, rows, P.step);
 }
 
 // ---------------------------------------------------------------------------
@@ -1302,9 +1426,10 @@ k_step_ab2(const S* __restrict__ in, S* __restrict__ out, const Consts<C> P, con
 // an XCD take items of its range from an atomic counter until it is exhausted.
 // Every lattice must satisfy the 32-bit buffer-offset bound ((18 ny + 17) nx sizeof(S)
 // + 64 < 2^32, checked on the host).
-template <typename S, typename C>
+template <typename S, typename C, bool kSR>
 __device__ __forceinline__ void batch_item(const BatchDesc<C>* __restrict__ desc, const int32_t* __restrict__ starts,
-                                           const int nlat, const int w, const int parity) {
+                                           uint32_t* __restrict__ steps, const int nlat, const int w,
+                                           const int parity) {
     int lo = 0, hi = nlat - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -1316,23 +1441,29 @@ __device__ __forceinline__ void batch_item(const BatchDesc<C>* __restrict__ desc
     const S* in = static_cast<const S*>(D->buf[parity]);
     S* out = const_cast<S*>(static_cast<const S*>(D->buf[parity ^ 1]));
     const int item = __builtin_amdgcn_readfirstlane(w - starts[b]);
+    // the lattice's step count: this launch reads the parity-p counter; the wavefront of
+    // the lattice's first item writes the count of the next launch into the other one
+    // (read by nobody in this launch), with a vector store
+    const uint32_t step = steps[2 * b + parity];
+    if (item == 0 && (threadIdx.x & 63) == 0) steps[2 * b + (parity ^ 1)] = step + 1u;
     if constexpr (sizeof(S) <= 4) {
         if (D->cols == 2) {
-            ab_strip2<S, C, true>(in, out, D->P, item, D->nstrips, D->rows);
+            ab_strip2<S, C, true, kSR>(in, out, D->P, item, D->nstrips, D->rows, step);
             return;
         }
     }
-    ab_strip<S, C, true>(in, out, D->P, item, D->nstrips, D->rows);
+    ab_strip<S, C, true, kSR>(in, out, D->P, item, D->nstrips, D->rows, step);
 }
 
-template <typename S, typename C, int WPB, bool kQueue>
+template <typename S, typename C, int WPB, bool kQueue, bool kSR>
 __global__ void __launch_bounds__(64 * WPB)
 k_step_ab_batch(const BatchDesc<C>* __restrict__ desc, const int32_t* __restrict__ starts,
-                unsigned* __restrict__ queue, const int nlat, const int nitems, const int parity, const int groups) {
+                unsigned* __restrict__ queue, uint32_t* __restrict__ steps, const int nlat, const int nitems,
+                const int parity, const int groups) {
     if (!kQueue) {
         const int w = __builtin_amdgcn_readfirstlane(remap_xcd(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6));
         if (w >= nitems) return;
-        batch_item<S, C>(desc, starts, nlat, w, parity);
+        batch_item<S, C, kSR>(desc, starts, steps, nlat, w, parity);
         return;
     }
     // counters of the other parity were used by the previous launch (complete by stream
@@ -1348,7 +1479,7 @@ k_step_ab_batch(const BatchDesc<C>* __restrict__ desc, const int32_t* __restrict
         if (lane == 0) t = atomicAdd(ctr, 1u);
         const int w = lo + (int)__builtin_amdgcn_readfirstlane(t);
         if (w >= hi) break;
-        batch_item<S, C>(desc, starts, nlat, w, parity);
+        batch_item<S, C, kSR>(desc, starts, steps, nlat, w, parity);
     }
 }
 
@@ -1622,31 +1753,38 @@ struct Launch {
                            u, v, T, P, layout);
         return hipGetLastError();
     }
-    template <bool kBuf>
+    template <bool kBuf, bool kSR>
     static hipError_t step_ab_wpb(const S* i, S* o, const Consts<C>& P, int nstrips, int rows, int nitems, int wpb,
                                   int nblocks, hipStream_t s) {
         switch (wpb) {
-            case 1: hipLaunchKernelGGL((k_step_ab<S, C, 1, kBuf>), dim3(nblocks), dim3(64), 0, s, i, o, P, nstrips, rows, nitems); break;
-            case 2: hipLaunchKernelGGL((k_step_ab<S, C, 2, kBuf>), dim3(nblocks), dim3(128), 0, s, i, o, P, nstrips, rows, nitems); break;
-            case 4: hipLaunchKernelGGL((k_step_ab<S, C, 4, kBuf>), dim3(nblocks), dim3(256), 0, s, i, o, P, nstrips, rows, nitems); break;
-            case 8: hipLaunchKernelGGL((k_step_ab<S, C, 8, kBuf>), dim3(nblocks), dim3(512), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 1: hipLaunchKernelGGL((k_step_ab<S, C, 1, kBuf, kSR>), dim3(nblocks), dim3(64), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 2: hipLaunchKernelGGL((k_step_ab<S, C, 2, kBuf, kSR>), dim3(nblocks), dim3(128), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 4: hipLaunchKernelGGL((k_step_ab<S, C, 4, kBuf, kSR>), dim3(nblocks), dim3(256), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 8: hipLaunchKernelGGL((k_step_ab<S, C, 8, kBuf, kSR>), dim3(nblocks), dim3(512), 0, s, i, o, P, nstrips, rows, nitems); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
-    template <bool kBuf>
+    template <bool kBuf, bool kSR>
     static hipError_t step_ab2_wpb(const S* i, S* o, const Consts<C>& P, int nstrips, int rows, int nitems, int wpb,
                                    int nblocks, hipStream_t s) {
         switch (wpb) {
-            case 1: hipLaunchKernelGGL((k_step_ab2<S, C, 1, kBuf>), dim3(nblocks), dim3(64), 0, s, i, o, P, nstrips, rows, nitems); break;
-            case 2: hipLaunchKernelGGL((k_step_ab2<S, C, 2, kBuf>), dim3(nblocks), dim3(128), 0, s, i, o, P, nstrips, rows, nitems); break;
-            case 4: hipLaunchKernelGGL((k_step_ab2<S, C, 4, kBuf>), dim3(nblocks), dim3(256), 0, s, i, o, P, nstrips, rows, nitems); break;
-            case 8: hipLaunchKernelGGL((k_step_ab2<S, C, 8, kBuf>), dim3(nblocks), dim3(512), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 1: hipLaunchKernelGGL((k_step_ab2<S, C, 1, kBuf, kSR>), dim3(nblocks), dim3(64), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 2: hipLaunchKernelGGL((k_step_ab2<S, C, 2, kBuf, kSR>), dim3(nblocks), dim3(128), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 4: hipLaunchKernelGGL((k_step_ab2<S, C, 4, kBuf, kSR>), dim3(nblocks), dim3(256), 0, s, i, o, P, nstrips, rows, nitems); break;
+            case 8: hipLaunchKernelGGL((k_step_ab2<S, C, 8, kBuf, kSR>), dim3(nblocks), dim3(512), 0, s, i, o, P, nstrips, rows, nitems); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
-    static hipError_t step_ab(const void* cv, const void* in, void* out, LaunchShape sh, hipStream_t s) {
+    static hipError_t step_ab(const void* cv, const void* in, void* out, LaunchShape sh, bool sr, hipStream_t s) {
+        if constexpr (sizeof(S) == 2) {
+            if (sr) return step_ab_sr<true>(cv, in, out, sh, s);
+        }
+        return step_ab_sr<false>(cv, in, out, sh, s);
+    }
+    template <bool kSR>
+    static hipError_t step_ab_sr(const void* cv, const void* in, void* out, LaunchShape sh, hipStream_t s) {
         const Consts<C>& P = *static_cast<const Consts<C>*>(cv);
         if constexpr (sizeof(S) <= 4) {
             if (pair_columns(P.nx) && sh.columns_per_lane != 1) {
@@ -1658,8 +1796,8 @@ struct Launch {
                 const bool kBuf = fits_32bit(P.nx, P.ny, sizeof(S)) && !generic_addressing();
                 const S* i = static_cast<const S*>(in);
                 S* o = static_cast<S*>(out);
-                if (kBuf) return step_ab2_wpb<true>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
-                return step_ab2_wpb<false>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
+                if (kBuf) return step_ab2_wpb<true, kSR>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
+                return step_ab2_wpb<false, kSR>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
             }
         }
         const int nstrips = (P.nx + 63) / 64;
@@ -1673,46 +1811,61 @@ struct Launch {
         // raw buffer addressing needs every offset and the drop offset in 32 bits;
         // LBM_GENERIC_ADDRESSING=1 selects the 64-bit path for any size (for tests)
         const bool kBuf = fits_32bit(P.nx, P.ny, sizeof(S)) && !generic_addressing();
-        if (kBuf) return step_ab_wpb<true>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
-        return step_ab_wpb<false>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
+        if (kBuf) return step_ab_wpb<true, kSR>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
+        return step_ab_wpb<false, kSR>(i, o, P, nstrips, rows, nitems, wpb, nblocks, s);
     }
-    template <int WPB>
-    static hipError_t batch_wpb(const void* d, const int32_t* st, unsigned* q, int nlat, int nitems, int parity,
-                                BatchLaunch bl, hipStream_t s) {
+    template <int WPB, bool kSR>
+    static hipError_t batch_wpb(const void* d, const int32_t* st, unsigned* q, uint32_t* steps, int nlat, int nitems,
+                                int parity, BatchLaunch bl, hipStream_t s) {
         const BatchDesc<C>* desc = static_cast<const BatchDesc<C>*>(d);
         if (bl.queue)
-            hipLaunchKernelGGL((k_step_ab_batch<S, C, WPB, true>), dim3(bl.blocks), dim3(64 * WPB), 0, s, desc, st, q,
-                               nlat, nitems, parity, bl.groups);
+            hipLaunchKernelGGL((k_step_ab_batch<S, C, WPB, true, kSR>), dim3(bl.blocks), dim3(64 * WPB), 0, s, desc, st,
+                               q, steps, nlat, nitems, parity, bl.groups);
         else
-            hipLaunchKernelGGL((k_step_ab_batch<S, C, WPB, false>), dim3(bl.blocks), dim3(64 * WPB), 0, s, desc, st,
-                               q, nlat, nitems, parity, bl.groups);
+            hipLaunchKernelGGL((k_step_ab_batch<S, C, WPB, false, kSR>), dim3(bl.blocks), dim3(64 * WPB), 0, s, desc,
+                               st, q, steps, nlat, nitems, parity, bl.groups);
         return hipGetLastError();
     }
-    static hipError_t step_ab_batch(const void* d, const int32_t* st, unsigned* q, int nlat, int nitems, int parity,
-                                    BatchLaunch bl, hipStream_t s) {
+    template <bool kSR>
+    static hipError_t batch_sr(const void* d, const int32_t* st, unsigned* q, uint32_t* steps, int nlat, int nitems,
+                               int parity, BatchLaunch bl, hipStream_t s) {
         switch (bl.waves_per_block) {
-            case 1: return batch_wpb<1>(d, st, q, nlat, nitems, parity, bl, s);
-            case 2: return batch_wpb<2>(d, st, q, nlat, nitems, parity, bl, s);
-            case 4: return batch_wpb<4>(d, st, q, nlat, nitems, parity, bl, s);
+            case 1: return batch_wpb<1, kSR>(d, st, q, steps, nlat, nitems, parity, bl, s);
+            case 2: return batch_wpb<2, kSR>(d, st, q, steps, nlat, nitems, parity, bl, s);
+            case 4: return batch_wpb<4, kSR>(d, st, q, steps, nlat, nitems, parity, bl, s);
             default: return hipErrorInvalidValue;
         }
     }
-    template <int WPB>
+    static hipError_t step_ab_batch(const void* d, const int32_t* st, unsigned* q, uint32_t* steps, int nlat,
+                                    int nitems, int parity, BatchLaunch bl, bool sr, hipStream_t s) {
+        if constexpr (sizeof(S) == 2) {
+            if (sr) return batch_sr<true>(d, st, q, steps, nlat, nitems, parity, bl, s);
+        }
+        return batch_sr<false>(d, st, q, steps, nlat, nitems, parity, bl, s);
+    }
+    template <int WPB, bool kSR>
     static int occ_wpb(int queue) {
         int n = 0;
         hipError_t e = queue ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &n, reinterpret_cast<const void*>(&k_step_ab_batch<S, C, WPB, true>), 64 * WPB, 0)
+                                   &n, reinterpret_cast<const void*>(&k_step_ab_batch<S, C, WPB, true, kSR>), 64 * WPB, 0)
                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &n, reinterpret_cast<const void*>(&k_step_ab_batch<S, C, WPB, false>), 64 * WPB, 0);
+                                   &n, reinterpret_cast<const void*>(&k_step_ab_batch<S, C, WPB, false, kSR>), 64 * WPB, 0);
         return e == hipSuccess ? n : 0;
     }
-    static int batch_occupancy(int wpb, int queue) {
+    template <bool kSR>
+    static int occ_sr(int wpb, int queue) {
         switch (wpb) {
-            case 1: return occ_wpb<1>(queue);
-            case 2: return occ_wpb<2>(queue);
-            case 4: return occ_wpb<4>(queue);
+            case 1: return occ_wpb<1, kSR>(queue);
+            case 2: return occ_wpb<2, kSR>(queue);
+            case 4: return occ_wpb<4, kSR>(queue);
             default: return 0;
         }
+    }
+    static int batch_occupancy(int wpb, int queue, bool sr) {
+        if constexpr (sizeof(S) == 2) {
+            if (sr) return occ_sr<true>(wpb, queue);
+        }
+        return occ_sr<false>(wpb, queue);
     }
     static hipError_t step_aa(const void* cv, void* st, double* rho, int parity, LaunchShape, hipStream_t s) {
         const Consts<C>& P = *static_cast<const Consts<C>*>(cv);
@@ -1770,9 +1923,9 @@ hipError_t launch_init(int prec, const void* c, void* state, const double* rho, 
                        const double* uy, const double* T, int layout, hipStream_t stream) {
     LBM_DISPATCH(prec, init(c, state, rho, ux, uy, T, layout, stream));
 }
-hipError_t launch_step_ab(int prec, const void* c, const void* in, void* out, LaunchShape shape,
+hipError_t launch_step_ab(int prec, const void* c, const void* in, void* out, LaunchShape shape, bool stochastic,
                           hipStream_t stream) {
-    LBM_DISPATCH(prec, step_ab(c, in, out, shape, stream));
+    LBM_DISPATCH(prec, step_ab(c, in, out, shape, stochastic, stream));
 }
 hipError_t launch_step_aa(int prec, const void* c, void* state, double* rho_scratch, int parity,
                           LaunchShape shape, hipStream_t stream) {
@@ -1791,16 +1944,17 @@ hipError_t launch_invariants(int prec, const void* c, const void* state, int aa_
     LBM_DISPATCH(prec, invariants(c, state, aa_parity, rho, partials, result, stream));
 }
 
-hipError_t launch_step_ab_batch(int prec, const void* desc, const int32_t* starts, unsigned* queue, int nlat,
-                                int nitems, int parity, BatchLaunch bl, hipStream_t stream) {
-    LBM_DISPATCH(prec, step_ab_batch(desc, starts, queue, nlat, nitems, parity, bl, stream));
+hipError_t launch_step_ab_batch(int prec, const void* desc, const int32_t* starts, unsigned* queue,
+                                uint32_t* steps, int nlat, int nitems, int parity, BatchLaunch bl, bool stochastic,
+                                hipStream_t stream) {
+    LBM_DISPATCH(prec, step_ab_batch(desc, starts, queue, steps, nlat, nitems, parity, bl, stochastic, stream));
 }
-int batch_blocks_per_cu(int prec, int waves_per_block, int queue) {
+int batch_blocks_per_cu(int prec, int waves_per_block, int queue, bool stochastic) {
     switch (prec) {
-        case kF64: return Launch<double, double>::batch_occupancy(waves_per_block, queue);
-        case kF32: return Launch<float, float>::batch_occupancy(waves_per_block, queue);
-        case kF16: return Launch<__half, float>::batch_occupancy(waves_per_block, queue);
-        case kBF16: return Launch<__hip_bfloat16, float>::batch_occupancy(waves_per_block, queue);
+        case kF64: return Launch<double, double>::batch_occupancy(waves_per_block, queue, false);
+        case kF32: return Launch<float, float>::batch_occupancy(waves_per_block, queue, false);
+        case kF16: return Launch<__half, float>::batch_occupancy(waves_per_block, queue, stochastic);
+        case kBF16: return Launch<__hip_bfloat16, float>::batch_occupancy(waves_per_block, queue, stochastic);
         default: return 0;
     }
 }

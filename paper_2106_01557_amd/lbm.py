@@ -19,6 +19,7 @@ LBM_OK, LBM_EINVAL, LBM_ESPACE, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2
 EOS_KINDS = {"cs": 0, "vdw": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 SCHEMES = {"ab": 0, "aa": 1}
+ROUNDINGS = {"nearest": 0, "stochastic": 1}
 DERIVED_NAMES = ["Tc", "pc", "T0", "rho_v", "rho_l", "p_s", "cs", "c", "dt", "G2", "a_mf", "kappa", "cv",
                  "C_ref", "beta", "k", "h", "bS", "s_p", "s_q", "s_e", "omega_e", "omega_p", "tau_j_v",
                  "tau_j_l", "h_lv"]
@@ -43,7 +44,7 @@ class _Eos(ctypes.Structure):
 _PARAM_DOUBLES = ["Tr0", "K_int", "varpi", "gamma1", "gamma2", "tau_p", "s_eps", "sigma_e", "sigma_eps",
                   "sigma_q", "sigma_p", "tau_j_v", "lambda_ratio", "cv", "ste", "dTr_ste", "C_ref", "accel_x",
                   "accel_y", "cs_override", "rho_ref", "T_ref"]
-_PARAM_INTS = ["precision", "scheme", "rows_per_wave", "waves_per_block", "columns_per_lane"]
+_PARAM_INTS = ["precision", "scheme", "rows_per_wave", "waves_per_block", "columns_per_lane", "rounding"]
 
 
 class _Params(ctypes.Structure):
@@ -152,6 +153,8 @@ def _params_c(overrides: dict | None) -> _Params:
             v = PRECISIONS[v]
         if k == "scheme" and isinstance(v, str):
             v = SCHEMES[v]
+        if k == "rounding" and isinstance(v, str):
+            v = ROUNDINGS[v]
         if k not in _PARAM_DOUBLES and k not in _PARAM_INTS:
             raise LbmError(LBM_EINVAL, f"unknown parameter {k!r}")
         setattr(p, k, v)
@@ -195,7 +198,8 @@ class Solver:
     """One periodic D2Q9 domain bound to a device workspace and a stream.
 
     params: overrides of the lbm_params fields (see include/lbm.h); 'dx' sets the
-    lattice spacing.  precision: 'f64' | 'f32' | 'f16' | 'bf16'; scheme: 'ab' | 'aa'.
+    lattice spacing.  precision: 'f64' | 'f32' | 'f16' | 'bf16'; scheme: 'ab' | 'aa';
+    rounding (16-bit storage): 'nearest' | 'stochastic'.
     """
 
     def __init__(self, nx: int, ny: int, *, eos: Eos | None = None, params: dict | None = None,

@@ -16,7 +16,8 @@ import numpy as np
 from oracle import lbm as olbm
 from oracle import thermo
 
-_LIB_ONLY = {"precision", "scheme", "rows_per_wave", "waves_per_block", "columns_per_lane", "rho_ref", "T_ref"}
+_LIB_ONLY = {"precision", "scheme", "rows_per_wave", "waves_per_block", "columns_per_lane", "rho_ref", "T_ref",
+             "rounding"}
 
 
 def say(*a):

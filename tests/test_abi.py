@@ -94,8 +94,12 @@ def test_host_constants_match_oracle(lbm, eos_kind, overrides):
     ({"tau_j_v": -1.0}, "tau_j_v"), ({"lambda_ratio": 0.0}, "lambda_ratio"), ({"precision": 7}, "precision"),
     ({"scheme": 3}, "scheme"), ({"waves_per_block": 3}, "waves_per_block"), ({"columns_per_lane": 3}, "columns_per_lane"), ({"cs_override": -1.0}, "cs_override"),
     ({"cv": 0.0, "ste": 0.0}, "cv"), ({"accel_x": float("nan")}, "acceleration"),
+    ({"rounding": 2}, "rounding"), ({"rounding": "stochastic"}, "stochastic"),
+    ({"rounding": "stochastic", "precision": "f32"}, "stochastic"),
+    ({"rounding": "stochastic", "precision": "f16", "scheme": "aa"}, "stochastic"),
 ])
 def test_invalid_parameters_are_rejected_before_any_device_call(lbm, bad, msg):
+    """(stochastic rounding applies to the 16-bit formats of the two-buffer update only)"""
     with pytest.raises(lbm.LbmError) as ei:
         lbm.Solver(16, 16, params=bad, host_only=True)
     assert ei.value.code == lbm.LBM_EINVAL

@@ -33,22 +33,22 @@ def _fields(nx, ny, d, kind, seed):
     return inputs.droplet(nx, ny, d["rho_l"], d["rho_v"], d["T0"], r, 4, eps=0.01, seed=seed)
 
 
-def _make(precision, members=MEMBERS, stream=None):
+def _make(precision, members=MEMBERS, stream=None, extra=None):
     from paper_2106_01557_amd import lbm
     out = []
     for k, (nx, ny, eos, tr, kind) in enumerate(members):
         e = lbm.Eos() if eos == "cs" else lbm.vdw_eos()
-        s = lbm.Solver(nx, ny, eos=e, params={"Tr0": tr, "precision": precision}, stream=stream)
+        s = lbm.Solver(nx, ny, eos=e, params={"Tr0": tr, "precision": precision, **(extra or {})}, stream=stream)
         f = _fields(nx, ny, s.derived(), kind, seed=10 + k)
         s.set_fields(*f.as_tuple())
         out.append((s, f))
     return out
 
 
-def _twins(precision, members=MEMBERS, stream=None):
+def _twins(precision, members=MEMBERS, stream=None, extra=None):
     """Two identical sets of solvers: one for the batch, one stepped alone."""
-    a = _make(precision, members, stream)
-    b = _make(precision, members, stream)
+    a = _make(precision, members, stream, extra)
+    b = _make(precision, members, stream, extra)
     return [s for s, _ in a], [s for s, _ in b]
 
 
@@ -107,6 +107,34 @@ def test_batch_bitwise_other_precisions(precision):
     for s in alone:
         s.step(21)
     _assert_bitwise(mine, alone, precision)
+
+
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+def test_batch_stochastic_rounding_bitwise(precision):
+    """Stochastic rounding draws its random bits from each member's step count, which a
+    batch keeps in device counters (two per member, by launch parity).  Batched members
+    stay bitwise equal to the lattices stepped alone through graph replays in queue mode,
+    an odd start parity, and a member stepped alone by an even count (same buffers,
+    different step count) between batched steps."""
+    import torch
+    from paper_2106_01557_amd import lbm
+    say(f"case: {precision} stochastic rounding, batch bitwise vs alone, graphs + queue")
+    stream = torch.cuda.Stream()
+    mine, alone = _twins(precision, stream=stream, extra={"rounding": "stochastic"})
+    b = lbm.Batch(mine)
+    b.set_shape(rows_per_wave=16, waves_per_block=2, queue=True)
+    b.set_graph(8)
+    for n in (1, 19, 8):
+        b.step(n)
+        for s in alone:
+            s.step(n)
+        _assert_bitwise(mine, alone, f"{precision} sr after {n}")
+    mine[1].step(2)
+    alone[1].step(2)
+    b.step(9)
+    for s in alone:
+        s.step(9)
+    _assert_bitwise(mine, alone, f"{precision} sr after a member stepped alone")
 
 
 def test_batch_fp64_against_oracle():

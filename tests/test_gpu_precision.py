@@ -28,15 +28,19 @@ def droplet_case():
     return model, f, o
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
-def test_16bit_storage_error_vs_fp64_oracle(droplet_case, prec):
+@pytest.mark.parametrize("prec,rounding", [("f32", "nearest"), ("f16", "nearest"), ("bf16", "nearest"),
+                                            ("f16", "stochastic"), ("bf16", "stochastic")])
+def test_16bit_storage_error_vs_fp64_oracle(droplet_case, prec, rounding):
     model, f, o = droplet_case
     d = model.d
-    say(f"case: {prec} storage AB 96x80 droplet, 1000 steps vs FP64 oracle")
-    g, s = gpu_moments(96, 80, f, 1000, params={"precision": prec, "Tr0": 0.75})
+    say(f"case: {prec} storage ({rounding} rounding) AB 96x80 droplet, 1000 steps vs FP64 oracle")
+    params = {"precision": prec, "Tr0": 0.75}
+    if rounding != "nearest":
+        params["rounding"] = rounding
+    g, s = gpu_moments(96, 80, f, 1000, params=params)
     inv = s.invariants()
     assert inv["bad_nodes"] == 0
-    assert_close(g, o, d, BARS[prec], f"{prec} storage droplet")
+    assert_close(g, o, d, BARS[prec], f"{prec} storage ({rounding}) droplet")
 
 
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
@@ -80,3 +84,59 @@ def test_16bit_storage_coexistence_densities_vs_fp64_oracle(slab_case, prec, bar
     el, ev = abs(lg / lo - 1), abs(vg / vo - 1)
     say(f"  oracle rho_l {lo:.7f} rho_v {vo:.7f}; {prec} rho_l {lg:.7f} ({el:.2e}) rho_v {vg:.7f} ({ev:.2e})")
     assert el <= bar_l and ev <= bar_v
+
+
+@pytest.mark.parametrize("prec,bar_l,bar_v", [("f16", 2e-3, 2e-3), ("bf16", 1e-2, 1e-2)])
+def test_stochastic_rounding_coexistence_densities_vs_fp64_oracle(slab_case, prec, bar_l, bar_v):
+    """The same slab with stochastic rounding of the 16-bit stores: rounding up with
+    probability equal to the discarded fraction removes the bias that rounding to
+    nearest accumulates in a nearly steady state."""
+    model, f, o = slab_case
+    say(f"case: {prec} storage, stochastic rounding, AB 64x64 slab, 2000 steps, bulk densities vs FP64 oracle")
+    g, s = gpu_moments(64, 64, f, 2000, params={"precision": prec, "rounding": "stochastic"})
+    assert s.invariants()["bad_nodes"] == 0
+    (lo, vo), (lg, vg) = _bulk(o), _bulk(g)
+    el, ev = abs(lg / lo - 1), abs(vg / vo - 1)
+    e = errors(g, o, model.d)
+    say(f"  oracle rho_l {lo:.7f} rho_v {vo:.7f}; {prec} sr rho_l {lg:.7f} ({el:.2e}) rho_v {vg:.7f} ({ev:.2e}); "
+        f"max errors {e}")
+    assert el <= bar_l and ev <= bar_v
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_stochastic_rounding_is_deterministic_across_forms_and_restarts(droplet_case, prec):
+    """The random bits are a hash of the step count and the node, so: two runs agree
+    bitwise; the one- and two-column kernel forms agree bitwise (ragged 70x45 and the
+    96x80 droplet); a state saved and restored continues bitwise as if never stopped;
+    and the result is not that of rounding to nearest."""
+    model, f, _ = droplet_case
+    d = model.d
+    say(f"case: {prec} stochastic rounding determinism, forms, restart")
+    base = {"precision": prec, "Tr0": 0.75, "rounding": "stochastic", "rows_per_wave": 16}
+    a, _ = gpu_moments(96, 80, f, 300, params=base)
+    b, _ = gpu_moments(96, 80, f, 300, params={**base, "columns_per_lane": 1})
+    for k in a:
+        assert np.array_equal(a[k], b[k]), ("forms", k)
+    c, _ = gpu_moments(96, 80, f, 300, params=base)
+    for k in a:
+        assert np.array_equal(a[k], c[k]), ("rerun", k)
+    r, _ = gpu_moments(96, 80, f, 300, params={**base, "rounding": "nearest"})
+    assert not np.array_equal(a["rho"], r["rho"])
+    g = inputs.random_smooth(70, 45, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.4, 0.04 * d.cs, 0.04, seed=5)
+    x, _ = gpu_moments(70, 45, g, 40, params=base)
+    y, _ = gpu_moments(70, 45, g, 40, params={**base, "columns_per_lane": 1})
+    for k in x:
+        assert np.array_equal(x[k], y[k]), ("ragged forms", k)
+    from tests.parity_helpers import gpu_solver
+    s = gpu_solver(96, 80, params=base)
+    s.set_fields(*f.as_tuple())
+    s.step(131)
+    blob, steps = s.save_state()
+    s.step(69)
+    want = s.moments_numpy()
+    s2 = gpu_solver(96, 80, params=base)
+    s2.load_state(blob, steps)
+    s2.step(69)
+    got = s2.moments_numpy()
+    for k in got:
+        assert np.array_equal(got[k], want[k]), ("restart", k)
