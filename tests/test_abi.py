@@ -188,3 +188,50 @@ def test_batch_validation_before_any_device_call(lbm):
     assert lib.lbm_batch_create(ctypes.byref(out), null, 1, ctypes.c_void_p(1 << 20), 1 << 20) == lbm.LBM_EINVAL
     assert lib.lbm_batch_destroy(None) == lbm.LBM_OK
     s.close()
+
+
+def test_header_is_plain_c_and_the_library_links_from_c(lbm, tmp_path):
+    """include/lbm.h compiles as C99 (-Wall -Werror) and a C program linked against
+    liblbm.so makes host-only calls (defaults, Maxwell query, a host-only context, error
+    strings) with no Python in between."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "abi_check.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "lbm.h"
+int main(void) {
+    lbm_params p; lbm_eos e; lbm_lattice lat = {32, 16, 1.0};
+    if (lbm_default_params(&p) != LBM_OK || lbm_default_eos(&e) != LBM_OK) return 1;
+    double mx[4];
+    if (lbm_maxwell(&e, p.Tr0, mx) != LBM_OK) return 2;
+    lbm_ctx* c = NULL;
+    if (lbm_init(&c, &lat, &e, &p, NULL, 0, NULL) != LBM_OK || c == NULL) return 3;
+    double d[26];
+    if (lbm_derived(c, d, 26) != LBM_OK) return 4;
+    if (lbm_step(c, 1) != LBM_ESTATE) return 5;
+    p.rounding = LBM_ROUND_STOCHASTIC;
+    lbm_ctx* bad = NULL;
+    if (lbm_init(&bad, &lat, &e, &p, NULL, 0, NULL) != LBM_EINVAL || bad != NULL) return 6;
+    if (strlen(lbm_last_error(NULL)) == 0) return 7;
+    printf("%.17g %.17g %.17g %.17g %s\n", mx[0], mx[1], d[3], d[8], lbm_strerror(LBM_ESTATE));
+    return lbm_destroy(c);
+}
+''')
+    lib_dir = os.path.dirname(lbm.LIB_PATH)
+    exe = tmp_path / "abi_check"
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+           "-o", str(exe), "-L", lib_dir, "-llbm", "-Wl,-rpath," + lib_dir, "-Wl,--allow-shlib-undefined"]
+    subprocess.run(cmd, check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, (out.returncode, out.stderr)
+    rv, rl, rv_d, dt, msg = out.stdout.split(maxsplit=4)
+    want = thermo.maxwell(thermo.paper_cs_eos(), 0.8 * thermo.critical_point(thermo.paper_cs_eos())[0])
+    assert float(rv) == pytest.approx(float(want[0]), rel=1e-12)
+    assert float(rl) == pytest.approx(float(want[1]), rel=1e-12)
+    assert float(rv_d) == float(rv)
+    assert float(dt) == pytest.approx(0.401407522, rel=1e-8)
+    assert "order" in msg
