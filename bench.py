@@ -180,7 +180,10 @@ def run_batch(args) -> dict:
             "autotune_ms_per_step": round(tuned_ms, 5),
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(f"step_ab_batch_{args.precision}_batch64",
+                                                 (shape["rows_per_wave"],
+                                                  f"{shape['waves_per_block']}q{int(bool(shape['queue']))}")),
                      "kernel": "k_step_ab_batch", "kernel_ms": round(kernel_ms, 5)},
         "checks": {"bad_nodes": bad,
                    "failed_domains": [(m["side"], m["kind"], round(m["Tr0"], 4))

@@ -103,8 +103,8 @@ typedef struct {
     int32_t precision;    /* LBM_F64, LBM_F32, LBM_F16, LBM_BF16                        */
     int32_t scheme;       /* LBM_SCHEME_AB or LBM_SCHEME_AA                             */
     int32_t rows_per_wave;/* rows one wavefront marches through per launch; 0 = auto
-                             (128; 64 for LBM_F16/LBM_BF16 storage)                   */
-    int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = auto                                 */
+                             (LBM_F32 2, LBM_F64 4, LBM_F16/LBM_BF16 16)               */
+    int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = auto (2; 4 for 16-bit storage)        */
     int32_t columns_per_lane;/* two-buffer kernel: columns per lane, 1 or 2; 0 = auto
                                 (2 for 4- and 2-byte storage with an even nx, else 1);
                                 2 is taken only where allowed                           */
@@ -242,8 +242,9 @@ int lbm_batch_workspace_bytes(int32_t n, int32_t precision, size_t* bytes);
 
 /* Groups n >= 1 distinct device contexts.  workspace: device memory of at least
  * lbm_batch_workspace_bytes() bytes, 256-byte aligned.  Synchronises the stream
- * once (descriptor upload).  Default shape: 32 rows per wave, 4 waves per block,
- * grid mode.  On failure *out is NULL and lbm_batch_last_error(NULL) explains. */
+ * once (descriptor upload).  Default shape: grid mode with the single-lattice
+ * default rows and waves of the precision (lbm_params.rows_per_wave).  On failure
+ * *out is NULL and lbm_batch_last_error(NULL) explains. */
 int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* workspace,
                      size_t workspace_bytes);
 
@@ -261,10 +262,10 @@ int lbm_batch_set_graph(lbm_batch* b, int32_t steps_per_graph);
  * needed only after a member was stepped or reset alone, synchronises). */
 int lbm_batch_step(lbm_batch* b, int64_t n);
 
-/* Times every candidate shape (rows 16/32/64/128 x 1/2/4 waves per block x grid
- * and queue mode) over steps_per_candidate >= 1 steps after 2 warm-up steps, and
- * keeps the fastest.  The timed steps are real steps: every member advances
- * 24 x (steps_per_candidate + 2) steps, bitwise as it would under any fixed
+/* Times every candidate shape (rows 2/4/8/16/32/64/128 x 1/2/4 waves per block x
+ * grid and queue mode) over steps_per_candidate >= 1 steps after 2 warm-up steps,
+ * and keeps the fastest.  The timed steps are real steps: every member advances
+ * 42 x (steps_per_candidate + 2) steps, bitwise as it would under any fixed
  * shape.  Writes the chosen shape and its milliseconds per step (either pointer
  * may be NULL).  Synchronising. */
 int lbm_batch_autotune(lbm_batch* b, int32_t steps_per_candidate, lbm_batch_shape* best,

@@ -324,11 +324,12 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     fill_consts(c, &c->c64);
     fill_consts(c, &c->c32);
     c->consts = p->precision == LBM_F64 ? (const void*)&c->c64 : (const void*)&c->c32;
-    // 16-bit storage halves the bytes per node but not the arithmetic, so it wants two
-    // resident wavefronts per SIMD (shorter strips, twice the work items) to hide latency
-    const bool half = p->precision == LBM_F16 || p->precision == LBM_BF16;
-    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : (half ? 64 : 128);
-    c->shape.waves_per_block = p->waves_per_block > 0 ? p->waves_per_block : 4;
+    // measured defaults (4096^2): short work items, so that vertically adjacent items run
+    // at nearly the same time on one XCD and their shared halo rows come from its L2,
+    // and each item spends a larger share of its life in the batched prologue with many
+    // loads in flight; 16-bit storage is VALU-bound and prefers longer items
+    c->shape.rows_per_wave = p->rows_per_wave > 0 ? p->rows_per_wave : lbm_dev::default_rows(p->precision);
+    c->shape.waves_per_block = p->waves_per_block > 0 ? p->waves_per_block : lbm_dev::default_waves(p->precision);
     {
         // two columns per lane: 4- and 2-byte storage, even rows, two-buffer scheme
         const bool pair_ok = p->precision != LBM_F64 && lat->nx % 2 == 0;

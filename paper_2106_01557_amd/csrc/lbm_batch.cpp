@@ -336,6 +336,7 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* 
     b->m.assign(members, members + n);
     b->prec = m0->p.precision;
     b->sr = m0->p.rounding == LBM_ROUND_STOCHASTIC;
+    b->shape = lbm_batch_shape{lbm_dev::default_rows(b->prec), lbm_dev::default_waves(b->prec), 0, 0};
     b->stream = m0->stream;
     b->desc_size = lbm_dev::batch_desc_size(b->prec);
     char* w = static_cast<char*>(workspace);
@@ -427,7 +428,7 @@ int lbm_batch_autotune(lbm_batch* b, int32_t steps_per_candidate, lbm_batch_shap
     lbm_batch_shape win = b->shape;
     double win_ms = 0;
     bool have = false;
-    static const int kRows[] = {16, 32, 64, 128};
+    static const int kRows[] = {2, 4, 8, 16, 32, 64, 128};
     static const int kWpb[] = {1, 2, 4};
     for (int q = 0; q < 2 && !r; ++q)
         for (int ri : kRows)

@@ -47,6 +47,12 @@ struct LaunchShape {
     int columns_per_lane;  // 0 auto (two where the form allows), 1 or 2
 };
 
+// Default work items of the two-buffer kernel per storage precision (rows per wavefront,
+// wavefronts per workgroup), measured on a 4096^2 lattice: FP32 2 x 2, FP64 4 x 2,
+// 16-bit 16 x 4.
+inline int default_rows(int prec) { return prec == kF64 ? 4 : (prec == kF32 ? 2 : 16); }
+inline int default_waves(int prec) { return prec == kF64 || prec == kF32 ? 2 : 4; }
+
 // All launchers enqueue on `stream` and return the hipError_t of the launch.
 // `state` points at the 18 planes of nx*ny values (9 for f then 9 for g).
 // layout of the state (see load_node): 0 AA even parity, 1 AA odd parity, 2 two-buffer pull

@@ -71,8 +71,7 @@ class Runner:
             self.solvers.append(sol)
             self.consts.append(sol.derived())
         self.width, self.eps = width, eps
-        self.batch = lbm.Batch(self.solvers)
-        self.batch.set_shape(rows_per_wave=32, waves_per_block=4, queue=False)
+        self.batch = lbm.Batch(self.solvers)  # the precision's default launch shape
         d = lambda key: torch.tensor([c[key] for c in self.consts], dtype=torch.float64, device="cuda")  # noqa: E731
         self.rho_v, self.rho_l, self.T0 = d("rho_v"), d("rho_l"), d("T0")
         self.cond = torch.tensor([_cond(s.tr) for s in self.specs], dtype=torch.float64, device="cuda")

@@ -54,7 +54,7 @@ def test_fp32_droplet_1000_steps():
     assert_close(g, o, d, TOL32, "fp32 droplet")
 
 
-@pytest.mark.parametrize("shape", [(32, 4), (1, 1), (7, 2), (5, 8), (200, 4)])
+@pytest.mark.parametrize("shape", [(32, 4), (1, 1), (7, 2), (5, 8), (200, 4), (4, 2), (2, 2)])
 def test_fp64_ragged_tiles_and_launch_shapes(cs_model, shape):
     """70 x 45 spans two strips (62 + 8 columns) and, for most shapes, several row chunks
     with a ragged tail; every launch shape gives the same numbers as the oracle."""
@@ -73,7 +73,7 @@ def test_launch_shapes_are_bitwise_identical(cs_model):
     f = inputs.droplet(130, 67, d.rho_l, d.rho_v, d.T0, 20, 5, eps=0.01, seed=4)
     for prec in ("f64", "f32"):
         ref = None
-        for rows, wpb in [(32, 4), (1, 8), (9, 1), (67, 2)]:
+        for rows, wpb in [(32, 4), (1, 8), (9, 1), (67, 2), (2, 2), (3, 2), (4, 2)]:
             g, _ = gpu_moments(130, 67, f, 25, params={"precision": prec, "rows_per_wave": rows,
                                                        "waves_per_block": wpb})
             if ref is None:
