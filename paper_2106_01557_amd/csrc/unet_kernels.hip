@@ -377,7 +377,9 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
 // A fragment of tile pixel (ty, tx) for tap (dy, dx) is halo pixel
 // (ty + dy + 1) * 18 + (tx + dx + 1).  Pixels are reused across taps from LDS instead
 // of being re-read from L2 per tap (324 pixels loaded per 256 computed).  One LDS
-// buffer (39 KB): four workgroups per CU overlap each other's loads.  LDS rows hold
+// buffer (39 KB); the next channel block's global loads are held in registers while
+// the current block's MFMAs run, then stored to LDS after a barrier (two resident
+// workgroups per CU: the registers, not the LDS, set the occupancy).  LDS rows hold
 // 4 x 16-byte pieces swizzled as in k_conv_lds (the 16 lanes of a fragment read 16
 // consecutive halo pixels); the bf16 epilogue is the same.  Accumulation order: per
 // output, channel block outer, taps inner.
@@ -406,22 +408,54 @@ __global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int wm = wave * WTM;
     const int r16 = lane & 15, k4 = lane >> 4;
+    // the next channel block's global loads are in flight while this block's MFMAs run
+    constexpr int HV = (kHalo * 4 + 255) / 256, WV = (9 * BN * 4 + 255) / 256;
+    uint4 hv[HV], wv[WV];
+    auto gload = [&](int c0) {
+#pragma unroll
+        for (int i = 0; i < HV; ++i) {
+            const int v = t + 256 * i;
+            if (v < kHalo * 4) {
+                const int h = v >> 2, piece = v & 3;
+                const int hr = h / 18, hc = h - 18 * hr;
+                const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
+                hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + c0 + 8 * piece);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < WV; ++i) {
+            const int v = t + 256 * i;
+            if (v < 9 * BN * 4) {
+                const int r = v >> 2, piece = v & 3;
+                const int tap = r / BN, n = r - tap * BN;
+                wv[i] = ld16(a.w + (size_t)(co0 + n) * K + tap * a.Cin + c0 + 8 * piece);
+            }
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < HV; ++i) {
+            const int v = t + 256 * i;
+            if (v < kHalo * 4) {
+                const int h = v >> 2, piece = v & 3;
+                *reinterpret_cast<uint4*>(&Ah[h * 32 + swz(h, piece)]) = hv[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < WV; ++i) {
+            const int v = t + 256 * i;
+            if (v < 9 * BN * 4) {
+                const int r = v >> 2, piece = v & 3;
+                *reinterpret_cast<uint4*>(&Bh[r * 32 + swz(r, piece)]) = wv[i];
+            }
+        }
+    };
+    gload(0);
     for (int c0 = 0; c0 < a.Cin; c0 += 32) {
     if (c0 > 0) __syncthreads();  // the previous channel block's fragments have been read
-    for (int v = t; v < kHalo * 4; v += 256) {
-        const int h = v >> 2, piece = v & 3;
-        const int hr = h / 18, hc = h - 18 * hr;
-        const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
-        const uint4 d = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + c0 + 8 * piece);
-        *reinterpret_cast<uint4*>(&Ah[h * 32 + swz(h, piece)]) = d;
-    }
-    for (int v = t; v < 9 * BN * 4; v += 256) {
-        const int r = v >> 2, piece = v & 3;
-        const int tap = r / BN, n = r - tap * BN;
-        const uint4 d = ld16(a.w + (size_t)(co0 + n) * K + tap * a.Cin + c0 + 8 * piece);
-        *reinterpret_cast<uint4*>(&Bh[r * 32 + swz(r, piece)]) = d;
-    }
+    lstore();
     __syncthreads();
+    if (c0 + 32 < a.Cin) gload(c0 + 32);
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - 3 * (tap / 3);  // offsets into the halo (0..2)
         uint4 A[MT], B[NT];
