@@ -219,6 +219,7 @@ __device__ __forceinline__ int swz(int row, int piece) { return 8 * (piece ^ ((r
 template <int BM, int BN, int WM, int WN, bool kF32>
 __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     static_assert(WM * WN == 4, "four wavefronts");
+    static_assert(BM % 64 == 0 && BN % 16 == 0, "the loader moves 64 rows of 4 vectors per pass");
     constexpr int WTM = BM / WM, WTN = BN / WN, MT = WTM / 16, NT = WTN / 16;
     constexpr int AV = BM / 64;              // 16-byte A vectors per thread per chunk
     constexpr int BV = (BN + 63) / 64;       // B vectors per thread (some threads idle for BN = 32)
@@ -706,6 +707,8 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
     constexpr int GVR = BO / 8, XVR = BK / 8;            // vectors per LDS row
     constexpr int GV = PC * GVR / 256, XV = PC * XVR / 256;  // vectors per thread per chunk
     static_assert(GV >= 1 && XV >= 1, "tile too small for the loader");
+    static_assert(256 % GVR == 0 && 256 % XVR == 0 && PC % (256 / GVR) == 0 && PC % (256 / XVR) == 0,
+                  "the loader steps rows by 256 / (vectors per row) and must tile the chunk exactly");
     __shared__ __attribute__((aligned(16))) bf16_t Gs[2][PC][PO];
     __shared__ __attribute__((aligned(16))) bf16_t Xs[2][PC][PK];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
