@@ -137,6 +137,25 @@ def test_batch_stochastic_rounding_bitwise(precision):
     _assert_bitwise(mine, alone, f"{precision} sr after a member stepped alone")
 
 
+@pytest.mark.parametrize("precision,extra", [("f32", None), ("f16", {"rounding": "stochastic"})])
+def test_batch_with_odd_width_members_bitwise(precision, extra):
+    """Members of odd width take the one-column form inside the batched kernel (the
+    others the two-column form); the mixed batch stays bitwise equal to the lattices
+    stepped alone, at the precision's default shape and in queue mode."""
+    from paper_2106_01557_amd import lbm
+    members = MEMBERS[:2] + [(71, 33, "cs", 0.8, "droplet"), (33, 70, "vdw", 0.75, "slab"), (1, 9, "cs", 0.8, "slab")]
+    say(f"case: {precision} batch with odd-width members {extra or ''}, bitwise vs alone")
+    mine, alone = _twins(precision, members=members, extra=extra)
+    b = lbm.Batch(mine)
+    for shape in (None, dict(rows_per_wave=3, waves_per_block=2, queue=True)):
+        if shape:
+            b.set_shape(**shape)
+        b.step(23)
+        for s in alone:
+            s.step(23)
+        _assert_bitwise(mine, alone, f"{precision} odd widths {shape}")
+
+
 def test_batch_fp64_against_oracle():
     """Two FP64 members (CS droplet at Tr 0.8, vdW slab at Tr 0.7) after 300 batched
     steps match the FP64 oracle run on each alone."""

@@ -166,3 +166,15 @@ def test_16bit_generic_addressing_path_matches_buffer_path(droplet_case, monkeyp
         e = errors(a, b, d)
         say(f"  paths differ by {e}")
         assert max(e.values()) <= (2e-3 if prec == "f16" else 1e-2)
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_16bit_storage_aa_scheme_vs_fp64_oracle(droplet_case, prec):
+    """The in-place AA scheme with 16-bit storage (density pass, then the in-place
+    collide-stream, both through the per-value conversions) meets the same bars as the
+    two-buffer form against the FP64 oracle."""
+    model, f, o = droplet_case
+    say(f"case: {prec} storage AA 96x80 droplet, 1000 steps vs FP64 oracle")
+    g, s = gpu_moments(96, 80, f, 1000, params={"precision": prec, "Tr0": 0.75, "scheme": "aa"})
+    assert s.invariants()["bad_nodes"] == 0
+    assert_close(g, o, model.d, BARS[prec], f"{prec} storage AA droplet")
