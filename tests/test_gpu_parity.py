@@ -293,3 +293,19 @@ def test_fp32_full_size_sampled():
 
 def test_fp64_full_size_sampled():
     _sampled_full_size("f64", TOL64)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_near_critical_temperature_matches_oracle(prec, tol):
+    """T/Tc = 0.95, a liquid around its coexistence density (linearly stable, so rounding
+    differences are not amplified): the equation of state is evaluated in the arithmetic
+    precision (FP32 for the FP32 form), where p_EOS cancels by a factor of about 14 but
+    p_BE, which enters the collision, does not cancel."""
+    model = oracle_model("cs", {"Tr0": 0.95})
+    d = model.d
+    say(f"case: {prec} AB 64x48 near-critical liquid (T/Tc 0.95) random smooth, 300 steps")
+    f = inputs.random_smooth(64, 48, d.rho_l, d.T0, 0.05, 0.03 * d.cs, 0.02, seed=31)
+    o, _ = oracle_moments(model, f, 300)
+    g, s = gpu_moments(64, 48, f, 300, params={"precision": prec, "Tr0": 0.95})
+    assert s.invariants()["bad_nodes"] == 0
+    assert_close(g, o, d, tol, f"{prec} near critical")
