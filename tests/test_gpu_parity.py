@@ -134,25 +134,27 @@ def test_fp64_edge_shapes(cs_model, nx, ny):
     assert_close(g, o, d, TOL64, f"{nx}x{ny}")
 
 
-def test_fp64_vdw_droplet():
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_vdw_droplet(prec, tol):
     model = oracle_model("vdw", {"K_int": 1.0})
     d = model.d
-    say("case: FP64 AB vdW 48x48 droplet, 300 steps")
+    say(f"case: {prec} AB vdW 48x48 droplet, 300 steps")
     f = inputs.droplet(48, 48, d.rho_l, d.rho_v, d.T0, 12, 4, eps=0.01, seed=5)
-    g, _ = gpu_moments(48, 48, f, 300, eos_kind="vdw", params={"precision": "f64", "K_int": 1.0})
+    g, _ = gpu_moments(48, 48, f, 300, eos_kind="vdw", params={"precision": prec, "K_int": 1.0})
     o, _ = oracle_moments(model, f, 300)
-    assert_close(g, o, d, TOL64, "vdw")
+    assert_close(g, o, d, tol, f"{prec} vdw")
 
 
-def test_fp64_external_acceleration(cs_model):
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_external_acceleration(cs_model, prec, tol):
     p = {"accel_x": 2e-4, "accel_y": -1e-4}
     model = oracle_model("cs", p)
     d = model.d
-    say("case: FP64 AB 40x36 droplet with acceleration, 200 steps")
+    say(f"case: {prec} AB 40x36 droplet with acceleration, 200 steps")
     f = inputs.droplet(40, 36, d.rho_l, d.rho_v, d.T0, 10, 4, eps=0.01, seed=6)
-    g, _ = gpu_moments(40, 36, f, 200, params=dict(p, precision="f64"))
+    g, _ = gpu_moments(40, 36, f, 200, params=dict(p, precision=prec))
     o, _ = oracle_moments(model, f, 200)
-    assert_close(g, o, d, TOL64, "accel")
+    assert_close(g, o, d, tol, f"{prec} accel")
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
