@@ -326,3 +326,27 @@ def test_low_temperature_slab_matches_oracle(prec, tol):
     g, s = gpu_moments(64, 48, f, 300, params={"precision": prec, "Tr0": 0.7})
     assert s.invariants()["bad_nodes"] == 0
     assert_close(g, o, d, tol, f"{prec} low-T slab")
+
+
+# every model parameter away from its default and from the others, so that a swapped or
+# dropped constant in the kernel (several rates equal 1 by default) changes the result
+# (sigma_q above 1 together with tau_j_v = 0.15 is unstable in the oracle and on the GPU alike)
+GENERAL_PARAMS = {"tau_p": 0.7, "varpi": 0.12, "gamma1": -1.5, "gamma2": 1.7, "s_eps": 1.3, "sigma_e": 1.15,
+                  "sigma_eps": 0.9, "sigma_q": 0.85, "sigma_p": 0.8, "tau_j_v": 0.15, "lambda_ratio": 6.0,
+                  "cv": 5.0, "C_ref": 0.07, "Tr0": 0.78}
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_general_model_parameters_match_oracle(prec, tol):
+    """Moving droplet (u = 0.05 c_s) with every relaxation rate, model coefficient and
+    heat-capacity constant distinct: all S, L and Y couplings of the collision are active
+    and weighted differently, 200 steps against the oracle."""
+    model = oracle_model("cs", GENERAL_PARAMS)
+    d = model.d
+    say(f"case: {prec} AB 56x40 moving droplet, general parameters, 200 steps")
+    f = inputs.droplet(56, 40, d.rho_l, d.rho_v, d.T0, 11, 4, eps=0.01, seed=12)
+    f = inputs.Fields(f.rho, f.ux + 0.05 * d.cs, f.uy - 0.03 * d.cs, f.T)
+    o, _ = oracle_moments(model, f, 200)
+    g, s = gpu_moments(56, 40, f, 200, params=dict(GENERAL_PARAMS, precision=prec))
+    assert s.invariants()["bad_nodes"] == 0
+    assert_close(g, o, d, tol, f"{prec} general parameters")
