@@ -230,7 +230,10 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nbytes = ctypes.c_size_t()
         _check(_lib.lbm_workspace_bytes(ctypes.byref(self._lat), ctypes.byref(self._p), ctypes.byref(nbytes)))
-        with torch.cuda.device(self.device):
+        # allocated on the stream the library uses it on: torch's caching allocator then
+        # reuses the memory after this Solver is gone only in that stream's order, after
+        # the work still queued on it
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
         self.workspace = raw[off:off + nbytes.value]
@@ -346,7 +349,7 @@ class Batch:
         code = _lib.lbm_batch_workspace_bytes(len(self.members), p, ctypes.byref(nbytes))
         if code != LBM_OK:
             raise LbmError(code, _lib.lbm_batch_last_error(None).decode())
-        with torch.cuda.device(self.device):
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):  # see Solver
             raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
         self._raw = raw
