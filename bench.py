@@ -192,6 +192,23 @@ def run_batch(args) -> dict:
     if args.coexistence > 0:
         out["coexistence"] = batch_coexistence(b, sols, spec, args.coexistence, args.check_every,
                                                wall * 1e3 / args.steps)
+    if args.alone_steps > 0:
+        # the plain method on the same domains: each lattice advanced alone by the
+        # single-lattice call (one launch per step, its default launch shape), one
+        # lattice after another on the same stream.  Every step is bitwise the one the
+        # batch computes, so the wall-clock ratio is the time-to-coexistence speed-up.
+        k = args.alone_steps
+        for sol in sols:
+            sol.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sol in sols:
+            sol.step(k)
+        torch.cuda.synchronize()
+        alone_ms = (time.perf_counter() - t0) * 1e3 / k
+        out["alone"] = {"ms_per_step": round(alone_ms, 5), "steps": k,
+                        "batched_speedup": round(alone_ms / (wall * 1e3 / args.steps), 3),
+                        "what": "each domain stepped by the single-lattice call, one domain after another"}
     return out
 
 
@@ -425,6 +442,8 @@ def main() -> int:
     ap.add_argument("--compare-steps", type=int, default=20000)
     ap.add_argument("--autotune-steps", type=int, default=5)
     ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--alone-steps", type=int, default=200,
+                    help="batch64: also time this many steps of each domain stepped alone (0 = skip)")
     ap.add_argument("--coexistence", type=int, default=0,
                     help="batch64: steps of the coexistence run after the timed steps (0 = skip)")
     ap.add_argument("--check-every", type=int, default=500)
