@@ -800,20 +800,22 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
                 part[(size_t)(cb + wo + 16 * m + g4 + r) * a.Kt + kb + wk + 16 * n + i16] = acc[m][n][r];
 }
 
-// Halo-tile weight gradient (used for C_in = C_out = 32, H and W multiples of 16; the
-// kernel handles C_in % 32 == 0 and C_out % 32 == 0).  A workgroup owns 32 output
-// channels and one block of 32 input channels and
-// walks a slab of 16 x 16 pixel tiles.  Per tile it loads g (256 pixels x 32 channels)
-// and the 18 x 18 pixels of the input tile with its periodic halo, once each, and
-// forms the columns of all nine taps out of LDS: for 8 consecutive pixels of a tile
-// row the tap-shifted halo pixels are consecutive rows, so the transposing read
-// (as in k_wgrad_tr) yields the MFMA fragment directly.  Row pitch 48 elements
-// (96 bytes): the 4 rows of one read sit on distinct bank groups.  The 18 column
-// blocks (9 taps x 2 halves of the 32 channels) are dealt to the four wavefronts
-// round robin, each for both 16-channel halves of the outputs.  The bias gradient
-// is summed per thread (FP32) over the g values it loads and combined in a fixed
-// order.  The partial sums per slab go to the same [slab][C_out][Kt] layout as the
-// other forms.
+// Halo-tile weight gradient (C_in % 32 == 0, C_out = 32 or a multiple of 64, H and W
+// multiples of 16: every layer of the network but the first).  A workgroup owns OC =
+// 32 or 64 output channels and one block of 32 input channels and walks a slab of
+// 16 x 16 pixel tiles.  Per tile it loads g (256 pixels x OC channels) and the 18 x 18
+// pixels of the input tile with its periodic halo, once each, and forms the columns
+// of all nine taps out of LDS: for 8 consecutive pixels of a tile row the tap-shifted
+// halo pixels are consecutive rows, so the transposing read (as in k_wgrad_tr) yields
+// the MFMA fragment directly.  Each input value is therefore read once per output
+// tile, where the im2col form reads it once per tap.  Row pitches OC + 16 (g) and 48
+// (halo) elements keep the 4 rows of one read on distinct bank groups.  The 18 column
+// blocks (9 taps x 2 halves of the 32 input channels) are dealt to the four
+// wavefronts round robin, each for all OC / 16 output blocks, so a halo fragment
+// feeds OC / 16 MFMAs.  The next tile's loads are held in registers while the current
+// tile's MFMAs run.  The bias gradient is summed per thread (FP32) over the g values
+// it loads and combined in a fixed order.  The partial sums per slab go to the same
+// [slab][C_out][Kt] layout as the other forms.
 constexpr int kWgPitch = 48;
 
 __device__ __forceinline__ bf16x8 halo_frag(const bf16_t* Hs, int ks, int dy, int dx, int c0, int lane) {
@@ -832,61 +834,93 @@ __device__ __forceinline__ bf16x8 halo_frag(const bf16_t* Hs, int ks, int dy, in
     return as_frag(u);
 }
 
+template <int OC>
 __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
     constexpr int NCB = 5;  // column blocks per wavefront (18 over 4: 5, 5, 4, 4)
-    __shared__ __attribute__((aligned(16))) bf16_t Gs[256 * kWgPitch];
+    constexpr int GP = OC + 16;     // row pitch of the g tile (OC channels + 16: distinct bank groups)
+    constexpr int PPR = OC / 8;     // 16-byte pieces per pixel of g
+    constexpr int RP = 256 / PPR;   // g pixels loaded per pass of the workgroup
+    constexpr int MH = OC / 16;     // 16-row output blocks
+    __shared__ __attribute__((aligned(16))) bf16_t Gs[256 * GP];
     __shared__ __attribute__((aligned(16))) bf16_t Hs[kHalo * kWgPitch];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     // flat grid: input-channel blocks, then output-channel blocks, then slabs
     const int L = xcd_block(blockIdx.x, gridDim.x);
     const int cc = L % a.ktiles, rest = L / a.ktiles, ob = rest % a.ctiles, z = rest / a.ctiles;
-    const int c0 = cc * 32, o0 = ob * 32;
+    const int c0 = cc * 32, o0 = ob * OC;
     const int tb = z * a.slab, te = min(a.P >> 8, tb + a.slab);
     const int Hm = (1 << a.lh) - 1, Wm = (1 << a.lw) - 1;
     const int txs = a.lw - 4, tys = a.lh - 4;
-    const int gpiece = t & 3;  // this thread's g channels: o0 + 8 gpiece .. + 7
-    f32x4 acc[2][NCB];
+    const int gpiece = t % PPR;  // this thread's g channels: o0 + 8 gpiece .. + 7
+    f32x4 acc[MH][NCB];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < MH; ++h)
 #pragma unroll
         for (int i = 0; i < NCB; ++i) acc[h][i] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int tile = tb; tile < te; ++tile) {
+    // the next tile's g and halo loads are in flight (in registers) while this tile's
+    // MFMAs run; the registers cost no occupancy (the LDS tiles already allow two
+    // workgroups per CU)
+    constexpr int HV = (kHalo * 4 + 255) / 256;
+    uint4 gv[PPR], hv[HV];
+    auto gload = [&](int tile) {
         const int tx0 = (tile & ((1 << txs) - 1)) << 4;
         const int ty0 = ((tile >> txs) & ((1 << tys) - 1)) << 4;
         const int img = (tile >> (txs + tys)) << (a.lw + a.lh);
+#pragma unroll
+        for (int i = 0; i < PPR; ++i) {
+            const int q = t / PPR + RP * i;  // tile pixel (row q >> 4, column q & 15)
+            const size_t p = (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15));
+            gv[i] = ld16(a.g + p * a.ldg + o0 + 8 * gpiece);
+        }
+#pragma unroll
+        for (int i = 0; i < HV; ++i) {
+            const int v = t + 256 * i;
+            if (v < kHalo * 4) {
+                const int h = v >> 2, piece = v & 3;
+                const int hr = h / 18, hc = h - 18 * hr;
+                const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
+                hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + c0 + 8 * piece);
+            }
+        }
+    };
+    if (tb < te) gload(tb);
+    for (int tile = tb; tile < te; ++tile) {
         if (tile != tb) __syncthreads();  // the previous tile's fragments have been read
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int q = (t >> 2) + 64 * i;  // tile pixel (row q >> 4, column q & 15)
-            const size_t p = (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15));
-            const uint4 v = ld16(a.g + p * a.ldg + o0 + 8 * gpiece);
-            *reinterpret_cast<uint4*>(&Gs[q * kWgPitch + 8 * gpiece]) = v;
+        for (int i = 0; i < PPR; ++i) {
+            const int q = t / PPR + RP * i;
+            *reinterpret_cast<uint4*>(&Gs[q * GP + 8 * gpiece]) = gv[i];
             float f[8];
-            unpack8(v, f);
+            unpack8(gv[i], f);
 #pragma unroll
             for (int j = 0; j < 8; ++j) bsum[j] += f[j];
         }
-        for (int v = t; v < kHalo * 4; v += 256) {
-            const int h = v >> 2, piece = v & 3;
-            const int hr = h / 18, hc = h - 18 * hr;
-            const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
-            const uint4 d = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + c0 + 8 * piece);
-            *reinterpret_cast<uint4*>(&Hs[h * kWgPitch + 8 * piece]) = d;
+#pragma unroll
+        for (int i = 0; i < HV; ++i) {
+            const int v = t + 256 * i;
+            if (v < kHalo * 4) {
+                const int h = v >> 2, piece = v & 3;
+                *reinterpret_cast<uint4*>(&Hs[h * kWgPitch + 8 * piece]) = hv[i];
+            }
         }
         __syncthreads();
+        if (tile + 1 < te) gload(tile + 1);
 #pragma unroll 2
         for (int ks = 0; ks < 8; ++ks) {
-            const bf16x8 A0 = tr_frag<kWgPitch>(reinterpret_cast<const bf16_t(*)[kWgPitch]>(Gs), ks * 32, 0, lane);
-            const bf16x8 A1 = tr_frag<kWgPitch>(reinterpret_cast<const bf16_t(*)[kWgPitch]>(Gs), ks * 32, 16, lane);
+            bf16x8 A[MH];
+#pragma unroll
+            for (int h = 0; h < MH; ++h)
+                A[h] = tr_frag<GP>(reinterpret_cast<const bf16_t(*)[GP]>(Gs), ks * 32, 16 * h, lane);
 #pragma unroll
             for (int i = 0; i < NCB; ++i) {
                 const int cb = wave + 4 * i;
                 if (cb < 18) {
                     const int tap = cb >> 1, dy = tap / 3, dx = tap - 3 * (tap / 3);
                     const bf16x8 B = halo_frag(Hs, ks, dy, dx, 16 * (cb & 1), lane);
-                    acc[0][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B, acc[0][i], 0, 0, 0);
-                    acc[1][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B, acc[1][i], 0, 0, 0);
+#pragma unroll
+                    for (int h = 0; h < MH; ++h)
+                        acc[h][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], B, acc[h][i], 0, 0, 0);
                 }
             }
         }
@@ -899,21 +933,21 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
         if (cb >= 18) continue;
         const int k = (cb >> 1) * a.Cin + c0 + 16 * (cb & 1) + i16;
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < MH; ++h)
 #pragma unroll
             for (int r = 0; r < 4; ++r) part[(size_t)(o0 + 16 * h + g4 + r) * a.Kt + k] = acc[h][i][r];
     }
     if (cc == 0) {
-        // bias: the 64 threads holding each 8-channel piece, combined in thread order
+        // bias: the RP threads holding each 8-channel piece, combined in thread order
         __syncthreads();
         float* red = reinterpret_cast<float*>(Gs);
 #pragma unroll
         for (int j = 0; j < 8; ++j) red[t * 8 + j] = bsum[j];
         __syncthreads();
-        if (t < 32) {
+        if (t < OC) {
             const int piece = t >> 3, j = t & 7;
             float s = 0.f;
-            for (int u = 0; u < 64; ++u) s += red[(4 * u + piece) * 8 + j];
+            for (int u = 0; u < RP; ++u) s += red[(PPR * u + piece) * 8 + j];
             part[(size_t)(o0 + t) * a.Kt + a.K] = s;
         }
     }
@@ -1358,14 +1392,14 @@ struct WgPlan {
 WgPlan wgrad_plan(int P, int lh, int lw, int Cin, int Cout) {
     WgPlan w;
     const int K = 9 * Cin;
-    // (measured: with more channels the per-block re-reads of g and of the halo cost more
-    // than the tap reuse saves, and k_wgrad_tr is faster)
-    w.halo = Cin == 32 && Cout == 32 && lh >= 4 && lw >= 4;
+    // the halo-tile form wherever its tiles fit: with the next tile prefetched it beats
+    // the im2col form on every such layer of the network (measured, 256^2 x 16)
+    w.halo = Cin % 32 == 0 && (Cout == 32 || Cout % 64 == 0) && lh >= 4 && lw >= 4;
     if (w.halo) {
         w.tr = false;
-        w.CT = 32;
+        w.CT = Cout % 64 == 0 ? 64 : 32;
         w.ktiles = Cin / 32;
-        w.ctiles = Cout / 32;
+        w.ctiles = Cout / w.CT;
         w.Kt = (K + 1 + 31) / 32 * 32;
         const int tiles = P >> 8;
         int slabs = (512 + w.ktiles * w.ctiles - 1) / (w.ktiles * w.ctiles);
@@ -1507,7 +1541,9 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const dim3 grid(p.ktiles, p.ctiles, p.slabs);
     if (p.halo) {
-        hipLaunchKernelGGL(k_wgrad_halo, dim3(p.ktiles * p.ctiles * p.slabs), dim3(256), 0, s, a);
+        const dim3 flat(p.ktiles * p.ctiles * p.slabs);
+        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_halo<64>), flat, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_wgrad_halo<32>), flat, dim3(256), 0, s, a);
     } else if (p.tr) {
         const dim3 flat(p.ktiles * p.ctiles * p.slabs);
         if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_tr<64, 256, 32, 2>), flat, dim3(256), 0, s, a);

@@ -487,7 +487,8 @@ def test_conv3x3_large_bf16_epilogue(case):
     assert (got[m <= 0] == 0).all()
 
 
-@pytest.mark.parametrize("case", [(1, 64, 64, 96, 32), (1, 64, 64, 64, 64), (2, 32, 32, 128, 128), (1, 16, 256, 32, 32)],
+@pytest.mark.parametrize("case", [(1, 64, 64, 96, 32), (1, 64, 64, 64, 64), (2, 32, 32, 128, 128), (1, 16, 256, 32, 32),
+                                  (1, 32, 32, 192, 64)],
                          ids=lambda c: "x".join(map(str, c)))
 def test_conv3x3_large_input_and_weight_gradients(case):
     """Input gradient (flipped weights) and weight gradient at thousands of pixels: the
