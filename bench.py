@@ -75,16 +75,33 @@ def cpu_baseline(seconds: float) -> dict:
     n = 256
     f = inputs.droplet(n, n, d.rho_l, d.rho_v, d.T0, 32, 4, eps=0.005, seed=1)
     st = olbm.init_state(model, *f.as_tuple())
-    st = olbm.step(model, st)  # warm-up
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        st = olbm.step(model, st)
-        steps += 1
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # one thread: any BLAS call the oracle makes stays serial
+        st = olbm.step(model, st)  # warm-up
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            st = olbm.step(model, st)
+            steps += 1
+        dt = time.perf_counter() - t0
     assert np.isfinite(st.f).all()
     return {"value": round(n * n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"FP64 numpy oracle, {n}x{n} droplet R=32 (same recipe), {steps} steps in {dt:.1f} s, "
-                      f"single thread (numpy einsum/roll loops, no BLAS)"}
+                      f"one thread (numpy einsum/roll, BLAS pools limited to 1) on {_host_cpu()}"}
+
+
+def _host_cpu() -> str:
+    """The host's CPU model and logical core count, for the baseline's record."""
+    import os
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical cores"
 
 
 def batch_members(seed: int = 2, count: int = 64):
