@@ -67,7 +67,9 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
                        float* dw, float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H,
                        int32_t W, int32_t C_in, int32_t C_out, void* stream);
 
-/* 2x2 max pooling with stride 2: y[n,Y,X,c] = max of x over rows 2Y..2Y+1, cols 2X..2X+1. */
+/* 2x2 max pooling with stride 2: y[n,Y,X,c] = max of x over rows 2Y..2Y+1, cols 2X..2X+1.
+ * The four 2x2 calls take C a multiple of 8 and need N * H * W * C / 8 < 2^31, with
+ * H, W the full-resolution sizes (UNET_EINVAL otherwise). */
 int unet_maxpool2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t ldy, int32_t offy,
                       int32_t N, int32_t H, int32_t W, int32_t C, void* stream);
 

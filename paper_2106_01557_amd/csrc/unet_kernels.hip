@@ -1340,6 +1340,13 @@ int check_geo(int N, int H, int W, int* lh, int* lw) {
     return UNET_OK;
 }
 
+// one thread per 8 channels of a full-resolution pixel must fit the int thread index
+int check_threads(int N, int H, int W, int C) {
+    if ((int64_t)N * H * W * (C / 8) >= ((int64_t)1 << 31))
+        return fail(UNET_EINVAL, "N H W C/8 must stay below 2^31 (got %d, %d, %d, %d)", N, H, W, C);
+    return UNET_OK;
+}
+
 template <int MT, int NT>
 void launch_conv(const ConvArgs& a, bool tap_outer, bool f32, hipStream_t s) {
     const dim3 grid((a.P + 64 * MT - 1) / (64 * MT), (a.Cout + 16 * NT - 1) / (16 * NT));
@@ -1564,6 +1571,7 @@ int unet_maxpool2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
     if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_threads(N, H, W, C))) return r;
     if ((r = check_tensor("x", x, ldx, offx, C, false)) || (r = check_tensor("y", y, ldy, offy, C, false))) return r;
     const Geo g{N, lh, lw, C};
     const int total = N * (H / 2) * (W / 2) * (C / 8);
@@ -1578,6 +1586,7 @@ int unet_maxpool2_bwd(const void* x, int32_t ldx, int32_t offx, const void* dy, 
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
     if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_threads(N, H, W, C))) return r;
     if ((r = check_tensor("x", x, ldx, offx, C, false)) || (r = check_tensor("dy", dy, lddy, offdy, C, false)) ||
         (r = check_tensor("add", add, lda, offa, C, true)) || (r = check_tensor("dx", dx, lddx, offdx, C, false)))
         return r;
@@ -1595,6 +1604,7 @@ int unet_upsample2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_
     int lh, lw, r;
     if ((r = check_geo(N, 2 * H, 2 * W, &lh, &lw))) return r;
     if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_threads(N, 2 * H, 2 * W, C))) return r;
     if ((r = check_tensor("x", x, ldx, offx, C, false)) || (r = check_tensor("y", y, ldy, offy, C, false))) return r;
     const Geo g{N, lh, lw, C};
     const int total = N * H * W * (C / 8);
@@ -1609,6 +1619,7 @@ int unet_upsample2_bwd(const void* dy, int32_t lddy, int32_t offdy, const void* 
     int lh, lw, r;
     if ((r = check_geo(N, 2 * H, 2 * W, &lh, &lw))) return r;
     if (C < 8 || C % 8) return fail(UNET_EINVAL, "C must be a multiple of 8");
+    if ((r = check_threads(N, 2 * H, 2 * W, C))) return r;
     if ((r = check_tensor("dy", dy, lddy, offdy, C, false)) || (r = check_tensor("gate", gate, ldgt, offgt, C, true)) ||
         (r = check_tensor("dx", dx, lddx, offdx, C, false)))
         return r;

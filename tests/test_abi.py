@@ -75,6 +75,15 @@ def test_network_calls_validate_before_launching(lbm):
     # head gradient: C / 8 must divide the 256-thread workgroup
     assert lib.unet_head_bwd(buf, 24, buf, buf, buf, buf, buf, buf, 1 << 30, 1, 8, 8, 24, 2, None) == -1
     assert "C / 8" in lib.unet_last_error().decode()
+    # 2x2 calls: one thread per 8 channels of a full-size pixel must fit an int index
+    # (N H W = 2^30 passes the geometry check; with C = 16 there are 2^31 threads)
+    assert lib.unet_maxpool2_fwd(buf, 16, 0, buf, 16, 0, 1, 1 << 15, 1 << 15, 16, None) == -1
+    assert "2^31" in lib.unet_last_error().decode()
+    assert lib.unet_maxpool2_bwd(buf, 16, 0, buf, 16, 0, None, 0, 0, buf, 16, 0, 1, 1, 1 << 15, 1 << 15, 16,
+                                 None) == -1
+    assert lib.unet_upsample2_fwd(buf, 16, 0, buf, 16, 0, 1, 1 << 14, 1 << 14, 16, None) == -1
+    assert lib.unet_upsample2_bwd(buf, 16, 0, None, 0, 0, buf, 16, 0, 1, 1 << 14, 1 << 14, 16, None) == -1
+    assert "2^31" in lib.unet_last_error().decode()
 
 
 @pytest.mark.parametrize("eos_kind", ["cs", "vdw"])

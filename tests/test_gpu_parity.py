@@ -250,6 +250,34 @@ def test_call_order_and_workspace_errors():
     assert b"workspace" in lib.lbm_last_error(None)
 
 
+@pytest.mark.parametrize("scheme", ["ab", "aa"])
+def test_zero_steps_is_a_no_op_and_negative_count_is_rejected(cs_model, scheme):
+    """lbm_step with n = 0 launches nothing: the moments are bitwise the same before and
+    after it, and match the oracle's at t = 0. n < 0 is LBM_EINVAL and leaves the state
+    and the step count untouched; stepping afterwards still follows the oracle."""
+    from paper_2106_01557_amd import lbm
+    d = cs_model.d
+    say(f"case: {scheme} FP64 40x24, step(0) and step(-1)")
+    f = inputs.random_smooth(40, 24, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.5, 0.03 * d.cs, 0.03, seed=5)
+    s = gpu_solver(40, 24, params={"precision": "f64", "scheme": scheme})
+    s.set_fields(*f.as_tuple())
+    m0 = s.moments_numpy()
+    s.step(0)
+    m1 = s.moments_numpy()
+    with pytest.raises(lbm.LbmError) as ei:
+        s.step(-1)
+    assert ei.value.code == lbm.LBM_EINVAL
+    assert s.steps == 0
+    m2 = s.moments_numpy()
+    for k in m0:
+        assert np.array_equal(m0[k], m1[k]) and np.array_equal(m0[k], m2[k]), k
+    o, _ = oracle_moments(cs_model, f, 0)
+    assert_close(m0, o, d, TOL64, "t = 0")
+    s.step(3)
+    o3, _ = oracle_moments(cs_model, f, 3)
+    assert_close(s.moments_numpy(), o3, d, TOL64, "3 steps after step(0)")
+
+
 # ---- full size, in the launch configuration the benchmark times ---------------------------
 
 def _sampled_full_size(prec, tol, steps=8, n=4096):

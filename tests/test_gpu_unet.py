@@ -164,14 +164,19 @@ def test_conv3x3_weight_gradient(case):
     assert (np.abs(host(db) - db_ref) <= gamma(P) * bb + 1e-30).all()
 
 
-def test_pool_upsample_and_their_gradients():
+@pytest.mark.parametrize("C", [8, 16, 24, 64])
+def test_pool_upsample_and_their_gradients(C):
+    """Channel counts from one 16-byte group per pixel to eight, including an odd group
+    count; ties inside a window in each row and across its rows."""
     import torch
-    say("case: maxpool / upsample forward and backward")
+    say(f"case: maxpool / upsample forward and backward, C = {C}")
     u = lib()
     L = u.library()
-    N, H, W, C = 2, 8, 16, 16
+    N, H, W = 2, 8, 16
     x = bf((N, H, W, C), 12)
     x[0, 0, 0, :] = x[0, 0, 1, :] = 5.0  # an exact tie: the first maximum takes the gradient
+    x[1, 2, 3, :] = x[1, 3, 2, :] = 6.0  # top right against bottom left: top right wins
+    x[1, 5, 4, :] = x[1, 5, 5, :] = 7.0  # bottom left against bottom right: bottom left wins
     dy = bf((N, H // 2, W // 2, C), 13)
     add = bf((N, H, W, C), 14)
     xd = dev_bf16(x)
@@ -184,7 +189,8 @@ def test_pool_upsample_and_their_gradients():
     ref = (U.maxpool2_grad(x, dy) + add) * (x > 0)
     want = U.bf16_round(ref)
     assert (np.abs(host(dx) - want) <= np.abs(want) * 2.0 ** -7 + 1e-30).all()
-    assert host(dx)[0, 0, 1, 0] == U.bf16_round(np.array([add[0, 0, 1, 0]]))[0]  # tie loser gets only `add`
+    for (n, yy, xx) in ((0, 0, 1), (1, 3, 2), (1, 5, 5)):  # tie losers get only `add`
+        assert (host(dx)[n, yy, xx] == U.bf16_round(add[n, yy, xx])).all()
     # upsample forward into channels 16..31 of a 32-channel buffer, and back
     s = bf((N, H // 2, W // 2, C), 15)
     big = torch.zeros((N, H, W, 2 * C), dtype=torch.bfloat16, device="cuda")
