@@ -954,36 +954,48 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
 }
 
 // dw[o][k] = sum_s part[s][o][k] (k < K), db[o] = sum_s part[s][o][K].  A workgroup
-// takes 64 consecutive outputs (one per lane) and its four wavefronts take slabs
-// w, w + 4, w + 8, ... each with four running sums (slab index mod 16), which are
-// combined in a fixed order, then the four wavefronts' sums in a fixed order:
-// deterministic for a given slab count.
-__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw,
-                                                      float* __restrict__ db, int slabs, int Cout, int K, int Kt) {
-    __shared__ float sm[4][64];
+// takes 64 consecutive outputs (one per lane) and its WV wavefronts take slabs
+// w, w + WV, w + 2 WV, ... each with NA running sums (slab index mod NA WV), which are
+// combined in a fixed order, then the wavefronts' sums in a fixed order: deterministic
+// for a given slab count.  Long slab ranges take 16 wavefronts with eight loads in
+// flight each (the 256^2 layers' 512 slabs: half the time of 4 x 4), short ones 4 x 4.
+template <int WV, int NA>
+__global__ void __launch_bounds__(64 * WV) k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw,
+                                                          float* __restrict__ db, int slabs, int Cout, int K,
+                                                          int Kt) {
+    static_assert((WV & (WV - 1)) == 0 && WV >= 2 && (NA == 4 || NA == 8), "power-of-two waves, 4 or 8 sums");
+    __shared__ float sm[WV][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int idx = blockIdx.x * 64 + lane;
     const bool on = idx < Cout * (K + 1);
     const int o = on ? idx / (K + 1) : 0, k = on ? idx - o * (K + 1) : 0;
     const size_t stride = (size_t)Cout * Kt;
     const float* q = part + (size_t)o * Kt + k;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    float a[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) a[j] = 0.f;
     if (on) {
         int z = wave;
-        for (; z + 12 < slabs; z += 16) {
-            a0 += q[(size_t)z * stride];
-            a1 += q[(size_t)(z + 4) * stride];
-            a2 += q[(size_t)(z + 8) * stride];
-            a3 += q[(size_t)(z + 12) * stride];
+        for (; z + (NA - 1) * WV < slabs; z += NA * WV) {
+#pragma unroll
+            for (int j = 0; j < NA; ++j) a[j] += q[(size_t)(z + j * WV) * stride];
         }
-        for (; z < slabs; z += 4) a0 += q[(size_t)z * stride];
+        for (; z < slabs; z += WV) a[0] += q[(size_t)z * stride];
     }
-    sm[wave][lane] = (a0 + a1) + (a2 + a3);
+    float t = (a[0] + a[1]) + (a[2] + a[3]);
+    if constexpr (NA == 8) t = t + ((a[4] + a[5]) + (a[6] + a[7]));
+    sm[wave][lane] = t;
     __syncthreads();
     if (wave != 0 || !on) return;
-    const float s = (sm[0][lane] + sm[1][lane]) + (sm[2][lane] + sm[3][lane]);
-    if (k < K) dw[(size_t)o * K + k] = s;
-    else if (db) db[o] = s;
+    float r[WV / 2];
+#pragma unroll
+    for (int w = 0; w < WV / 2; ++w) r[w] = sm[2 * w][lane] + sm[2 * w + 1][lane];
+#pragma unroll
+    for (int h = WV / 4; h >= 1; h >>= 1)
+#pragma unroll
+        for (int w = 0; w < h; ++w) r[w] = r[2 * w] + r[2 * w + 1];
+    if (k < K) dw[(size_t)o * K + k] = r[0];
+    else if (db) db[o] = r[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1561,8 +1573,12 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
     }
     if ((r = launched("wgrad launch"))) return r;
     const int n = C_out * (a.K + 1);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 63) / 64), dim3(256), 0, s, a.part, dw, db, p.slabs, C_out, a.K,
-                       p.Kt);
+    if (p.slabs >= 256)
+        hipLaunchKernelGGL((k_wgrad_reduce<16, 8>), dim3((n + 63) / 64), dim3(1024), 0, s, a.part, dw, db, p.slabs,
+                           C_out, a.K, p.Kt);
+    else
+        hipLaunchKernelGGL((k_wgrad_reduce<4, 4>), dim3((n + 63) / 64), dim3(256), 0, s, a.part, dw, db, p.slabs,
+                           C_out, a.K, p.Kt);
     return launched("wgrad reduce launch");
 }
 

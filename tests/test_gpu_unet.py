@@ -494,7 +494,8 @@ def test_conv3x3_large_bf16_epilogue(case):
 
 
 @pytest.mark.parametrize("case", [(1, 64, 64, 96, 32), (1, 64, 64, 64, 64), (2, 32, 32, 128, 128), (1, 16, 256, 32, 32),
-                                  (1, 32, 32, 192, 64)],
+                                  (1, 32, 32, 192, 64),
+                                  (5, 64, 256, 32, 32)],  # 320 slabs: the wide reduction, full passes and a tail
                          ids=lambda c: "x".join(map(str, c)))
 def test_conv3x3_large_input_and_weight_gradients(case):
     """Input gradient (flipped weights) and weight gradient at thousands of pixels: the
