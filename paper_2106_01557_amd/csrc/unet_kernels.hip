@@ -379,8 +379,9 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
 // (ty + dy + 1) * 18 + (tx + dx + 1).  Pixels are reused across taps from LDS instead
 // of being re-read from L2 per tap (324 pixels loaded per 256 computed).  One LDS
 // buffer (39 KB); the next channel block's global loads are held in registers while
-// the current block's MFMAs run, then stored to LDS after a barrier (two resident
-// workgroups per CU: the registers, not the LDS, set the occupancy).  LDS rows hold
+// the current block's MFMAs run, then stored to LDS after a barrier (the registers,
+// not the LDS, set the occupancy: one workgroup per CU; forcing two, or keeping the
+// tap loop rolled for three or four, was no faster).  LDS rows hold
 // 4 x 16-byte pieces swizzled as in k_conv_lds (the 16 lanes of a fragment read 16
 // consecutive halo pixels); the bf16 epilogue is the same.  Accumulation order: per
 // output, channel block outer, taps inner.
