@@ -371,6 +371,72 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     }
 }
 
+// Epilogue of a 16 x 16 pixel tile x 32 output channels (the same steps as k_conv_halo's
+// own): bias, ReLU, mask, then FP32 stores, or bfloat16 through the staging tile Os
+// (256 rows of 40) as 16-byte stores.
+template <bool kF32, int MT, int NT>
+__device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&acc)[MT][NT], bf16_t* Os, int co0,
+                                              int img, int ty0, int tx0, int wm, int lane, int t) {
+    constexpr int BM = 256, BN = 32, OP = BN + 8;
+    const int r16 = lane & 15;
+    // image pixel of tile pixel q (row q >> 4, column q & 15)
+    auto pixel = [&](int q) { return (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15)); };
+    const int g4 = 4 * (lane >> 4);
+    if constexpr (kF32) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int co = co0 + 16 * n + r16;
+            const float b = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const size_t p = pixel(wm + 16 * m + g4 + r);
+                    float v = acc[m][n][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    if (a.mask && !(bf2f(a.mask[p * a.ldm + co]) > 0.f)) v = 0.f;
+                    static_cast<float*>(a.y)[p * a.ldy + co] = v;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int c = 16 * n + r16;
+            const float b = a.bias ? a.bias[co0 + c] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[m][n][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    Os[(wm + 16 * m + g4 + r) * OP + c] = (bf16_t)f2bf_hw(v);
+                }
+            }
+        }
+        __syncthreads();
+        constexpr int VR = BN / 8;
+        for (int v = t; v < BM * VR; v += 256) {
+            const int row = v / VR, cv = v - row * VR;
+            const size_t p = pixel(row);
+            const int co = co0 + 8 * cv;
+            uint4 o = *reinterpret_cast<const uint4*>(&Os[row * OP + 8 * cv]);
+            if (a.mask) {
+                const uint4 mk = ld16(a.mask + p * a.ldm + co);
+                const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+                uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t keep = (lo(mw[j]) > 0.f ? 0xffffu : 0u) | (hi(mw[j]) > 0.f ? 0xffff0000u : 0u);
+                    ow[j] &= keep;
+                }
+                o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+            }
+            st16(static_cast<bf16_t*>(a.y) + p * a.ldy + co, o);
+        }
+    }
+}
+
 // Halo-tile form for C_in % 32 == 0 (H, W multiples of 16): a workgroup owns a 16 x 16
 // pixel tile and BN = 32 output channels.  Per block of 32 input channels it loads
 // the 18 x 18 pixels of the tile and its one-pixel periodic halo and the weights of
@@ -537,6 +603,81 @@ __global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
             st16(static_cast<bf16_t*>(a.y) + p * a.ldy + co, o);
         }
     }
+}
+
+// Halo-tile form for C_in = 8 (the network's first layer; H, W multiples of 16).  As in
+// k_conv_halo a workgroup owns a 16 x 16 pixel tile and 32 output channels, with the
+// 18 x 18 halo pixels (one 16-byte piece each) and the weights in LDS, all loads issued
+// together.  The 72-long reduction (9 taps x 8 channels) runs as three 32-wide MFMA
+// chunks of four taps: the lane group k4 that supplies K elements 8 k4 .. 8 k4 + 7 of
+// chunk j takes tap 4 j + k4, whose A fragment is one halo pixel.  Taps 9..11 of the
+// last chunk are zero in A and in the weights: k_conv3x3's K order for C_in = 8, chunk
+// by chunk, with the input read from L2 once per tile instead of once per tap.
+template <bool kF32>
+__global__ void __launch_bounds__(256) k_conv_halo8(const ConvArgs a) {
+    constexpr int BM = 256, BN = 32, WTM = 64, MT = 4, NT = 2, OP = BN + 8;
+    constexpr int KP = 12 * 8 + 8;  // weight row pitch: 12 taps of 8 channels, 8 elements of padding
+    __shared__ __attribute__((aligned(16))) bf16_t Ah[kHalo * 8];
+    __shared__ __attribute__((aligned(16))) bf16_t Bh[BN * KP];
+    __shared__ __attribute__((aligned(16))) bf16_t Os[kF32 ? 8 : BM * OP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int ctiles = a.Cout / BN, L = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = L / ctiles, co0 = (L % ctiles) * BN;
+    const int W = 1 << a.lw, Hm = (1 << a.lh) - 1, Wm = W - 1;
+    const int txs = a.lw - 4, tys = a.lh - 4;  // log2 of the tiles per row and per column
+    const int tx0 = (tile & ((1 << txs) - 1)) << 4;
+    const int ty0 = ((tile >> txs) & ((1 << tys) - 1)) << 4;
+    const int img = (tile >> (txs + tys)) << (a.lw + a.lh);
+    uint4 hv[2], wv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int v = t + 256 * i;
+        if (v < kHalo) {
+            const int hr = v / 18, hc = v - 18 * hr;
+            const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
+            hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx);
+        }
+        if (v < BN * 12) {  // output channel v / 12, tap v % 12
+            const int n = v / 12, tap = v - 12 * n;
+            wv[i] = tap < 9 ? ld16(a.w + (size_t)(co0 + n) * 72 + 8 * tap) : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int v = t + 256 * i;
+        if (v < kHalo) *reinterpret_cast<uint4*>(&Ah[v * 8]) = hv[i];
+        if (v < BN * 12) {
+            const int n = v / 12, tap = v - 12 * n;
+            *reinterpret_cast<uint4*>(&Bh[n * KP + 8 * tap]) = wv[i];
+        }
+    }
+    __syncthreads();
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int wm = wave * WTM, r16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int tap = 4 * j + k4;
+        const bool tv = tap < 9;
+        const int dy = tv ? tap / 3 : 0, dx = tv ? tap - 3 * (tap / 3) : 0;  // offsets into the halo (0..2)
+        uint4 A[MT], B[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int h = ((wm >> 4) + m + dy) * 18 + r16 + dx;
+            A[m] = sel(tv, *reinterpret_cast<const uint4*>(&Ah[h * 8]));
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) B[n] = *reinterpret_cast<const uint4*>(&Bh[(16 * n + r16) * KP + 32 * j + 8 * k4]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]), acc[m][n], 0, 0, 0);
+    }
+    halo_epilogue<kF32, MT, NT>(a, acc, Os, co0, img, ty0, tx0, wm, lane, t);
 }
 
 // several layers in one launch: workgroup b works on the layer whose element range
@@ -1382,8 +1523,14 @@ void launch_lds(const ConvArgs& a, bool f32, hipStream_t s) {
 // The LDS-staged kernel where its shape conditions hold; false: use k_conv3x3.
 // bf16 output is written in 16-byte vectors: it needs an aligned output and stride.
 bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
-    if (a.Cin % 32) return false;
     if (!f32 && (!aligned16(a.y) || a.ldy % 8)) return false;
+    if (a.Cin == 8 && a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
+        const dim3 grid((a.P / 256) * (a.Cout / 32));
+        if (f32) hipLaunchKernelGGL((k_conv_halo8<true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv_halo8<false>), grid, dim3(256), 0, s, a);
+        return true;
+    }
+    if (a.Cin % 32) return false;
     // 16 x 16 pixel tiles: H and W multiples of 16
     if (a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
         const dim3 grid((a.P / 256) * (a.Cout / 32));

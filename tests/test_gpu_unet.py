@@ -73,6 +73,7 @@ CONV_CASES = [  # N, H, W, Cin, Cout
     (1, 16, 16, 64, 64),   # LDS-staged form, 256 x 64 tiles
     (1, 16, 16, 32, 96),   # LDS-staged form, three 32-wide column tiles
     (1, 16, 16, 128, 256), # LDS-staged form, four channel blocks per tap, two column tiles
+    (1, 16, 32, 8, 64),    # C_in = 8 halo-tile form (first layer), two column tiles
 ]
 
 
@@ -464,6 +465,7 @@ LARGE_CONV = [  # N, H, W, Cin, Cout: thousands of pixels, every LDS tile shape,
     (1, 16, 256, 32, 32),    # halo-tile form at the network's widest rows (one row per tile)
     (2, 32, 128, 32, 64),    # halo-tile form, two rows per tile, two column tiles
     (2, 2, 64, 32, 32),      # 128-pixel images: a 256-pixel tile would cross images, LDS-staged form instead
+    (2, 32, 64, 8, 32),      # C_in = 8 halo-tile form (the network's first layer)
 ]
 
 
