@@ -1095,6 +1095,141 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
     }
 }
 
+// Halo-tile weight gradient for C_in = 8 (the network's first layer), the same scheme
+// as k_wgrad_halo with one 16-byte piece per halo pixel.  The 72 columns (9 taps x 8
+// channels) form five 16-column blocks of two taps: in the transposing read, lanes
+// 4j + q with q < 2 address the first tap's halo row and q >= 2 the second's, so lane
+// l receives column l = (tap 2 cb + l / 8, channel l % 8), k = 16 cb + l.  Tap 9 of the
+// last block reads tap 8's rows (inside the halo) and its columns are not stored.
+constexpr int kWg8Pitch = 16;  // halo row pitch: 8 channels + 8 elements of padding
+
+__device__ __forceinline__ bf16x8 halo_frag8(const bf16_t* Hs, int ks, int cb, int lane) {
+    const int g = lane >> 4, i = lane & 15;
+    const int px0 = ks * 32 + 8 * g;  // 8 consecutive tile pixels within one tile row
+    const int tap = min(2 * cb + ((i & 3) >> 1), 8);
+    const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+    const int hb = ((px0 >> 4) + dy) * 18 + (px0 & 15) + dx;
+    const bf16_t* q = Hs + (hb + (i >> 2)) * kWg8Pitch + 4 * (i & 1);
+    typedef __attribute__((address_space(3))) v4s lds_v4s;
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q));
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q + 4 * kWg8Pitch));
+    uint4 u;
+    u.x = (uint32_t)(uint16_t)lo[0] | ((uint32_t)(uint16_t)lo[1] << 16);
+    u.y = (uint32_t)(uint16_t)lo[2] | ((uint32_t)(uint16_t)lo[3] << 16);
+    u.z = (uint32_t)(uint16_t)hi[0] | ((uint32_t)(uint16_t)hi[1] << 16);
+    u.w = (uint32_t)(uint16_t)hi[2] | ((uint32_t)(uint16_t)hi[3] << 16);
+    return as_frag(u);
+}
+
+template <int OC>
+__global__ void __launch_bounds__(256) k_wgrad_halo8(const WgArgs a) {
+    constexpr int NCB = 2;          // column blocks per wavefront (5 over 4: 2, 1, 1, 1)
+    constexpr int GP = OC + 16;     // row pitch of the g tile
+    constexpr int PPR = OC / 8;     // 16-byte pieces per pixel of g
+    constexpr int RP = 256 / PPR;   // g pixels loaded per pass of the workgroup
+    constexpr int MH = OC / 16;     // 16-row output blocks
+    __shared__ __attribute__((aligned(16))) bf16_t Gs[256 * GP];
+    __shared__ __attribute__((aligned(16))) bf16_t Hs[kHalo * kWg8Pitch];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // flat grid: output-channel blocks, then slabs (one input-channel block)
+    const int L = xcd_block(blockIdx.x, gridDim.x);
+    const int ob = L % a.ctiles, z = L / a.ctiles;
+    const int o0 = ob * OC;
+    const int tb = z * a.slab, te = min(a.P >> 8, tb + a.slab);
+    const int Hm = (1 << a.lh) - 1, Wm = (1 << a.lw) - 1;
+    const int txs = a.lw - 4, tys = a.lh - 4;
+    const int gpiece = t % PPR;
+    f32x4 acc[MH][NCB];
+#pragma unroll
+    for (int h = 0; h < MH; ++h)
+#pragma unroll
+        for (int i = 0; i < NCB; ++i) acc[h][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    constexpr int HV = (kHalo + 255) / 256;
+    uint4 gv[PPR], hv[HV];
+    auto gload = [&](int tile) {
+        const int tx0 = (tile & ((1 << txs) - 1)) << 4;
+        const int ty0 = ((tile >> txs) & ((1 << tys) - 1)) << 4;
+        const int img = (tile >> (txs + tys)) << (a.lw + a.lh);
+#pragma unroll
+        for (int i = 0; i < PPR; ++i) {
+            const int q = t / PPR + RP * i;  // tile pixel (row q >> 4, column q & 15)
+            const size_t p = (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15));
+            gv[i] = ld16(a.g + p * a.ldg + o0 + 8 * gpiece);
+        }
+#pragma unroll
+        for (int i = 0; i < HV; ++i) {
+            const int h = t + 256 * i;
+            if (h < kHalo) {
+                const int hr = h / 18, hc = h - 18 * hr;
+                const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
+                hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx);
+            }
+        }
+    };
+    if (tb < te) gload(tb);
+    for (int tile = tb; tile < te; ++tile) {
+        if (tile != tb) __syncthreads();  // the previous tile's fragments have been read
+#pragma unroll
+        for (int i = 0; i < PPR; ++i) {
+            const int q = t / PPR + RP * i;
+            *reinterpret_cast<uint4*>(&Gs[q * GP + 8 * gpiece]) = gv[i];
+            float f[8];
+            unpack8(gv[i], f);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+        }
+#pragma unroll
+        for (int i = 0; i < HV; ++i) {
+            const int h = t + 256 * i;
+            if (h < kHalo) *reinterpret_cast<uint4*>(&Hs[h * kWg8Pitch]) = hv[i];
+        }
+        __syncthreads();
+        if (tile + 1 < te) gload(tile + 1);
+#pragma unroll 2
+        for (int ks = 0; ks < 8; ++ks) {
+            bf16x8 A[MH];
+#pragma unroll
+            for (int h = 0; h < MH; ++h)
+                A[h] = tr_frag<GP>(reinterpret_cast<const bf16_t(*)[GP]>(Gs), ks * 32, 16 * h, lane);
+#pragma unroll
+            for (int i = 0; i < NCB; ++i) {
+                const int cb = wave + 4 * i;
+                if (cb < 5) {
+                    const bf16x8 B = halo_frag8(Hs, ks, cb, lane);
+#pragma unroll
+                    for (int h = 0; h < MH; ++h)
+                        acc[h][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], B, acc[h][i], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* part = a.part + (size_t)z * a.Cout * a.Kt;
+    const int i16 = lane & 15, g4 = 4 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < NCB; ++i) {
+        const int cb = wave + 4 * i;
+        const int k = 16 * cb + i16;
+        if (cb >= 5 || k >= 72) continue;
+#pragma unroll
+        for (int h = 0; h < MH; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[(size_t)(o0 + 16 * h + g4 + r) * a.Kt + k] = acc[h][i][r];
+    }
+    // bias: the RP threads holding each 8-channel piece, combined in thread order
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(Gs);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[t * 8 + j] = bsum[j];
+    __syncthreads();
+    if (t < OC) {
+        const int piece = t >> 3, j = t & 7;
+        float s = 0.f;
+        for (int u = 0; u < RP; ++u) s += red[(PPR * u + piece) * 8 + j];
+        part[(size_t)(o0 + t) * a.Kt + a.K] = s;
+    }
+}
+
 // dw[o][k] = sum_s part[s][o][k] (k < K), db[o] = sum_s part[s][o][K].  A workgroup
 // takes 64 consecutive outputs (one per lane) and its WV wavefronts take slabs
 // w, w + WV, w + 2 WV, ... each with NA running sums (slab index mod NA WV), which are
@@ -1553,7 +1688,8 @@ bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
 struct WgPlan {
     int ktiles, ctiles, CT, slabs, slab, Kt;
     bool tr;    // k_wgrad_tr (C_out % 32 == 0), else k_wgrad
-    bool halo;  // k_wgrad_halo: ktiles = input-channel blocks, slab in 256-pixel tiles
+    bool halo;  // k_wgrad_halo (or k_wgrad_halo8): ktiles = input-channel blocks, slab in 256-pixel tiles
+    bool halo8; // C_in = 8: k_wgrad_halo8, one input-channel block
 };
 
 WgPlan wgrad_plan(int P, int lh, int lw, int Cin, int Cout) {
@@ -1561,11 +1697,12 @@ WgPlan wgrad_plan(int P, int lh, int lw, int Cin, int Cout) {
     const int K = 9 * Cin;
     // the halo-tile form wherever its tiles fit: with the next tile prefetched it beats
     // the im2col form on every such layer of the network (measured, 256^2 x 16)
-    w.halo = Cin % 32 == 0 && (Cout == 32 || Cout % 64 == 0) && lh >= 4 && lw >= 4;
+    w.halo8 = Cin == 8 && (Cout == 32 || Cout % 64 == 0) && lh >= 4 && lw >= 4;
+    w.halo = w.halo8 || (Cin % 32 == 0 && (Cout == 32 || Cout % 64 == 0) && lh >= 4 && lw >= 4);
     if (w.halo) {
         w.tr = false;
         w.CT = Cout % 64 == 0 ? 64 : 32;
-        w.ktiles = Cin / 32;
+        w.ktiles = w.halo8 ? 1 : Cin / 32;
         w.ctiles = Cout / w.CT;
         w.Kt = (K + 1 + 31) / 32 * 32;
         const int tiles = P >> 8;
@@ -1707,7 +1844,11 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
     a.ctiles = p.ctiles;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const dim3 grid(p.ktiles, p.ctiles, p.slabs);
-    if (p.halo) {
+    if (p.halo8) {
+        const dim3 flat(p.ctiles * p.slabs);
+        if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_halo8<64>), flat, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_wgrad_halo8<32>), flat, dim3(256), 0, s, a);
+    } else if (p.halo) {
         const dim3 flat(p.ktiles * p.ctiles * p.slabs);
         if (p.CT == 64) hipLaunchKernelGGL((k_wgrad_halo<64>), flat, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_wgrad_halo<32>), flat, dim3(256), 0, s, a);

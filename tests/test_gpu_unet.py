@@ -139,7 +139,9 @@ def test_conv3x3_input_gradient_by_flipped_weights(case):
     assert (err <= bound + 1e-30).all(), float((err / (bound + 1e-30)).max())
 
 
-@pytest.mark.parametrize("case", [(3, 4, 8, 8, 16), (2, 64, 64, 32, 32), (1, 16, 32, 96, 64), (2, 8, 8, 40, 128)],
+@pytest.mark.parametrize("case", [(3, 4, 8, 8, 16), (2, 64, 64, 32, 32), (1, 16, 32, 96, 64), (2, 8, 8, 40, 128),
+                                  (2, 64, 64, 8, 32),    # C_in = 8 halo-tile form, 32 output channels, 32 slabs
+                                  (1, 16, 32, 8, 64)],   # C_in = 8 halo-tile form, 64 output channels
                          ids=lambda c: "x".join(map(str, c)))
 def test_conv3x3_weight_gradient(case):
     """Weight and bias gradients; the 64 x 64 case splits the pixel sum over many slabs."""
