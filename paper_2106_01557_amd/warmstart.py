@@ -250,6 +250,20 @@ def coexistence_times(runner: Runner, start_rho, steps: int, every: int, final=N
     return times, last, t_step
 
 
+def guard_prediction(rho, T, rho_v, rho_l, T0, t_band: float = 0.15):
+    """Keeps a predicted state inside the range a solver run can start from.  The network
+    predicts the normalised density (rho - rho_v) / (rho_l - rho_v), so an error of a few
+    hundredths in the vapour gives a negative density at low temperature, and the solver
+    diverges from it.  Densities are held in [rho_v / 2, rho_l + (rho_l - rho_v) / 20]
+    and temperatures within t_band of T0, per problem ([N, H, W] tensors, [N] bounds)."""
+    lo = (0.5 * rho_v)[:, None, None]
+    hi = (rho_l + 0.05 * (rho_l - rho_v))[:, None, None]
+    t0 = T0[:, None, None]
+    rho = rho.clamp_min(0).maximum(lo).minimum(hi)
+    T = T.maximum((1 - t_band) * t0).minimum((1 + t_band) * t0)
+    return rho, T
+
+
 def compare_warm_start(net, specs, horizon: int, steps: int, every: int, log=None):
     """Plain runs against warm-started runs on the same problems.  Returns a summary
     dict with the per-problem times to coexistence."""
@@ -264,6 +278,8 @@ def compare_warm_start(net, specs, horizon: int, steps: int, every: int, log=Non
     prho, pT = net.predict_fields(rho0, r.uniform_T(), r.rho_v, r.rho_l, r.T0, r.cond)
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
+    with torch.cuda.stream(r.stream):  # the runner's stream, which starts the runs
+        prho, pT = guard_prediction(prho, pT, r.rho_v, r.rho_l, r.T0)
     warm, wlast, t_warm = coexistence_times(r, prho.contiguous(), steps, every, start_T=pT.contiguous())
     r.close()
     ok = [i for i in range(len(specs)) if plain[i] is not None and warm[i] is not None
