@@ -42,6 +42,8 @@ extern "C" {
                                 fraction >= 1                                            */
 #define LBM_ESTATE     (-5)  /* call out of order (e.g. lbm_step before lbm_set_fields,
                                 or a device call on a host-only context)                 */
+#define LBM_EIO        (-6)  /* checkpoint file cannot be opened, read or written, or its
+                                header or checksum does not match                         */
 
 /* ---- equation of state kinds (p_EOS of the text after Eq. (11)) --------- */
 #define LBM_EOS_CS  0  /* Eq. (17): K[rho R T (1+t+t^2-t^3)/(1-t)^3 - a rho^2], t = b rho/4 */
@@ -62,12 +64,27 @@ extern "C" {
 #define LBM_SCHEME_AB 0  /* fused single pass, two state buffers (pull streaming)      */
 #define LBM_SCHEME_AA 1  /* in-place AA pattern, one state buffer, plus a density pass */
 
+/* ---- boundaries in x (y is always periodic) -------------------------------- */
+#define LBM_BC_PERIODIC       0  /* periodic in x (the default)                          */
+#define LBM_BC_HEATED_OUTFLOW 1  /* the one-dimensional Stefan problem (Eqs. (20)-(21)):
+                                    x = 0 is a heated wall (T_r1 = lbm_params.Tr_wall) with
+                                    vapour outflow at constant pressure (lbm_params.p_out),
+                                    x = nx-1 a wall at rest (lbm_params.Tr_far); both by
+                                    non-equilibrium extrapolation from the neighbouring
+                                    fluid column (Guo, Zheng & Shi 2002, standing in for
+                                    the improved scheme the paper cites).  Columns 0 and
+                                    nx-1 are boundary nodes.  Needs the two-buffer scheme,
+                                    LBM_F64 or LBM_F32, nx >= 4 and nx*ny <= 8192 (one
+                                    workgroup steps the lattice); not a batch member.    */
+
 typedef struct lbm_ctx lbm_ctx;   /* opaque; owned by the library */
 
-/* Lattice: D2Q9 velocities of SM Eq. (1), periodic in both directions. */
+/* Lattice: D2Q9 velocities of SM Eq. (1), periodic in y, and in x unless bc_x says
+ * otherwise (a zero-initialised bc_x is periodic). */
 typedef struct {
     int32_t nx, ny;   /* nodes, each >= 1 and nx*ny < 2^31                           */
     double  dx;       /* lattice spacing delta_x (> 0; the paper uses 1)              */
+    int32_t bc_x;     /* LBM_BC_PERIODIC or LBM_BC_HEATED_OUTFLOW                     */
 } lbm_lattice;
 
 /* Equation of state, Eq. (17).  For LBM_EOS_CS, a_t and b_t are a~ and b~ (Tc, pc
@@ -100,6 +117,13 @@ typedef struct {
     double cs_override;   /* > 0: use this lattice sound speed instead of Eq. (19)      */
     double rho_ref, T_ref;/* deviation reference for LBM_F16/LBM_BF16 storage;
                              <= 0: rho_v at T0 (vapour coexistence) and T0            */
+    double Tr_wall;       /* LBM_BC_HEATED_OUTFLOW: T/Tc of the heated wall (T_r1; the
+                             paper's 0.85); > 0                                       */
+    double Tr_far;        /* LBM_BC_HEATED_OUTFLOW: T/Tc of the far wall; <= 0: Tr0     */
+    double p_out;         /* LBM_BC_HEATED_OUTFLOW: outflow pressure; <= 0: the
+                             saturation pressure at T0 (reading: the pressure of the
+                             liquid at rest).  The boundary density is the vapour root
+                             of p_EOS(rho, T_wall) = p_out                            */
     int32_t precision;    /* LBM_F64, LBM_F32, LBM_F16, LBM_BF16                        */
     int32_t scheme;       /* LBM_SCHEME_AB or LBM_SCHEME_AA                             */
     int32_t rows_per_wave;/* rows one wavefront marches through per launch; 0 = auto
@@ -120,6 +144,13 @@ typedef struct {
                              members stay bitwise equal to uninterrupted single runs.
                              LBM_EINVAL for other precisions or the AA scheme.
                              lbm_set_fields rounds to nearest.                       */
+    int32_t check_every;  /* failure detection: > 0 makes lbm_step run the state check of
+                             lbm_invariants (NaN/Inf, rho <= 0, T <= 0, packing fraction
+                             >= 1) after every step whose count is a multiple of
+                             check_every; that check synchronises the stream.  On a
+                             failure lbm_step stops there and returns LBM_ENONFINITE, and
+                             lbm_last_error() names the step count and the number of
+                             failing nodes.  0 (default): no checks inside lbm_step.     */
 } lbm_params;
 
 /* Fills *p with the paper's numerical-test parameters (varpi = 1/6, gamma1 = -2,
@@ -158,7 +189,8 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos,
 int lbm_set_fields(lbm_ctx* ctx, const double* rho, const double* ux,
                    const double* uy, const double* T);
 
-/* Advances n >= 0 time steps.  Asynchronous; launches only (no host sync). */
+/* Advances n >= 0 time steps.  Asynchronous; launches only (no host sync), except for
+ * the state checks that lbm_params.check_every > 0 asks for (see there). */
 int lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Writes rho, u and T at the current time (Eq. (14); u includes the dt/2 F
@@ -181,10 +213,11 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* T);
  * n_out must be >= 8. */
 int lbm_invariants(lbm_ctx* ctx, double* out, int n_out);
 
-/* Per-run constants, in this order (n <= 26 values are written):
+/* Per-run constants, in this order (n <= 27 values are written):
  *  0 Tc   1 pc   2 T0   3 rho_v  4 rho_l  5 p_s   6 c_s  7 c   8 dt   9 G^2
  * 10 a   11 kappa 12 cv 13 C_ref 14 beta 15 k  16 h  17 b (SM Eq. (5a))
- * 18 s_p 19 s_q 20 s_e 21 omega_e 22 omega_p 23 tau_j_v 24 tau_j_l 25 h_lv */
+ * 18 s_p 19 s_q 20 s_e 21 omega_e 22 omega_p 23 tau_j_v 24 tau_j_l 25 h_lv
+ * 26 rho_wall (LBM_BC_HEATED_OUTFLOW: the boundary density of the heated side; else 0) */
 int lbm_derived(const lbm_ctx* ctx, double* out, int n);
 
 /* Effective launch shape of the fused two-buffer kernel (after resolving the
@@ -205,6 +238,22 @@ int lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
 int lbm_save_state(lbm_ctx* ctx, void* dst_device, int64_t* steps);
 int lbm_load_state(lbm_ctx* ctx, const void* src_device, int64_t steps);
 
+/* Checkpoint to a file and restart from one (synchronising).  The file holds a
+ * 256-byte header (magic "LBMSTATE", format version, lattice, EOS, every model
+ * parameter that enters the update, storage precision, scheme, rounding, the step count
+ * and an FNV-1a 64-bit checksum of the payload) followed by the raw state of
+ * lbm_save_state (little-endian, storage precision, state_bytes of lbm_state_bytes()).
+ * The state is staged through host memory the library allocates for the call.
+ * lbm_load() accepts only a file written for the same lattice, EOS, parameters,
+ * precision, scheme and rounding (launch-shape fields may differ) and restores the step
+ * count with the state, so that stepping on is bitwise identical to never having
+ * stopped.  LBM_EIO when the file cannot be opened, read or written, is truncated, or
+ * its magic, version or checksum is wrong; LBM_EINVAL when it was written for a
+ * different configuration (the message names the first field that differs); the
+ * context is unchanged on any failure of lbm_load(). */
+int lbm_save(lbm_ctx* ctx, const char* path);
+int lbm_load(lbm_ctx* ctx, const char* path);
+
 /* Releases the context (never the caller's workspace).  NULL is allowed. */
 int lbm_destroy(lbm_ctx* ctx);
 
@@ -214,6 +263,17 @@ int lbm_destroy(lbm_ctx* ctx);
  * out[1] rho_l, out[2] p_s, out[3] Tc.  LBM_EINVAL on bad input or when no
  * coexistence is found. */
 int lbm_maxwell(const lbm_eos* eos, double Tr, double out[4]);
+
+/* The paper's procedure for the two scaling constants (text before Eq. (20)): a
+ * prescribed surface tension sigma and 5 %-95 % interface width W of the flat interface
+ * at T = Tr Tc fix K_EOS and K_INT.  With kappa = G^2 dx^4 / 4 and G of Eq. (18), the
+ * square-gradient tension int sqrt(2 kappa dOmega) drho scales as K_INT K_EOS and the
+ * width int sqrt(kappa / (2 dOmega)) drho as K_INT, so both follow from the integrals at
+ * K_EOS = K_INT = 1 (dOmega: grand-potential excess over the Maxwell tie line of p_EOS).
+ * eos->K_eos is ignored.  Host-only: out[0] K_EOS, out[1] K_INT.  LBM_EINVAL on bad input
+ * or when there is no coexistence at Tr.  (sigma = 0.01, W = 10 at Tr = 0.8 give the
+ * paper's 0.479820 and 2.294922.) */
+int lbm_interface_constants(const lbm_eos* eos, double Tr, double sigma, double W, double dx, double out[2]);
 
 /* ---- batched form -----------------------------------------------------------
  * Many independent lattices (each its own size, EOS, temperature and constants,

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
 ARCH = "gfx950"
 
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "lbm_batch.cpp", "thermo.cpp", "unet_kernels.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_bounded.hip", "lbm_api.cpp", "lbm_batch.cpp", "thermo.cpp",
+           "unet_kernels.hip"]
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
@@ -32,27 +33,40 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the HIP library)")
 
 
+def compile_command(src: str, resources: bool = False) -> tuple:
+    """(hipcc command, object path) of one source file."""
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(HERE, "_build", src + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c"] + lang + [
+        path, "-o", obj, "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"] + NO_PACKED_FP32
+    if src in ("lbm_kernels.hip", "lbm_bounded.hip"):
+        # contract a*b+c only within one source expression: the fused-multiply-add
+        # decisions then do not depend on the surrounding code, and the one- and
+        # two-column kernel forms (and the batched kernel) give bitwise equal states
+        cmd += ["-ffp-contract=on"]
+    if src.endswith(".hip") and resources:
+        cmd += ["-Rpass-analysis=kernel-resource-usage"]
+    return cmd, obj
+
+
 def build(verbose: bool = True, resources: bool = False) -> str:
-    objdir = os.path.join(HERE, "_build")
-    os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(objdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c"] + lang + [
-            path, "-o", obj, "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"] + NO_PACKED_FP32
-        if src == "lbm_kernels.hip":
-            # contract a*b+c only within one source expression: the fused-multiply-add
-            # decisions then do not depend on the surrounding code, and the one- and
-            # two-column kernel forms (and the batched kernel) give bitwise equal states
-            cmd += ["-ffp-contract=on"]
-        if src.endswith(".hip") and resources:
-            cmd += ["-Rpass-analysis=kernel-resource-usage"]
-        if verbose:
+    """Compiles every source (in parallel, one hipcc per file) and links liblbm.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    jobs = [compile_command(src, resources) for src in SOURCES]
+    if verbose:
+        for cmd, _ in jobs:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as pool:
+        results = list(pool.map(lambda j: subprocess.run(j[0], capture_output=True, text=True), jobs))
+    for (cmd, _), res in zip(jobs, results):
+        if verbose or res.returncode:
+            sys.stdout.write(res.stdout)
+            sys.stderr.write(res.stderr)
+        if res.returncode:
+            raise subprocess.CalledProcessError(res.returncode, cmd)
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

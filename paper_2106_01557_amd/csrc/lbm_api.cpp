@@ -3,12 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lbm_ctx.hpp"
 #include "thermo.hpp"
@@ -46,6 +48,12 @@ int check_lattice(const lbm_lattice* lat) {
     if ((int64_t)lat->nx * lat->ny > 0x7fffffffLL)
         return fail(nullptr, LBM_EINVAL, "nx * ny must be < 2^31 (got %lld)", (long long)lat->nx * lat->ny);
     if (!finite_pos(lat->dx)) return fail(nullptr, LBM_EINVAL, "dx must be finite and > 0");
+    if (lat->bc_x != LBM_BC_PERIODIC && lat->bc_x != LBM_BC_HEATED_OUTFLOW)
+        return fail(nullptr, LBM_EINVAL, "unknown bc_x %d", lat->bc_x);
+    if (lat->bc_x == LBM_BC_HEATED_OUTFLOW &&
+        (lat->nx < 4 || (int64_t)lat->nx * lat->ny > lbm_dev::kMaxBoundedNodes))
+        return fail(nullptr, LBM_EINVAL, "bc_x = LBM_BC_HEATED_OUTFLOW needs nx >= 4 and nx * ny <= %d (got %d x %d)",
+                    lbm_dev::kMaxBoundedNodes, lat->nx, lat->ny);
     return LBM_OK;
 }
 
@@ -88,6 +96,9 @@ int check_params(const lbm_params* p) {
         return fail(nullptr, LBM_EINVAL, "columns_per_lane must be 0, 1 or 2 (got %d)", p->columns_per_lane);
     if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
         return fail(nullptr, LBM_EINVAL, "unknown rounding %d", p->rounding);
+    if (p->check_every < 0) return fail(nullptr, LBM_EINVAL, "check_every must be >= 0 (got %d)", p->check_every);
+    if (!std::isfinite(p->Tr_wall) || !std::isfinite(p->Tr_far) || !std::isfinite(p->p_out))
+        return fail(nullptr, LBM_EINVAL, "Tr_wall, Tr_far and p_out must be finite");
     if (p->rounding == LBM_ROUND_STOCHASTIC &&
         ((p->precision != LBM_F16 && p->precision != LBM_BF16) || p->scheme != LBM_SCHEME_AB))
         return fail(nullptr, LBM_EINVAL, "stochastic rounding needs LBM_F16 or LBM_BF16 storage and LBM_SCHEME_AB");
@@ -227,10 +238,22 @@ int derive(lbm_ctx* c) {
     const long double tau_q = 1.0L / (12.0L * tau_p);          // tau_p tau_q = 1/12
     const long double tau_e = 1.0L / (12.0L * (k + 1) * tau_q); // (k+1) tau_e tau_q = 1/12
     const long double s_p = 1 / (tau_p + 0.5L), s_q = 1 / (tau_q + 0.5L), s_e = 1 / (tau_e + 0.5L);
-    const long double vals[26] = {Tc, pc, T0, rv, rl, ps, cs, cc, dt, G2, a_mf, kappa, cv, Cref,
+    // heated-outflow walls: the boundary density is vapour at p_out and T_wall
+    long double rho_wall = 0;
+    if (c->lat.bc_x == LBM_BC_HEATED_OUTFLOW) {
+        const long double T_wall = (long double)c->p.Tr_wall * Tc;
+        const long double p_out = c->p.p_out > 0 ? (long double)c->p.p_out : ps;
+        if (!lbm_host::vapour_root(e, T_wall, p_out, &rho_wall, &why))
+            return fail(nullptr, LBM_EINVAL, "heated wall at Tr_wall = %g, p_out = %Lg: %s", c->p.Tr_wall, p_out,
+                        why.c_str());
+        const long double T_far = c->p.Tr_far > 0 ? (long double)c->p.Tr_far * Tc : T0;
+        c->w64 = lbm_dev::Walls<double>{(double)rho_wall, (double)T_wall, (double)T_far};
+        c->w32 = lbm_dev::Walls<float>{(float)rho_wall, (float)T_wall, (float)T_far};
+    }
+    const long double vals[27] = {Tc, pc, T0, rv, rl, ps, cs, cc, dt, G2, a_mf, kappa, cv, Cref,
                                   beta, k, h, bS, s_p, s_q, s_e, s_e / 2 - 1, s_p / 2 - 1,
-                                  c->p.tau_j_v, c->p.tau_j_v * c->p.lambda_ratio, h_lv};
-    for (int i = 0; i < 26; ++i) {
+                                  c->p.tau_j_v, c->p.tau_j_v * c->p.lambda_ratio, h_lv, rho_wall};
+    for (int i = 0; i < 27; ++i) {
         c->derived[i] = (double)vals[i];
         if (!std::isfinite(c->derived[i])) return fail(nullptr, LBM_EINVAL, "derived constant %d is not finite", i);
     }
@@ -257,9 +280,137 @@ int aa_parity(const lbm_ctx* c) { return c->p.scheme == LBM_SCHEME_AA ? (int)(c-
 
 const void* current_state(const lbm_ctx* c) { return c->buf[c->p.scheme == LBM_SCHEME_AA ? 0 : c->cur]; }
 
+// Density pass, the FP64 reductions of lbm_invariants and the state check, then a stream
+// synchronisation; LBM_ENONFINITE (with the step count in the message) when any node fails.
+int state_check(lbm_ctx* c, double* out) {
+    hipError_t e;
+    if (c->lat.bc_x == LBM_BC_HEATED_OUTFLOW) {
+        e = lbm_dev::launch_invariants_bounded(c->p.precision, c->consts, c->walls, current_state(c), c->result,
+                                               c->stream);
+    } else {
+        e = lbm_dev::launch_density(c->p.precision, c->consts, current_state(c), aa_parity(c), c->rho_scratch,
+                                    c->stream);
+        if (e == hipSuccess)
+            e = lbm_dev::launch_invariants(c->p.precision, c->consts, current_state(c), aa_parity(c),
+                                           c->rho_scratch, c->partials, c->result, c->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, c->result, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "state check");
+    if (out[7] > 0)
+        return fail(c, LBM_ENONFINITE, "state check failed at %.0f nodes after %lld steps", out[7],
+                    (long long)c->steps);
+    return LBM_OK;
+}
+
+
+// ---- checkpoint files -------------------------------------------------------------
+// A 512-byte header, then the raw state of lbm_save_state.  Host byte order, which is
+// little-endian on every host this library builds for.
+constexpr char kFileMagic[8] = {'L', 'B', 'M', 'S', 'T', 'A', 'T', 'E'};
+constexpr uint32_t kFileVersion = 1;
+constexpr int kModelDoubles = 25;
+const char* const kModelNames[kModelDoubles] = {
+    "Tr0", "K_int", "varpi", "gamma1", "gamma2", "tau_p", "s_eps", "sigma_e", "sigma_eps", "sigma_q", "sigma_p",
+    "tau_j_v", "lambda_ratio", "cv", "ste", "dTr_ste", "C_ref", "accel_x", "accel_y", "cs_override", "rho_ref",
+    "T_ref", "Tr_wall", "Tr_far", "p_out"};
+
+struct FileHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    int32_t nx, ny, precision, scheme, rounding, eos_kind, bc_x, pad_;
+    int64_t steps;
+    uint64_t state_bytes, checksum;
+    double dx;
+    double eos[4];               // a_t, b_t, R, K_eos
+    double model[kModelDoubles];  // the double fields of lbm_params, in declaration order
+    unsigned char reserved[512 - 8 - 8 - 32 - 8 - 16 - 8 - 32 - 8 * kModelDoubles];
+};
+static_assert(sizeof(FileHeader) == 512, "checkpoint header is 512 bytes");
+
+void model_doubles(const lbm_params& p, double* m) {
+    const double v[kModelDoubles] = {p.Tr0, p.K_int, p.varpi, p.gamma1, p.gamma2, p.tau_p, p.s_eps, p.sigma_e,
+                                     p.sigma_eps, p.sigma_q, p.sigma_p, p.tau_j_v, p.lambda_ratio, p.cv, p.ste,
+                                     p.dTr_ste, p.C_ref, p.accel_x, p.accel_y, p.cs_override, p.rho_ref, p.T_ref,
+                                     p.Tr_wall, p.Tr_far, p.p_out};
+    std::memcpy(m, v, sizeof v);
+}
+
+void fill_header(const lbm_ctx* c, FileHeader* h) {
+    std::memset(h, 0, sizeof *h);
+    std::memcpy(h->magic, kFileMagic, sizeof kFileMagic);
+    h->version = kFileVersion;
+    h->header_bytes = sizeof(FileHeader);
+    h->nx = c->lat.nx;
+    h->ny = c->lat.ny;
+    h->precision = c->p.precision;
+    h->scheme = c->p.scheme;
+    h->rounding = c->p.rounding;
+    h->eos_kind = c->eos.kind;
+    h->bc_x = c->lat.bc_x;
+    h->steps = c->steps;
+    h->state_bytes = c->state_bytes;
+    h->dx = c->lat.dx;
+    h->eos[0] = c->eos.a_t;
+    h->eos[1] = c->eos.b_t;
+    h->eos[2] = c->eos.R;
+    h->eos[3] = c->eos.K_eos;
+    model_doubles(c->p, h->model);
+}
+
+// FNV-1a, 64-bit
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// First field in which the file's configuration differs from the context's, or nullptr.
+const char* header_mismatch(const FileHeader& f, const FileHeader& want) {
+    if (f.nx != want.nx || f.ny != want.ny) return "lattice size";
+    if (f.bc_x != want.bc_x) return "boundary kind";
+    if (std::memcmp(&f.dx, &want.dx, sizeof f.dx)) return "dx";
+    if (f.precision != want.precision) return "precision";
+    if (f.scheme != want.scheme) return "scheme";
+    if (f.rounding != want.rounding) return "rounding";
+    if (f.eos_kind != want.eos_kind || std::memcmp(f.eos, want.eos, sizeof f.eos)) return "equation of state";
+    for (int i = 0; i < kModelDoubles; ++i)
+        if (std::memcmp(&f.model[i], &want.model[i], sizeof(double))) return kModelNames[i];
+    if (f.state_bytes != want.state_bytes) return "state size";
+    return nullptr;
+}
+
 }  // namespace
 
 extern "C" {
+
+int lbm_interface_constants(const lbm_eos* eos, double Tr, double sigma, double W, double dx, double out[2]) {
+    g_init_error.clear();
+    if (!eos || !out) return fail(nullptr, LBM_EINVAL, "eos and out must not be NULL");
+    lbm_eos unit = *eos;
+    unit.K_eos = 1.0;
+    int r = check_eos(&unit);
+    if (r) return r;
+    if (!(Tr > 0 && Tr < 1)) return fail(nullptr, LBM_EINVAL, "Tr must lie in (0, 1) (got %g)", Tr);
+    if (!finite_pos(sigma) || !finite_pos(W) || !finite_pos(dx))
+        return fail(nullptr, LBM_EINVAL, "sigma, W and dx must be finite and > 0");
+    lbm_host::Eos e{unit.kind, unit.a_t, unit.b_t, unit.R, 1.0L};
+    long double Tc, pc;
+    lbm_host::critical(e, &Tc, &pc);
+    // kappa at K_INT = K_EOS = 1: G^2 dx^4 / 4 with G^2 = 2 a~ / dx^2 (Eq. (18))
+    const long double kappa1 = 0.5L * e.a * (long double)dx * dx;
+    long double s1, w1;
+    std::string why;
+    if (!lbm_host::interface_sigma_width(e, (long double)Tr * Tc, kappa1, &s1, &w1, &why))
+        return fail(nullptr, LBM_EINVAL, "interface at Tr = %g: %s", Tr, why.c_str());
+    const long double Kint = (long double)W / w1;
+    out[1] = (double)Kint;
+    out[0] = (double)((long double)sigma / (Kint * s1));
+    return LBM_OK;
+}
 
 int lbm_default_params(lbm_params* p) {
     if (!p) return LBM_EINVAL;
@@ -312,6 +463,11 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     *out = nullptr;
     int r;
     if ((r = check_lattice(lat)) || (r = check_eos(eos)) || (r = check_params(p))) return r;
+    if (lat->bc_x == LBM_BC_HEATED_OUTFLOW) {
+        if (p->scheme != LBM_SCHEME_AB || (p->precision != LBM_F64 && p->precision != LBM_F32))
+            return fail(nullptr, LBM_EINVAL, "bc_x = LBM_BC_HEATED_OUTFLOW needs LBM_SCHEME_AB and LBM_F64 or LBM_F32");
+        if (!(p->Tr_wall > 0)) return fail(nullptr, LBM_EINVAL, "Tr_wall must be > 0 (got %g)", p->Tr_wall);
+    }
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_EINVAL, "out of host memory");
     c->lat = *lat;
@@ -324,6 +480,7 @@ int lbm_init(lbm_ctx** out, const lbm_lattice* lat, const lbm_eos* eos, const lb
     fill_consts(c, &c->c64);
     fill_consts(c, &c->c32);
     c->consts = p->precision == LBM_F64 ? (const void*)&c->c64 : (const void*)&c->c32;
+    c->walls = p->precision == LBM_F64 ? (const void*)&c->w64 : (const void*)&c->w32;
     // measured defaults (4096^2): short work items, so that vertically adjacent items run
     // at nearly the same time on one XCD and their shared halo rows come from its L2,
     // and each item spends a larger share of its life in the batched prologue with many
@@ -391,6 +548,29 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     int r = need_fields(c);
     if (r) return r;
     if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+    if (c->lat.bc_x == LBM_BC_HEATED_OUTFLOW) {
+        // many steps per launch (the whole small lattice is one workgroup), in chunks
+        // that end at every state check
+        const int64_t chunk = 2048;
+        while (n > 0) {
+            int64_t k = n < chunk ? n : chunk;
+            if (c->p.check_every > 0) {
+                const int64_t to_check = c->p.check_every - c->steps % c->p.check_every;
+                if (to_check < k) k = to_check;
+            }
+            hipError_t e = lbm_dev::launch_step_bounded(c->p.precision, c->consts, c->walls, c->buf[0], c->buf[1],
+                                                        c->cur, (int)k, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "bounded step launch");
+            c->cur ^= (int)(k & 1);
+            c->steps += k;
+            n -= k;
+            if (c->p.check_every > 0 && c->steps % c->p.check_every == 0) {
+                double out[8];
+                if ((r = state_check(c, out))) return r;
+            }
+        }
+        return LBM_OK;
+    }
     for (int64_t k = 0; k < n; ++k) {
         hipError_t e;
         if (c->p.scheme == LBM_SCHEME_AB) {
@@ -406,6 +586,10 @@ int lbm_step(lbm_ctx* c, int64_t n) {
         }
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         ++c->steps;
+        if (c->p.check_every > 0 && c->steps % c->p.check_every == 0) {
+            double out[8];
+            if ((r = state_check(c, out))) return r;
+        }
     }
     return LBM_OK;
 }
@@ -414,6 +598,11 @@ int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* T) {
     int r = need_fields(c);
     if (r) return r;
     if (!rho) return fail(c, LBM_EINVAL, "rho must not be NULL");
+    if (c->lat.bc_x == LBM_BC_HEATED_OUTFLOW) {
+        hipError_t e = lbm_dev::launch_moments_bounded(c->p.precision, c->consts, c->walls, current_state(c), rho,
+                                                       ux, uy, T, c->stream);
+        return e == hipSuccess ? LBM_OK : hip_fail(c, e, "bounded moments launch");
+    }
     hipError_t e = lbm_dev::launch_density(c->p.precision, c->consts, current_state(c), aa_parity(c), rho, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "density launch");
     if (ux || uy || T) {
@@ -428,23 +617,12 @@ int lbm_invariants(lbm_ctx* c, double* out, int n_out) {
     int r = need_fields(c);
     if (r) return r;
     if (!out || n_out < 8) return fail(c, LBM_EINVAL, "out must hold at least 8 doubles");
-    hipError_t e = lbm_dev::launch_density(c->p.precision, c->consts, current_state(c), aa_parity(c),
-                                           c->rho_scratch, c->stream);
-    if (e == hipSuccess)
-        e = lbm_dev::launch_invariants(c->p.precision, c->consts, current_state(c), aa_parity(c), c->rho_scratch,
-                                       c->partials, c->result, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(out, c->result, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "invariants");
-    if (out[7] > 0)
-        return fail(c, LBM_ENONFINITE, "state check failed at %.0f nodes after %lld steps", out[7],
-                    (long long)c->steps);
-    return LBM_OK;
+    return state_check(c, out);
 }
 
 int lbm_derived(const lbm_ctx* c, double* out, int n) {
     if (!c || !out || n < 0) return LBM_EINVAL;
-    for (int i = 0; i < n && i < 26; ++i) out[i] = c->derived[i];
+    for (int i = 0; i < n && i < 27; ++i) out[i] = c->derived[i];
     return LBM_OK;
 }
 
@@ -490,6 +668,84 @@ int lbm_load_state(lbm_ctx* c, const void* src, int64_t steps) {
     return LBM_OK;
 }
 
+int lbm_save(lbm_ctx* c, const char* path) {
+    int r = need_fields(c);
+    if (r) return r;
+    if (!path || !*path) return fail(c, LBM_EINVAL, "path is NULL or empty");
+    std::vector<unsigned char> host;
+    try {
+        host.resize(c->state_bytes);
+    } catch (const std::bad_alloc&) {
+        return fail(c, LBM_EIO, "cannot allocate %zu bytes of host memory to stage the state", c->state_bytes);
+    }
+    hipError_t e = hipMemcpyAsync(host.data(), current_state(c), c->state_bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy to host");
+    FileHeader h;
+    fill_header(c, &h);
+    h.checksum = fnv1a(host.data(), host.size());
+    // written next to the target and renamed over it, so an interrupted save leaves any
+    // previous checkpoint of that name intact
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(c, LBM_EIO, "cannot open %s for writing: %s", tmp.c_str(), std::strerror(errno));
+    bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 &&
+              (host.empty() || std::fwrite(host.data(), host.size(), 1, f) == 1);
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(c, LBM_EIO, "cannot write checkpoint %s", path);
+    }
+    return LBM_OK;
+}
+
+int lbm_load(lbm_ctx* c, const char* path) {
+    int r = need_device(c);
+    if (r) return r;
+    if (!path || !*path) return fail(c, LBM_EINVAL, "path is NULL or empty");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(c, LBM_EIO, "cannot open %s: %s", path, std::strerror(errno));
+    FileHeader h;
+    if (std::fread(&h, sizeof h, 1, f) != 1) {
+        std::fclose(f);
+        return fail(c, LBM_EIO, "%s: truncated header", path);
+    }
+    if (std::memcmp(h.magic, kFileMagic, sizeof kFileMagic) || h.version != kFileVersion ||
+        h.header_bytes != sizeof(FileHeader)) {
+        std::fclose(f);
+        return fail(c, LBM_EIO, "%s: not a checkpoint of this format (magic, version %u or header size %u)", path,
+                    h.version, h.header_bytes);
+    }
+    FileHeader want;
+    fill_header(c, &want);
+    if (const char* what = header_mismatch(h, want)) {
+        std::fclose(f);
+        return fail(c, LBM_EINVAL, "%s was written for a different %s", path, what);
+    }
+    if (h.steps < 0) {
+        std::fclose(f);
+        return fail(c, LBM_EIO, "%s: negative step count", path);
+    }
+    std::vector<unsigned char> host;
+    try {
+        host.resize(c->state_bytes);
+    } catch (const std::bad_alloc&) {
+        std::fclose(f);
+        return fail(c, LBM_EIO, "cannot allocate %zu bytes of host memory to stage the state", c->state_bytes);
+    }
+    const bool got = host.empty() || std::fread(host.data(), host.size(), 1, f) == 1;
+    std::fclose(f);
+    if (!got) return fail(c, LBM_EIO, "%s: truncated state", path);
+    if (fnv1a(host.data(), host.size()) != h.checksum) return fail(c, LBM_EIO, "%s: checksum mismatch", path);
+    hipError_t e = hipMemcpyAsync(c->buf[0], host.data(), c->state_bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy to device");
+    c->cur = 0;
+    c->steps = h.steps;
+    c->fields_set = true;
+    return LBM_OK;
+}
+
 int lbm_destroy(lbm_ctx* c) {
     delete c;
     return LBM_OK;
@@ -503,6 +759,7 @@ const char* lbm_strerror(int code) {
         case LBM_EHIP: return "HIP runtime error";
         case LBM_ENONFINITE: return "state check failed (non-finite or out-of-range values)";
         case LBM_ESTATE: return "call out of order";
+        case LBM_EIO: return "checkpoint file error";
         default: return "unknown error";
     }
 }

@@ -313,6 +313,8 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* members, int32_t n, void* 
         if (!c) return bfail(nullptr, LBM_EINVAL, "member %d is NULL", i);
         if (c->host_only) return bfail(nullptr, LBM_ESTATE, "member %d is a host-only context", i);
         if (c->p.scheme != LBM_SCHEME_AB) return bfail(nullptr, LBM_EINVAL, "member %d: batches need LBM_SCHEME_AB", i);
+        if (c->lat.bc_x != LBM_BC_PERIODIC)
+            return bfail(nullptr, LBM_EINVAL, "member %d: batches need periodic lattices", i);
         if (c->p.precision != m0->p.precision)
             return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one precision", i);
         if (c->stream != m0->stream) return bfail(nullptr, LBM_EINVAL, "member %d: all members must share one stream", i);

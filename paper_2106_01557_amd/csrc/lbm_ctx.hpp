@@ -14,10 +14,13 @@ struct lbm_ctx {
     lbm_lattice lat;
     lbm_eos eos;
     lbm_params p;
-    double derived[26];
+    double derived[27];
     lbm_dev::Consts<double> c64;
     lbm_dev::Consts<float> c32;
     const void* consts;       // &c64 or &c32 depending on precision
+    lbm_dev::Walls<double> w64;   // boundary state of a LBM_BC_HEATED_OUTFLOW lattice
+    lbm_dev::Walls<float> w32;
+    const void* walls;        // &w64 or &w32
     bool host_only;
     void* ws;
     size_t ws_bytes;

@@ -108,6 +108,30 @@ hipError_t launch_step_ab_batch(int prec, const void* desc, const int32_t* start
 // Resident blocks per CU of the batched kernel for the given precision and block size.
 int batch_blocks_per_cu(int prec, int waves_per_block, int queue, bool stochastic);
 size_t batch_desc_size(int prec);
+
+// ---- lattices bounded in x (lbm_bounded.hip) ----
+// Boundary state of the heated-outflow / wall pair: the heated side at x = 0 holds
+// rho_wall (vapour at p_out and T_wall) and T_wall with the velocity of column 1; the far
+// side at x = nx - 1 holds the density of column nx - 2, zero velocity and T_far.
+template <typename C>
+struct Walls {
+    C rho_wall, T_wall, T_far;
+};
+// One workgroup steps the whole lattice, with each step's densities in LDS.
+constexpr int kMaxBoundedNodes = 8192;
+constexpr int kBoundedThreads = 1024;
+// Advances `steps` steps of the two-buffer pull scheme: step k reads buf[(first + k) & 1]
+// and writes the other buffer.
+hipError_t launch_step_bounded(int prec, const void* c, const void* walls, void* buf0, void* buf1, int first,
+                               int steps, hipStream_t stream);
+// rho, u, T of the current state (rho may not be NULL; the others may); boundary columns
+// report the imposed boundary state.
+hipError_t launch_moments_bounded(int prec, const void* c, const void* walls, const void* state, double* rho,
+                                  double* ux, double* uy, double* T, hipStream_t stream);
+// The 8 FP64 diagnostics of launch_invariants over the fluid columns 1 .. nx - 2, in a
+// fixed summation order.
+hipError_t launch_invariants_bounded(int prec, const void* c, const void* walls, const void* state,
+                                     double* result, hipStream_t stream);
 size_t consts_size(int prec);
 size_t storage_bytes(int prec);
 

@@ -144,4 +144,79 @@ bool coexistence(const Eos& e, long double T, long double* rho_v, long double* r
     return true;
 }
 
+namespace {
+
+// Composite 20-point Gauss-Legendre rule on `panels` equal panels of [a, b].
+template <class F>
+long double gauss_legendre(F f, long double a, long double b, int panels) {
+    // nodes and weights of the 20-point rule on [-1, 1] (positive half; symmetric)
+    static const long double x[10] = {
+        0.0765265211334973337546404093988382L, 0.2277858511416450780804961953685746L,
+        0.3737060887154195606725481770249272L, 0.5108670019508270980043640509552510L,
+        0.6360536807265150254528366962262859L, 0.7463319064601507926143050703556416L,
+        0.8391169718222188233945290617015207L, 0.9122344282513259058677524412032981L,
+        0.9639719272779137912676661311972772L, 0.9931285991850949247861223884713203L};
+    static const long double w[10] = {
+        0.1527533871307258506980843319550976L, 0.1491729864726037467878287370019694L,
+        0.1420961093183820513292983250671649L, 0.1316886384491766268984944997481631L,
+        0.1181945319615184173123773777113823L, 0.1019301198172404350367501354803499L,
+        0.0832767415767047487247581432220463L, 0.0626720483341090635695065351870416L,
+        0.0406014298003869413310399522749321L, 0.0176140071391521183118619623518528L};
+    const long double h = (b - a) / panels;
+    long double sum = 0;
+    for (int k = 0; k < panels; ++k) {
+        const long double mid = a + (k + 0.5L) * h, half = 0.5L * h;
+        long double ps = 0;
+        for (int j = 0; j < 10; ++j) ps += w[j] * (f(mid - half * x[j]) + f(mid + half * x[j]));
+        sum += half * ps;
+    }
+    return sum;
+}
+
+}  // namespace
+
+bool interface_sigma_width(const Eos& e, long double T, long double kappa, long double* sigma, long double* W,
+                           std::string* err) {
+    long double rv, rl, ps;
+    if (!coexistence(e, T, &rv, &rl, &ps, err)) return false;
+    const long double mus = chem_potential(e, rv, T);
+    // grand-potential excess over the tie line: rho (mu - mu_s) - (p - p_s) >= 0
+    auto dom = [&](long double r) {
+        const long double v = r * (chem_potential(e, r, T) - mus) - (pressure(e, r, T) - ps);
+        return v > 0 ? v : 0.0L;
+    };
+    *sigma = gauss_legendre([&](long double r) { return std::sqrt(2.0L * kappa * dom(r)); }, rv, rl, 256);
+    const long double r5 = rv + 0.05L * (rl - rv), r95 = rv + 0.95L * (rl - rv);
+    *W = gauss_legendre([&](long double r) { return std::sqrt(kappa / (2.0L * dom(r))); }, r5, r95, 256);
+    if (!(std::isfinite(*sigma) && std::isfinite(*W) && *sigma > 0 && *W > 0)) {
+        if (err) *err = "interface integrals did not converge";
+        return false;
+    }
+    return true;
+}
+
+bool vapour_root(const Eos& e, long double T, long double p, long double* rho, std::string* err) {
+    // the first zero of dp/drho bounds the vapour branch, on which p rises with rho
+    const long double rmax = density_limit(e);
+    const int nscan = 20000;
+    long double top = -1, prev_r = 0, prev_v = 0;
+    for (int k = 1; k < nscan; ++k) {
+        const long double r = rmax * k / nscan;
+        const long double v = pressure_slope(e, r, T);
+        if (k > 1 && ((v > 0) != (prev_v > 0))) {
+            top = bisect([&](long double x) { return pressure_slope(e, x, T); }, prev_r, r);
+            break;
+        }
+        prev_r = r;
+        prev_v = v;
+    }
+    if (top < 0) top = rmax * (1.0L - 1e-12L);  // supercritical: p rises everywhere
+    if (!(p > 0) || !(pressure(e, top, T) > p)) {
+        if (err) *err = "the pressure is not reached on the vapour branch at this temperature";
+        return false;
+    }
+    *rho = bisect([&](long double x) { return pressure(e, x, T) - p; }, 1e-30L, top);
+    return true;
+}
+
 }  // namespace lbm_host

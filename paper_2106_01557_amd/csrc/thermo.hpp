@@ -24,5 +24,13 @@ void critical(const Eos& e, long double* Tc, long double* pc);
 // Coexisting densities and pressure at T < Tc.  Returns false (with a message) on failure.
 bool coexistence(const Eos& e, long double T, long double* rho_v, long double* rho_l,
                  long double* p_s, std::string* err);
+// Density on the vapour branch (below the first spinodal) at which p_EOS(rho, T) = p.
+// Returns false (with a message) when p is not reached there.
+bool vapour_root(const Eos& e, long double T, long double p, long double* rho, std::string* err);
+// Square-gradient surface tension sigma = int sqrt(2 kappa dOmega) drho over [rho_v, rho_l]
+// and 5 %-95 % width W = int sqrt(kappa / (2 dOmega)) drho of the flat interface at T,
+// with dOmega the grand-potential excess over the coexistence tie line.
+bool interface_sigma_width(const Eos& e, long double T, long double kappa, long double* sigma, long double* W,
+                           std::string* err);
 
 }  // namespace lbm_host

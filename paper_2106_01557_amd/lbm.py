@@ -15,14 +15,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
-LBM_OK, LBM_EINVAL, LBM_ESPACE, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_OK, LBM_EINVAL, LBM_ESPACE, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE, LBM_EIO = 0, -1, -2, -3, -4, -5, -6
 EOS_KINDS = {"cs": 0, "vdw": 1}
+BOUNDARIES = {"periodic": 0, "heated_outflow": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 SCHEMES = {"ab": 0, "aa": 1}
 ROUNDINGS = {"nearest": 0, "stochastic": 1}
 DERIVED_NAMES = ["Tc", "pc", "T0", "rho_v", "rho_l", "p_s", "cs", "c", "dt", "G2", "a_mf", "kappa", "cv",
                  "C_ref", "beta", "k", "h", "bS", "s_p", "s_q", "s_e", "omega_e", "omega_p", "tau_j_v",
-                 "tau_j_l", "h_lv"]
+                 "tau_j_l", "h_lv", "rho_wall"]
 INVARIANT_NAMES = ["mass", "mom_x", "mom_y", "sum_g", "dt_sum_q", "E_p", "E_kin", "bad_nodes"]
 
 
@@ -33,7 +34,7 @@ class LbmError(RuntimeError):
 
 
 class _Lattice(ctypes.Structure):
-    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double)]
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double), ("bc_x", ctypes.c_int32)]
 
 
 class _Eos(ctypes.Structure):
@@ -43,8 +44,9 @@ class _Eos(ctypes.Structure):
 
 _PARAM_DOUBLES = ["Tr0", "K_int", "varpi", "gamma1", "gamma2", "tau_p", "s_eps", "sigma_e", "sigma_eps",
                   "sigma_q", "sigma_p", "tau_j_v", "lambda_ratio", "cv", "ste", "dTr_ste", "C_ref", "accel_x",
-                  "accel_y", "cs_override", "rho_ref", "T_ref"]
-_PARAM_INTS = ["precision", "scheme", "rows_per_wave", "waves_per_block", "columns_per_lane", "rounding"]
+                  "accel_y", "cs_override", "rho_ref", "T_ref", "Tr_wall", "Tr_far", "p_out"]
+_PARAM_INTS = ["precision", "scheme", "rows_per_wave", "waves_per_block", "columns_per_lane", "rounding",
+               "check_every"]
 
 
 class _Params(ctypes.Structure):
@@ -54,8 +56,8 @@ class _Params(ctypes.Structure):
 EXPORTED = ["lbm_default_params", "lbm_default_eos", "lbm_workspace_bytes", "lbm_init", "lbm_set_fields",
             "lbm_step", "lbm_moments", "lbm_invariants", "lbm_derived", "lbm_launch_shape", "lbm_step_count",
             "lbm_state_bytes",
-            "lbm_save_state", "lbm_load_state", "lbm_destroy", "lbm_strerror", "lbm_last_error",
-            "lbm_maxwell", "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set_shape",
+            "lbm_save_state", "lbm_load_state", "lbm_save", "lbm_load", "lbm_destroy", "lbm_strerror", "lbm_last_error",
+            "lbm_maxwell", "lbm_interface_constants", "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set_shape",
             "lbm_batch_get_shape", "lbm_batch_set_graph", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_size",
             "lbm_batch_destroy", "lbm_batch_last_error"]
 
@@ -85,12 +87,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_state_bytes.argtypes = [V, P(S)]
     lib.lbm_save_state.argtypes = [V, V, P(ctypes.c_int64)]
     lib.lbm_load_state.argtypes = [V, V, ctypes.c_int64]
+    lib.lbm_save.argtypes = [V, ctypes.c_char_p]
+    lib.lbm_load.argtypes = [V, ctypes.c_char_p]
     lib.lbm_destroy.argtypes = [V]
     lib.lbm_strerror.argtypes = [I]
     lib.lbm_strerror.restype = ctypes.c_char_p
     lib.lbm_last_error.argtypes = [V]
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_maxwell.argtypes = [P(_Eos), D, P(D)]
+    lib.lbm_interface_constants.argtypes = [P(_Eos), D, D, D, D, P(D)]
     lib.lbm_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, P(S)]
     lib.lbm_batch_create.argtypes = [P(V), P(V), ctypes.c_int32, V, S]
     lib.lbm_batch_set_shape.argtypes = [V, P(_BatchShape)]
@@ -161,6 +166,11 @@ def _params_c(overrides: dict | None) -> _Params:
     return p
 
 
+def _bc(v) -> int:
+    """Boundary kind in x: 'periodic' | 'heated_outflow' or the LBM_BC_* value."""
+    return BOUNDARIES[v] if isinstance(v, str) else int(v)
+
+
 def maxwell(Tr: float, eos: Eos | None = None) -> dict:
     """Coexistence of the EOS alone at T/Tc = Tr (host thermodynamics of the library)."""
     out = (ctypes.c_double * 4)()
@@ -169,6 +179,19 @@ def maxwell(Tr: float, eos: Eos | None = None) -> dict:
     if code != LBM_OK:
         raise LbmError(code, f"no coexistence at Tr = {Tr}")
     return {"rho_v": out[0], "rho_l": out[1], "p_s": out[2], "Tc": out[3]}
+
+
+def interface_constants(Tr: float, sigma: float = 0.01, W: float = 10.0, eos: Eos | None = None,
+                        dx: float = 1.0) -> dict:
+    """K_EOS and K_INT for which the flat interface at T/Tc = Tr has surface tension sigma
+    and 5 %-95 % width W (the paper's procedure; its 0.01 and 10 at Tr = 0.8 give
+    0.479820 and 2.294922).  Host thermodynamics of the library."""
+    out = (ctypes.c_double * 2)()
+    e = (eos or Eos())._c()
+    code = _lib.lbm_interface_constants(ctypes.byref(e), float(Tr), float(sigma), float(W), float(dx), out)
+    if code != LBM_OK:
+        raise LbmError(code, _lib.lbm_last_error(None).decode())
+    return {"K_eos": out[0], "K_int": out[1]}
 
 
 def _check(code: int, ctx=None):
@@ -187,8 +210,8 @@ def derived_constants(nx: int, ny: int, eos: Eos | None = None, params: dict | N
 
 
 def workspace_bytes(nx: int, ny: int, params: dict | None = None) -> int:
-    lat = _Lattice(nx, ny, float((params or {}).get("dx", 1.0)))
-    p = _params_c({k: v for k, v in (params or {}).items() if k != "dx"})
+    lat = _Lattice(nx, ny, float((params or {}).get("dx", 1.0)), _bc((params or {}).get("bc_x", 0)))
+    p = _params_c({k: v for k, v in (params or {}).items() if k not in ("dx", "bc_x")})
     out = ctypes.c_size_t()
     _check(_lib.lbm_workspace_bytes(ctypes.byref(lat), ctypes.byref(p), ctypes.byref(out)))
     return out.value
@@ -198,7 +221,7 @@ class Solver:
     """One periodic D2Q9 domain bound to a device workspace and a stream.
 
     params: overrides of the lbm_params fields (see include/lbm.h); 'dx' sets the
-    lattice spacing.  precision: 'f64' | 'f32' | 'f16' | 'bf16'; scheme: 'ab' | 'aa';
+    lattice spacing and 'bc_x' the boundaries in x ('periodic' or 'heated_outflow').  precision: 'f64' | 'f32' | 'f16' | 'bf16'; scheme: 'ab' | 'aa';
     rounding (16-bit storage): 'nearest' | 'stochastic'.
     """
 
@@ -207,12 +230,13 @@ class Solver:
                  host_only: bool = False):
         params = dict(params or {})
         dx = float(params.pop("dx", 1.0))
+        bc = _bc(params.pop("bc_x", 0))
         if precision is not None:
             params["precision"] = precision
         if scheme is not None:
             params["scheme"] = scheme
         self.nx, self.ny = int(nx), int(ny)
-        self._lat = _Lattice(self.nx, self.ny, dx)
+        self._lat = _Lattice(self.nx, self.ny, dx, bc)
         self._eos = (eos or Eos())._c()
         self._p = _params_c(params)
         self._ctx = ctypes.c_void_p()
@@ -291,8 +315,8 @@ class Solver:
         return dict(zip(INVARIANT_NAMES, list(buf)))
 
     def derived(self) -> dict:
-        buf = (ctypes.c_double * 26)()
-        _check(_lib.lbm_derived(self._ctx, buf, 26))
+        buf = (ctypes.c_double * 27)()
+        _check(_lib.lbm_derived(self._ctx, buf, 27))
         return dict(zip(DERIVED_NAMES, list(buf)))
 
     def launch_shape(self) -> tuple:
@@ -320,6 +344,14 @@ class Solver:
     def load_state(self, src, steps: int):
         _check(_lib.lbm_load_state(self._ctx, self._ptr(src), int(steps)), self._ctx)
         self._keep = [src]
+
+    def save(self, path: str):
+        """Checkpoint to a file (header + raw state; synchronising)."""
+        _check(_lib.lbm_save(self._ctx, os.fsencode(path)), self._ctx)
+
+    def load(self, path: str):
+        """Restart from a checkpoint file written for the same configuration."""
+        _check(_lib.lbm_load(self._ctx, os.fsencode(path)), self._ctx)
 
     def close(self):
         if self._ctx:

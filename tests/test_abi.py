@@ -93,8 +93,41 @@ def test_host_constants_match_oracle(lbm, eos_kind, overrides):
     got = lbm.derived_constants(8, 8, eos=eos, params=overrides)
     oe = thermo.paper_cs_eos() if eos_kind == "cs" else thermo.vdw_eos()
     want = dataclasses.asdict(thermo.derive(oe, thermo.Params(**overrides)))
+    assert got.pop("rho_wall") == 0.0  # periodic lattice: no heated wall
     for k, v in got.items():
         assert abs(v - want[k]) <= 1e-14 * max(abs(want[k]), 1e-300), (k, v, want[k])
+
+
+@pytest.mark.parametrize("Tr_wall,p_out", [(0.85, 0.0), (0.9, 0.0), (0.82, 5e-4), (1.1, 0.0)])
+def test_heated_wall_density_matches_oracle(lbm, Tr_wall, p_out):
+    """The boundary density of the heated side (vapour root of p_EOS(rho, T_wall) = p_out,
+    p_out defaulting to the saturation pressure at T0) from the library's long-double host
+    thermodynamics against the 40-digit oracle, also above the critical temperature."""
+    from oracle import lbm as olbm
+    from oracle import stefan
+    params = {"bc_x": "heated_outflow", "Tr_wall": Tr_wall, "p_out": p_out}
+    got = lbm.derived_constants(1024, 4, params=params)
+    model = olbm.Model.build(thermo.paper_cs_eos(), thermo.Params())
+    if Tr_wall >= 1.0:
+        pytest.skip("the oracle's wall density stops at the critical temperature")
+    w = stefan.walls(model, Tr_wall, p_out=p_out if p_out > 0 else None)
+    assert got["rho_wall"] == pytest.approx(w.rho_wall, rel=1e-13)
+    assert got["rho_wall"] < got["rho_v"] if p_out == 0.0 else got["rho_wall"] > 0
+
+
+@pytest.mark.parametrize("params,msg", [
+    ({"bc_x": 5}, "bc_x"), ({"bc_x": "heated_outflow", "Tr_wall": 0.0}, "Tr_wall"),
+    ({"bc_x": "heated_outflow", "Tr_wall": 0.85, "scheme": "aa"}, "SCHEME_AB"),
+    ({"bc_x": "heated_outflow", "Tr_wall": 0.85, "precision": "f16"}, "SCHEME_AB"),
+    ({"bc_x": "heated_outflow", "Tr_wall": 0.85, "p_out": 1.0}, "vapour branch"),
+])
+def test_bounded_lattice_validation(lbm, params, msg):
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Solver(1024, 4, params=params, host_only=True)
+    assert ei.value.code == lbm.LBM_EINVAL and msg in str(ei.value), str(ei.value)
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Solver(8192, 2, params={"bc_x": "heated_outflow", "Tr_wall": 0.85}, host_only=True)
+    assert "8192" in str(ei.value)
 
 
 @pytest.mark.parametrize("bad,msg", [
@@ -106,6 +139,7 @@ def test_host_constants_match_oracle(lbm, eos_kind, overrides):
     ({"rounding": 2}, "rounding"), ({"rounding": "stochastic"}, "stochastic"),
     ({"rounding": "stochastic", "precision": "f32"}, "stochastic"),
     ({"rounding": "stochastic", "precision": "f16", "scheme": "aa"}, "stochastic"),
+    ({"check_every": -1}, "check_every"),
 ])
 def test_invalid_parameters_are_rejected_before_any_device_call(lbm, bad, msg):
     """(stochastic rounding applies to the 16-bit formats of the two-buffer update only)"""
@@ -129,11 +163,25 @@ def test_invalid_eos_is_rejected(lbm):
         lbm.Solver(8, 8, eos=lbm.Eos("redlich", 1.0, 4.0, 1.0, 1.0), host_only=True)
 
 
-def test_host_only_context_refuses_device_calls(lbm):
+def test_host_only_context_refuses_device_calls(lbm, tmp_path):
     s = lbm.Solver(8, 8, host_only=True)
     with pytest.raises(lbm.LbmError) as ei:
         s.step(1)
     assert ei.value.code == lbm.LBM_ESTATE
+    # checkpoint files: no state to save, none to load into (refused before the file is opened)
+    for call in (s.save, s.load):
+        with pytest.raises(lbm.LbmError) as ei:
+            call(str(tmp_path / "state.lbm"))
+        assert ei.value.code == lbm.LBM_ESTATE
+    assert not os.path.exists(tmp_path / "state.lbm")
+    lib = lbm.library()
+    assert lib.lbm_save(None, b"x") == lbm.LBM_EINVAL and lib.lbm_load(None, b"x") == lbm.LBM_EINVAL
+    s.close()
+
+
+def test_check_every_is_a_parameter_with_default_zero(lbm):
+    assert lbm.default_params()["check_every"] == 0
+    s = lbm.Solver(8, 8, params={"check_every": 100}, host_only=True)
     s.close()
 
 
@@ -152,7 +200,7 @@ def test_workspace_size_accounts_for_scheme_and_precision(lbm):
 
 def test_strerror_covers_codes(lbm):
     lib = lbm.library()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.lbm_strerror(code).decode() not in ("", "unknown error")
     assert lib.lbm_strerror(-99).decode() == "unknown error"
 
@@ -213,7 +261,7 @@ def test_header_is_plain_c_and_the_library_links_from_c(lbm, tmp_path):
 #include <string.h>
 #include "lbm.h"
 int main(void) {
-    lbm_params p; lbm_eos e; lbm_lattice lat = {32, 16, 1.0};
+    lbm_params p; lbm_eos e; lbm_lattice lat = {32, 16, 1.0, LBM_BC_PERIODIC};
     if (lbm_default_params(&p) != LBM_OK || lbm_default_eos(&e) != LBM_OK) return 1;
     double mx[4];
     if (lbm_maxwell(&e, p.Tr0, mx) != LBM_OK) return 2;
@@ -244,3 +292,32 @@ int main(void) {
     assert float(rv_d) == float(rv)
     assert float(dt) == pytest.approx(0.401407522, rel=1e-8)
     assert "order" in msg
+
+
+def test_interface_constants_reproduce_the_paper(lbm, golden):
+    """The paper's procedure (sigma and W of the flat interface at T_r0 fix K_EOS and K_INT)
+    in the library's host thermodynamics gives the printed pair for sigma = 0.01, W = 10."""
+    g = golden["sigma_W_scaling"]
+    got = lbm.interface_constants(0.8, g["sigma"], g["W"])
+    assert got["K_eos"] == pytest.approx(g["K_eos"], abs=5e-7)
+    assert got["K_int"] == pytest.approx(g["K_int"], abs=5e-7)
+
+
+@pytest.mark.parametrize("eos_kind", ["cs", "vdw"])
+@pytest.mark.parametrize("Tr", [0.6, 0.7, 0.9])
+def test_interface_constants_match_oracle(lbm, eos_kind, Tr):
+    """The constants, fed back into the 40-digit oracle, give the requested tension and
+    width (the oracle integrates the same square-gradient definitions with mpmath)."""
+    eos = lbm.Eos() if eos_kind == "cs" else lbm.vdw_eos()
+    got = lbm.interface_constants(Tr, 0.01, 10.0, eos=eos)
+    oe = thermo.paper_cs_eos() if eos_kind == "cs" else thermo.vdw_eos()
+    oe = thermo.Eos(oe.kind, oe.a_t, oe.b_t, oe.R, got["K_eos"])
+    d = thermo.derive(oe, thermo.Params(Tr0=Tr, K_int=got["K_int"]))
+    assert float(thermo.surface_tension(oe, d.T0, d.kappa)) == pytest.approx(0.01, rel=1e-11)
+    assert float(thermo.interface_width(oe, d.T0, d.kappa)) == pytest.approx(10.0, rel=1e-11)
+
+
+def test_interface_constants_reject_bad_input(lbm):
+    for args in ((1.0, 0.01, 10.0), (0.8, 0.0, 10.0), (0.8, 0.01, -1.0), (float("nan"), 0.01, 10.0)):
+        with pytest.raises(lbm.LbmError):
+            lbm.interface_constants(*args)

@@ -425,15 +425,20 @@ def test_unet_every_layer_teacher_forced(widths, hw):
             wgrad_check("e0a", b["x0"], b["ge0a"])
 
 
-@pytest.mark.parametrize("widths,hw,bars", [((16, 32, 48), 16, (2e-3, 1e-2, 0.9999)),
-                                            ((32, 64, 128, 256), 32, (3e-2, 1.5e-1, 0.99))], ids=["small", "full"])
-def test_unet_end_to_end_against_reference(widths, hw, bars):
-    """One training step end to end against the reference with the GPU's bfloat16
-    storage points.  The per-layer test above is the parity check; here the small
-    network must agree to accumulation level, while in the deep one the rare values
-    that fall on the other side of a bfloat16 rounding boundary or of a ReLU gate
-    propagate through eighteen layers (measured: outputs 7e-3, gradients up to about
-    5e-2 relative L2), hence the wider bars."""
+@pytest.mark.parametrize("widths,hw,bars,exact_bars",
+                         [((16, 32, 48), 16, (2e-3, 1e-2, 0.9999), (1.2e-2, 6e-2, 0.998)),
+                          ((32, 64, 128, 256), 32, (3e-2, 1.5e-1, 0.99), (1.2e-2, 6e-2, 0.998))],
+                         ids=["small", "full"])
+def test_unet_end_to_end_against_reference(widths, hw, bars, exact_bars):
+    """One training step end to end, first against the plain FP64 reference (no storage
+    rounding anywhere): the GPU stores activations and their gradients in bfloat16, so the
+    outputs may differ by a few bfloat16 steps relative (measured 4e-3 to 6e-3 relative L2
+    on the outputs and 2e-2 to 3e-2 on the gradients of the full network), held at twice
+    that.  Then against the reference with the GPU's bfloat16 storage points: the
+    per-layer test above is the parity check; here the small network must agree to
+    accumulation level, while in the deep one the rare values that fall on the other side
+    of a bfloat16 rounding boundary or of a ReLU gate propagate through eighteen layers
+    (measured: outputs 7e-3, gradients up to about 5e-2 relative L2), hence the wider bars."""
     out_bar, grad_bar, cos_bar = bars
     say(f"case: U-Net widths {widths} on {hw}x{hw}, end to end")
     net, arch, p, x, rin, tn, out, loss, grads = _net_case(widths, hw)
@@ -443,8 +448,14 @@ def test_unet_end_to_end_against_reference(widths, hw, bars):
     ro, cache = U.forward(arch, p, x, rin=rin)
     lref, dref = U.mse(ro, tn)
     gref, _ = U.backward(arch, p, cache, dref)
+    r_exact = _rel(o - rin, ro - rin)
     worst_exact = max(_rel(got[k].reshape(gref[k].shape), gref[k]) for k in gref)
-    say(f"  vs exact FP64: out rel {_rel(o - rin, ro - rin):.2e}, worst gradient rel {worst_exact:.2e}")
+    say(f"  vs exact FP64: out rel {r_exact:.2e}, worst gradient rel {worst_exact:.2e}")
+    eo, eg, ec = exact_bars
+    assert r_exact < eo
+    for k in gref:
+        gg = got[k].reshape(gref[k].shape)
+        assert _rel(gg, gref[k]) < eg and _cos(gg, gref[k]) > ec, (k, _rel(gg, gref[k]))
     ro, cache = U.forward(arch, p, x, store=U.bf16_round, rin=rin)
     lref, dref = U.mse(ro, tn)
     gref, _ = U.backward(arch, p, cache, dref, store=U.bf16_round)

@@ -1,0 +1,102 @@
+"""Pins for oracle/stefan.py, the oracle of the update on a domain bounded in x (the
+one-dimensional Stefan problem, Eqs. (20)-(21)), against what the physics fixes:
+
+* a uniform vapour at the wall state stays exactly steady (the boundary rule returns the
+  equilibrium when the neighbour is in equilibrium);
+* steady heat conduction through a vapour layer between two walls at different
+  temperatures, at constant pressure, gives a linear temperature profile (Fourier's law
+  with the constant vapour conductivity of the text after Eq. (16)) and no flow;
+* the Neumann root of Eq. (21) and the small-Stefan-number limit k = sqrt(Ste / 2) are
+  pinned in test_oracle_thermo.py; here the position formula of Eq. (20) is checked on
+  its own definition's derivative (X dX/dt = 2 k^2 alpha).
+The boundary rule itself stands in for a scheme the paper cites without stating it; the
+comparison that fixes the whole bounded update against the paper is the interface
+position against the Neumann solution, a long run made on the GPU
+(test_gpu_stefan.py).  Parity unpinned beyond these checks: the boundary populations'
+non-equilibrium part (a plain equilibrium boundary also passes the conduction check).
+"""
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import lbm, stefan, thermo
+
+
+@pytest.fixture(scope="module")
+def model():
+    return lbm.Model.build(thermo.paper_cs_eos(), thermo.Params())
+
+
+def test_wall_density_is_vapour_at_the_outflow_pressure(model):
+    d = model.d
+    w = stefan.walls(model, 0.85)
+    assert w.p_out == d.p_s and w.T_wall == pytest.approx(0.85 * d.Tc, rel=1e-15)
+    assert float(thermo.pressure(model.eos, w.rho_wall, w.T_wall)) == pytest.approx(d.p_s, rel=1e-13)
+    # superheated vapour: below the saturated vapour density at T0, above zero
+    assert 0 < w.rho_wall < d.rho_v
+    sp = float(thermo.spinodals(model.eos, mp.mpf(w.T_wall))[0])
+    assert w.rho_wall < sp
+
+
+def test_uniform_vapour_at_the_wall_state_is_steady(model):
+    w = stefan.walls(model, 0.85, Tr_far=0.85)
+    rho = np.full((3, 12), w.rho_wall)
+    st0 = stefan.init_state(model, rho, 0 * rho, 0 * rho, 0 * rho + w.T_wall)
+    st = stefan.run(model, w, st0, 40)
+    r, ux, uy, T = stefan.moments(model, w, st)
+    assert np.abs(r / w.rho_wall - 1).max() < 1e-13
+    assert np.abs(T / w.T_wall - 1).max() < 1e-13
+    assert np.abs(ux).max() < 1e-13 * model.d.cs and np.abs(uy).max() < 1e-13 * model.d.cs
+    assert np.allclose(st.f[:, :, 1:-1], st0.f[:, :, 1:-1], rtol=0, atol=1e-15)
+
+
+def _isobaric_vapour(model, w, T):
+    """Vapour densities with p_EOS(rho, T) = p_out (the steady state has uniform pressure)."""
+    out = []
+    for Tx in T:
+        lo, hi = mp.mpf("1e-30"), thermo.spinodals(model.eos, mp.mpf(Tx))[0]
+        for _ in range(200):
+            mid = (lo + hi) / 2
+            if thermo.pressure(model.eos, mid, Tx) > w.p_out:
+                hi = mid
+            else:
+                lo = mid
+        out.append(float((lo + hi) / 2))
+    return np.array(out)
+
+
+def check_conduction(model, steps=3000, nx=32):
+    """Vapour between the heated wall (T_r 0.85) and a wall at T_r 0.81: after `steps`
+    steps from the isobaric linear state the temperature is linear between the two
+    boundary nodes within 1.5e-3 of the temperature difference, with no flow."""
+    w = stefan.walls(model, 0.85, Tr_far=0.81)
+    x = np.arange(nx, dtype=float)
+    lin = w.T_wall + (w.T_far - w.T_wall) * x / (nx - 1)
+    rho = _isobaric_vapour(model, w, lin)[None, :]
+    st = stefan.init_state(model, rho, 0 * rho, 0 * rho, lin[None, :])
+    st = stefan.run(model, w, st, steps)
+    r, ux, uy, T = stefan.moments(model, w, st)
+    dev = np.abs(T[0] - lin).max() / (w.T_wall - w.T_far)
+    assert dev < 1.5e-3, dev
+    assert np.abs(ux).max() < 2e-4 * model.d.cs
+
+
+def test_steady_conduction_profile_is_linear():
+    # a conductivity five times the default brings the layer to its steady state sooner
+    check_conduction(lbm.Model.build(thermo.paper_cs_eos(), thermo.Params(tau_j_v=0.5)))
+
+
+def test_neumann_position_formula():
+    k, alpha, t0 = 0.0499584, 0.083, 1234.0
+    t = np.linspace(0, 1e6, 11)
+    X = stefan.neumann_position(k, alpha, t, t0)
+    h = 1e-3
+    dXdt = (stefan.neumann_position(k, alpha, t + h, t0) - stefan.neumann_position(k, alpha, t - h, t0)) / (2 * h)
+    assert np.allclose(X * dXdt, 2 * k * k * alpha, rtol=1e-6)
+    assert X[0] == pytest.approx(2 * k * np.sqrt(alpha * t0))
+
+
+def test_interface_position_interpolates_the_mid_density():
+    row = np.array([0.02, 0.02, 0.05, 0.2, 0.3, 0.3])
+    X = stefan.interface_position(row, 0.02, 0.3)
+    assert X == pytest.approx(2 + (0.16 - 0.05) / 0.15)
