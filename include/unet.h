@@ -67,6 +67,22 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
                        float* dw, float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H,
                        int32_t W, int32_t C_in, int32_t C_out, void* stream);
 
+/* The same weight and bias gradients for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * partial sums go to a static device array of UNET_WGRAD_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends, and nothing is allocated.  The
+ * caller still owns x, g, dw and db.  Results are bitwise those of unet_conv3x3_wgrad
+ * (same split and summation order).  UNET_EINVAL when the shape needs more partials than
+ * the array holds (unet_wgrad_partial_bytes() > UNET_WGRAD_SCRATCH_BYTES; every layer of
+ * the 32/64/128/256 network at 256x256 x 16 fits), UNET_EHIP when the array's device
+ * address cannot be looked up.  Every call on one GPU uses that GPU's one array: calls
+ * that overlap on one GPU (other streams, other host threads) race and must be ordered
+ * by the caller; calls on one stream are ordered by the stream. */
+#define UNET_WGRAD_SCRATCH_BYTES ((size_t)48 << 20)
+int unet_conv3x3_wgrad_noalloc(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg,
+                               float* dw, float* db, int32_t N, int32_t H, int32_t W, int32_t C_in,
+                               int32_t C_out, void* stream);
+
 /* 2x2 max pooling with stride 2: y[n,Y,X,c] = max of x over rows 2Y..2Y+1, cols 2X..2X+1.
  * The four 2x2 calls take C a multiple of 8 and need N * H * W * C / 8 < 2^31, with
  * H, W the full-resolution sizes (UNET_EINVAL otherwise). */

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "../../include/unet.h"
@@ -1813,16 +1814,33 @@ int unet_wgrad_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C_in, int3
     return UNET_OK;
 }
 
-int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, float* dw,
-                       float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C_in,
-                       int32_t C_out, void* stream) {
-    size_t need = 0;
+}  // extern "C"
+
+// Partial sums of unet_conv3x3_wgrad_noalloc.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is ever handed to a kernel.
+static __device__ __align__(256) float scratch[UNET_WGRAD_SCRATCH_BYTES / sizeof(float)];
+
+namespace {
+
+// Checks the arguments shared by both weight-gradient entry points; *need gets the
+// partials size of this shape.
+int wgrad_check(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, const float* dw,
+                int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, size_t* need) {
     int r;
-    if ((r = unet_wgrad_partial_bytes(N, H, W, C_in, C_out, &need))) return r;
+    if ((r = unet_wgrad_partial_bytes(N, H, W, C_in, C_out, need))) return r;
     if ((r = check_tensor("x", x, ldx, offx, C_in, false))) return r;
     if ((r = check_tensor("g", g, ldg, offg, C_out, false))) return r;
     if (!dw) return fail(UNET_EINVAL, "dw is NULL");
-    if (!partials || partial_bytes < need) return fail(UNET_EINVAL, "partials: %zu bytes needed", need);
+    return UNET_OK;
+}
+
+// Launches the split weight gradient with its partial sums in `partials` (device memory
+// of at least the checked size) and the fixed-order reduction.
+int wgrad_launch(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, float* dw,
+                 float* db, void* partials, int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out,
+                 void* stream) {
+    int r;
     int lh, lw;
     check_geo(N, H, W, &lh, &lw);
     const WgPlan p = wgrad_plan(N * H * W, lh, lw, C_in, C_out);
@@ -1869,6 +1887,57 @@ int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, 
         hipLaunchKernelGGL((k_wgrad_reduce<4, 4>), dim3((n + 63) / 64), dim3(256), 0, s, a.part, dw, db, p.slabs,
                            C_out, a.K, p.Kt);
     return launched("wgrad reduce launch");
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+int scratch_on_current_device(float** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(UNET_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(UNET_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(UNET_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return UNET_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, float* dw,
+                       float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C_in,
+                       int32_t C_out, void* stream) {
+    size_t need = 0;
+    int r;
+    if ((r = wgrad_check(x, ldx, offx, g, ldg, offg, dw, N, H, W, C_in, C_out, &need))) return r;
+    if (!partials || partial_bytes < need) return fail(UNET_EINVAL, "partials: %zu bytes needed", need);
+    return wgrad_launch(x, ldx, offx, g, ldg, offg, dw, db, partials, N, H, W, C_in, C_out, stream);
+}
+
+int unet_conv3x3_wgrad_noalloc(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg,
+                               float* dw, float* db, int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out,
+                               void* stream) {
+    size_t need = 0;
+    int r;
+    if ((r = wgrad_check(x, ldx, offx, g, ldg, offg, dw, N, H, W, C_in, C_out, &need))) return r;
+    if (need > UNET_WGRAD_SCRATCH_BYTES)
+        return fail(UNET_EINVAL, "wgrad_noalloc: this shape needs %zu bytes of partial sums, above the %zu-byte "
+                                 "static scratch; use unet_conv3x3_wgrad with a caller workspace",
+                    need, (size_t)UNET_WGRAD_SCRATCH_BYTES);
+    float* part = nullptr;
+    if ((r = scratch_on_current_device(&part))) return r;
+    return wgrad_launch(x, ldx, offx, g, ldg, offg, dw, db, part, N, H, W, C_in, C_out, stream);
 }
 
 int unet_maxpool2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t ldy, int32_t offy, int32_t N,

@@ -27,7 +27,7 @@ _lib = _lbm.library()
 _P, _I, _F, _V, _S = ctypes.POINTER, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
 
 EXPORTED = ["unet_conv3x3_fwd", "unet_flip_weights", "unet_flip_weights_many", "unet_wgrad_partial_bytes",
-            "unet_conv3x3_wgrad",
+            "unet_conv3x3_wgrad", "unet_conv3x3_wgrad_noalloc",
             "unet_maxpool2_fwd", "unet_maxpool2_bwd", "unet_upsample2_fwd", "unet_upsample2_bwd",
             "unet_prepare_input", "unet_output_fields", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd", "unet_adam",
             "unet_to_bf16", "unet_to_f32", "unet_last_error"]
@@ -40,6 +40,7 @@ _lib.unet_flip_weights_many.argtypes = [ctypes.POINTER(_V), ctypes.POINTER(_V), 
                                         ctypes.POINTER(_I), _I, _V]
 _lib.unet_wgrad_partial_bytes.argtypes = [_I, _I, _I, _I, _I, _P(_S)]
 _lib.unet_conv3x3_wgrad.argtypes = [_V, _I, _I, _V, _I, _I, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
+_lib.unet_conv3x3_wgrad_noalloc.argtypes = [_V, _I, _I, _V, _I, _I, _V, _V, _I, _I, _I, _I, _I, _V]
 _lib.unet_maxpool2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_maxpool2_bwd.argtypes = [_V, _I, _I, _V, _I, _I, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_upsample2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
