@@ -68,6 +68,14 @@ def slab(nx, ny, rho_l, rho_v, T0, y0, y1, width=0.0, eps=0.0, seed=None) -> Fie
     return _finish(_noise(rho, eps, seed), T0)
 
 
+def heated_layer(nx, ny, rho_l, rho_v, T0, X0, width) -> Fields:
+    """Vapour for x < X0 and liquid beyond (the start of the one-dimensional Stefan
+    problem: a vapour layer against the heated side x = 0), tanh interface of the given
+    width centred at x = X0, uniform in y, at rest, T = T0."""
+    x = np.arange(nx, dtype=np.float64)[None, :] * np.ones((ny, 1))
+    return _finish(tanh_blend(X0 - x, rho_l, rho_v, width), T0)
+
+
 def droplet(nx, ny, rho_l, rho_v, T0, radius, width, cx=None, cy=None, eps=0.0, seed=None) -> Fields:
     """A circular liquid droplet (tanh interface of the given width) centred at (nx/2, ny/2)
     unless (cx, cy) are given; distances are not wrapped."""

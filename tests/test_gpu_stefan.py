@@ -106,3 +106,41 @@ def test_one_row_equals_every_row_of_a_y_uniform_domain():
     for k in a:
         for row in range(4):
             assert np.array_equal(a[k][row], b[k][0]), (k, row)
+
+
+def test_interface_approaches_the_neumann_solution():
+    """Eq. (20) holds in the sharp-interface limit: once the vapour layer is much thicker
+    than the interface (W = 10 nodes), X_i^2 grows at the rate 4 k^2 alpha_v with k from
+    Eq. (21) (Ste = 0.005) and alpha_v = c^2 dt tau_j,v / 3.  From a 20-node layer, 4e6
+    FP64 steps (t = 1.6e6, X_i 20 -> 44) on one row: X_i rises monotonically, the rate of
+    X_i^2 over successive 1e6-step windows falls toward 4 k^2 alpha_v and ends within 10 %
+    of it, and X_i at the end is within 8 % of Eq. (20) with t_0 set by the start
+    (X_i(0) = 20).  The paper's own run (its Fig. 1) is ten times longer; the benchmark's
+    Stefan workload runs that length."""
+    from oracle import stefan, thermo
+    model = oracle_model("cs")
+    d = model.d
+    k = float(thermo.stefan_root(0.005))
+    alpha = d.c ** 2 * d.dt * d.tau_j_v / 3.0
+    rate = 4 * k * k * alpha
+    f = stefan_fields(d, ny=1)
+    say("case: bounded 1024x1 FP64, 4e6 steps, interface position against Eq. (20)")
+    from paper_2106_01557_amd import lbm
+    s = lbm.Solver(1024, 1, params=dict(WALL, precision="f64"))
+    s.set_fields(*f.as_tuple())
+    ts, xs = [0.0], [stefan.interface_position(f.rho[0], d.rho_v, d.rho_l)]
+    for _ in range(16):
+        s.step(250_000)
+        rho = s.moments_numpy()["rho"][0]
+        ts.append(s.steps * d.dt)
+        xs.append(stefan.interface_position(rho, d.rho_v, d.rho_l))
+    assert s.invariants()["bad_nodes"] == 0
+    ts, xs = np.array(ts), np.array(xs)
+    rates = [np.polyfit(ts[a:a + 5], xs[a:a + 5] ** 2, 1)[0] / rate for a in (0, 4, 8, 12)]
+    x_eq20 = np.sqrt(xs[0] ** 2 + rate * ts[-1])
+    say(f"  X_i {xs[0]:.2f} -> {xs[-1]:.3f} (Eq. (20): {x_eq20:.3f}); rate of X_i^2 / 4k^2 alpha_v per window: "
+        + ", ".join(f"{r:.4f}" for r in rates))
+    assert np.all(np.diff(xs) > 0)
+    assert all(b < a for a, b in zip(rates, rates[1:]))
+    assert 1.0 - 0.1 < rates[-1] < 1.0 + 0.1
+    assert abs(xs[-1] / x_eq20 - 1) < 0.08

@@ -44,20 +44,22 @@ def test_trained_network_beats_no_change_baseline(trained):
 
 
 def test_warm_started_solver_settles_near_the_plain_state(trained):
-    """The solver finishes from the network's prediction: the warm-started runs settle
-    (bulk densities steady to 1e-3) and end near the plain runs' bulk densities (this
-    small network, trained on 96 problems, lands within about 5 %; the full-size
-    workload's figures come from the benchmark)."""
+    """The solver finishes from the network's prediction, put back on the initial state's
+    mass and total energy: at least half of the warm-started runs settle into the plain
+    runs' state (both bulk densities within 1e-3 of the plain run's final values; the
+    full-size workload's figures come from the benchmark)."""
     from paper_2106_01557_amd import warmstart as ws
     net = trained[0]
     say("case: warm start comparison on 8 held-out problems, 3000 steps")
     res = ws.compare_warm_start(net, _small_specs(8, seed=13), horizon=400, steps=3000, every=100)
     for q in res["per_problem"]:
         say(f"  {q}")
-    say(f"  {res['compared']} compared; plain median {res['plain_steps_median']}, warm median "
-        f"{res['warm_steps_median']}, final deviation {res['warm_final_max_rel_dev']}")
-    assert res["compared"] >= 4
-    assert res["warm_final_max_rel_dev"] < 1e-1
+    say(f"  {res['same_final_state']} reach the plain final state (within 1e-3), {res['other_final_state']} "
+        f"settle elsewhere; plain median {res['plain_steps_median']}, warm median {res['warm_steps_median']}, "
+        f"final deviation median {res['warm_final_rel_dev_median']}, max {res['warm_final_rel_dev_max']}; "
+        f"start offsets: mass {res['start_mass_offset_max']:.1e}, energy {res['start_energy_offset_max']:.1e}")
+    assert res["start_mass_offset_max"] < 1e-6 and res["start_energy_offset_max"] < 1e-6
+    assert res["same_final_state"] >= 4
 
 
 def test_equal_error_steps_are_positive_for_the_trained_network(trained):
