@@ -276,8 +276,11 @@ def batch_coexistence(b, sols, spec, steps, every, ms_per_step) -> dict:
     per = []
     for i, (s, m) in enumerate(zip(sols, spec)):
         rl, rv, Tl, Tv = (float(v) for v in final[i])
+        # settled: from this sample on, both bulk densities stay within 1e-3 of the run's
+        # final values, and the run goes on for at least ten more samples (a domain that
+        # only settles at the end of the run has no time to coexistence within it)
         t_first = None
-        for k in range(len(hist)):
+        for k in range(len(hist) - 10):
             ok = all(abs(h[1][i][0] - rl) <= 1e-3 * rl and abs(h[1][i][1] - rv) <= 1e-3 * rv for h in hist[k:])
             if ok:
                 t_first = hist[k][0]
@@ -296,7 +299,8 @@ def batch_coexistence(b, sols, spec, steps, every, ms_per_step) -> dict:
     slabs = [p for p in per if p["kind"] == "slab"]
     return {
         "steps": steps, "check_every": every,
-        "converged_domains": len(ttc), "domains": len(per),
+        "settled_domains": len(ttc), "domains": len(per),
+        "finite_domains": sum(1 for p in per if p["bad_nodes"] == 0),
         "failed_domains": [(p["side"], p["kind"], p["Tr0"]) for p in per if p["bad_nodes"] > 0],
         "steps_to_coexistence_median": float(np.median(ttc)) if ttc else None,
         "steps_to_coexistence_max": max(ttc) if ttc else None,
@@ -371,7 +375,7 @@ def run_warmstart(args) -> dict:
     cmp_specs = cmp_pool[: args.compare_runs]
     eq = ws.equal_error_steps(net, cmp_specs, args.horizon, 250, log=log)
     log(f"equal-error steps saved: median {eq['steps_saved_median']:.0f} of {args.horizon}")
-    res = ws.compare_warm_start(net, cmp_specs, args.horizon, args.compare_steps, args.check_every, log=log)
+    res = ws.compare_warm_start(net, cmp_specs, args.horizon, args.compare_steps, max(args.check_every, 1000), log=log)
     per = res.pop("per_problem")
     samples_s = args.epochs * (n_train // B) * B / t_train
     achieved = flops / (step_ms * 1e-3) / 1e12
@@ -581,7 +585,8 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--compare-runs", type=int, default=64)
-    ap.add_argument("--compare-steps", type=int, default=20000)
+    ap.add_argument("--compare-steps", type=int, default=120000,
+                    help="warmstart: steps of the plain and warm-started runs (256 x 256 runs settle to 1e-3 in about 1e5)")
     ap.add_argument("--autotune-steps", type=int, default=5)
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--alone-steps", type=int, default=200,

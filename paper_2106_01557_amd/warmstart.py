@@ -233,11 +233,14 @@ def evaluate_loss(net, ds, batch: int = 16) -> float:
     return tot / (n // batch * batch)
 
 
-def coexistence_times(runner: Runner, start_rho, steps: int, every: int, final=None, start_T=None):
+def coexistence_times(runner: Runner, start_rho, steps: int, every: int, final=None, start_T=None,
+                      settle: int = 10):
     """Runs from (start_rho, start_T) and records the bulk densities every `every` steps.
-    final: (liquid, vapour) reference values (default: this run's last sample).
-    Returns the per-problem step counts to coexistence (None where never reached),
-    the last bulk values and the elapsed seconds of the stepping."""
+    final: (liquid, vapour) reference values (default: this run's last sample).  A
+    problem's time to coexistence is the first sample from which both bulk densities stay
+    within 1e-3 of the reference, provided at least `settle` more samples follow (a run
+    that only gets there at its end has none).  Returns the per-problem step counts (None
+    where not reached), the last bulk values and the elapsed seconds of the stepping."""
     runner.set_fields(start_rho, start_T)
     hist, t_step = [], 0.0
     done = 0
@@ -254,7 +257,7 @@ def coexistence_times(runner: Runner, start_rho, steps: int, every: int, final=N
     times = []
     for i in range(len(runner.specs)):
         t_hit = None
-        for k in range(len(hist)):
+        for k in range(len(hist) - settle):
             ok = all(abs(h[1][i] - ref[0][i]) <= 1e-3 * abs(ref[0][i]) and
                      abs(h[2][i] - ref[1][i]) <= 1e-3 * abs(ref[1][i]) for h in hist[k:])
             if ok:
@@ -278,37 +281,31 @@ def guard_prediction(rho, T, rho_v, rho_l, T0, t_band: float = 0.15):
     return rho, T
 
 
-def _totals(runner: Runner, rho, T):
-    """Per-problem (mass, total energy) of the state (rho, T, at rest) as the library's
-    diagnostics report them: mass, and sum rho e_k plus the discrete potential energy."""
-    runner.set_fields(rho, T)
-    inv = [s.invariants(raise_on_bad=False) for s in runner.solvers]
-    return (np.array([v["mass"] for v in inv]), np.array([v["E_kin"] + v["E_p"] for v in inv]))
+def _masses(runner: Runner, rho):
+    """Per-problem mass of the density field, as the library's diagnostics sum it."""
+    runner.set_fields(rho)
+    return np.array([s.invariants(raise_on_bad=False)["mass"] for s in runner.solvers])
 
 
-def match_invariants(runner: Runner, rho0, T0f, prho, pT, rounds: int = 3):
-    """Puts a guarded prediction on the initial state's invariant manifold: the solver
-    conserves mass exactly and the total energy to truncation error, so a start with
-    other totals settles into another equilibrium.  The density is rescaled per problem
-    to the initial mass (and re-guarded), then the temperature shifted uniformly so that
-    sum rho e_k + E_p equals the initial state's.  Returns (rho, T, relative mass and
-    energy offsets left)."""
+def match_mass(runner: Runner, rho0, prho, pT, rounds: int = 3):
+    """Puts a guarded prediction back on the initial state's mass, the one invariant the
+    update keeps exactly: the density is rescaled per problem to the initial mass and
+    re-guarded.  The temperature stays as predicted.  The total energy (sum rho e_k plus
+    the discrete potential energy) is not an invariant of the discrete update: it falls
+    by about 1.5e-3 of itself in the first 400 steps of a two-droplet 64 x 64 problem
+    and 6e-3 in 3000, so the horizon state the network learned already carries that
+    loss, and restoring the initial energy would start the run too hot.  Returns (rho,
+    relative mass offsets left)."""
     torch = runner.torch
-    m0, e0 = _totals(runner, rho0, T0f)
-    cv = torch.tensor([c["cv"] for c in runner.consts], dtype=torch.float64, device="cuda")
+    m0 = _masses(runner, rho0)
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
     for k in range(rounds + 1):
-        m1, _ = _totals(runner, prho, pT)
+        m1 = _masses(runner, prho)
         with torch.cuda.stream(runner.stream):
             prho = prho * dev(m0 / m1)[:, None, None]
             if k < rounds:  # the last rescale is not clamped again: it is within a part in 1e6 of 1
-                prho, pT = guard_prediction(prho, pT, runner.rho_v, runner.rho_l, runner.T0)
-    for _ in range(2):
-        m1, e1 = _totals(runner, prho, pT)
-        with torch.cuda.stream(runner.stream):
-            pT = pT + (dev(e0 - e1) / (cv * dev(m1)))[:, None, None]
-    m1, e1 = _totals(runner, prho, pT)
-    return prho, pT, np.abs(m1 / m0 - 1), np.abs(e1 / e0 - 1)
+                prho, _ = guard_prediction(prho, pT, runner.rho_v, runner.rho_l, runner.T0)
+    return prho, np.abs(_masses(runner, prho) / m0 - 1)
 
 
 def compare_warm_start(net, specs, horizon: int, steps: int, every: int, log=None):
@@ -332,7 +329,7 @@ def compare_warm_start(net, specs, horizon: int, steps: int, every: int, log=Non
     t_inf = time.perf_counter() - t0
     with torch.cuda.stream(r.stream):  # the runner's stream, which starts the runs
         prho, pT = guard_prediction(prho, pT, r.rho_v, r.rho_l, r.T0)
-    prho, pT, dmass, denergy = match_invariants(r, rho0, T0f, prho, pT)
+    prho, dmass = match_mass(r, rho0, prho, pT)
     warm, wlast, t_warm = coexistence_times(r, prho.contiguous(), steps, every, final=final, start_T=pT.contiguous())
     r.close()
     finite = [i for i in range(len(specs)) if all(np.isfinite(v[i]) for v in (final[0], final[1], wlast[0], wlast[1]))]
@@ -353,7 +350,7 @@ def compare_warm_start(net, specs, horizon: int, steps: int, every: int, log=Non
         "inference_seconds": t_inf, "plain_step_seconds": t_plain, "warm_step_seconds": t_warm,
         "warm_final_rel_dev_median": float(np.median(list(dev.values()))) if dev else None,
         "warm_final_rel_dev_max": float(max(dev.values())) if dev else None,
-        "start_mass_offset_max": float(dmass.max()), "start_energy_offset_max": float(denergy.max()),
+        "start_mass_offset_max": float(dmass.max()),
         "per_problem": [{"plain": plain[i], "warm": warm[i], "rho_l": float(final[0][i]), "rho_v": float(final[1][i]),
                          "warm_rho_l": float(wlast[0][i]), "warm_rho_v": float(wlast[1][i]), "tr": specs[i].tr}
                         for i in range(len(specs))],
@@ -375,7 +372,7 @@ def equal_error_steps(net, specs, horizon: int, every: int, log=None):
     solver steps from the initial field after which the state is as close to the
     horizon state (normalised mean squared difference of density and temperature) as
     the state the solver would start from is (the network's prediction, guarded and put
-    back on the initial mass and energy); linear interpolation between samples every `every`
+    back on the initial mass); linear interpolation between samples every `every`
     steps.  Returns a summary with the per-problem values."""
     import torch
     r = Runner(specs)
@@ -389,10 +386,10 @@ def equal_error_steps(net, specs, horizon: int, every: int, log=None):
     prho, pT = net.predict_fields(rho0, T0f, r.rho_v, r.rho_l, r.T0, r.cond)
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
-    # score the state the solver would start from: guarded, with the initial mass and energy
+    # score the state the solver would start from: guarded, with the initial mass
     with torch.cuda.stream(r.stream):
         prho, pT = guard_prediction(prho, pT, r.rho_v, r.rho_l, r.T0)
-    prho, pT, _, _ = match_invariants(r, rho0, T0f, prho, pT)
+    prho, _ = match_mass(r, rho0, prho, pT)
     ek = dict(rho_v=r.rho_v, rho_l=r.rho_l, T0=r.T0, outputs=net.K)
     e_net = _mse_fields(prho, pT, rhoT, TT, **ek).cpu().numpy()
     r.set_fields(rho0)

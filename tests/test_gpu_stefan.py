@@ -2,8 +2,8 @@
 (20)-(21): heated wall with vapour outflow at x = 0, wall at rest at x = nx - 1, y
 periodic) on the GPU, through the C ABI, against oracle/stefan.py.
 
-Parity: FP64 within 1e-12 and FP32 within 1e-5 of the FP64 oracle (norms of
-parity_helpers), on the paper's 1024 x 4 domain with a vapour layer next to the heated
+Parity: FP64 within 1e-12 and FP32 within 1e-5 of the FP64 oracle after 1000 steps (norms
+of parity_helpers), on the paper's 1024 x 4 domain with a vapour layer next to the heated
 wall, and on a small moving two-phase field with an odd number of rows.  Boundary columns
 report the imposed boundary state on both sides.  Launch chunking and file checkpoints
 leave the state bitwise unchanged.
@@ -49,10 +49,10 @@ def _gpu(nx, ny, f, steps, params):
 def test_stefan_domain_matches_oracle(prec, tol):
     model = oracle_model("cs")
     d = model.d
-    say(f"case: {prec} bounded 1024x4 Stefan start (vapour layer 20 nodes), 400 steps")
+    say(f"case: {prec} bounded 1024x4 Stefan start (vapour layer 20 nodes), 1000 steps")
     f = stefan_fields(d)
-    o = _oracle(model, f, 400)
-    g, s = _gpu(1024, 4, f, 400, dict(WALL, precision=prec))
+    o = _oracle(model, f, 1000)
+    g, s = _gpu(1024, 4, f, 1000, dict(WALL, precision=prec))
     assert s.invariants()["bad_nodes"] == 0
     assert_close(g, o, d, tol, f"{prec} stefan 1024x4")
 
@@ -64,10 +64,10 @@ def test_moving_two_phase_field_between_walls_matches_oracle(prec, tol):
     temperature of both walls, the y wrap) with motion through the boundary columns."""
     model = oracle_model("cs")
     d = model.d
-    say(f"case: {prec} bounded 37x5 moving two-phase field, 200 steps")
+    say(f"case: {prec} bounded 37x5 moving two-phase field, 1000 steps")
     f = inputs.random_smooth(37, 5, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.6, 0.05 * d.cs, 0.03, seed=41)
-    o = _oracle(model, f, 200, Tr_wall=0.85, Tr_far=0.82)
-    g, s = _gpu(37, 5, f, 200, dict(WALL, Tr_far=0.82, precision=prec))
+    o = _oracle(model, f, 1000, Tr_wall=0.85, Tr_far=0.82)
+    g, s = _gpu(37, 5, f, 1000, dict(WALL, Tr_far=0.82, precision=prec))
     assert s.invariants()["bad_nodes"] == 0
     assert_close(g, o, d, tol, f"{prec} bounded 37x5")
 
