@@ -842,6 +842,31 @@ __device__ __forceinline__ bf16x8 tr_frag(const bf16_t (*T)[PITCH], int p0, int 
     return as_frag(u);
 }
 
+// The same fragment from a tile whose rows carry 32 extra elements after every 8 rows
+// (row r at r * PITCH + (r >> 3) * 32), with the 32 pixels of step p0 (a multiple of
+// 32) dealt as two rows of 16: lane group g takes pixels p0 + 16 (g & 1) + 8 (g >> 1)
+// .. + 7.  The gfx950 LDS has 64 four-byte banks and serves a 64-bit read 32 lanes at
+// a time; with this layout the two 16-lane groups of each half-wavefront fall on
+// disjoint banks for row pitches of 48, 80 and 272 elements, where the unpadded tile
+// with groups 8 rows apart puts them on the same banks (a 2-way conflict on every read).
+__device__ __forceinline__ int pad_row(int r, int pitch) { return r * pitch + (r >> 3) * 32; }
+__device__ __forceinline__ int frag_px(int p0, int g) { return p0 + 16 * (g & 1) + 8 * (g >> 1); }
+
+template <int PITCH>
+__device__ __forceinline__ bf16x8 tr_frag_pad(const bf16_t* T, int p0, int c0, int lane) {
+    const int g = lane >> 4, i = lane & 15;
+    const bf16_t* q = T + pad_row(frag_px(p0, g) + (i >> 2), PITCH) + c0 + 4 * (i & 3);
+    typedef __attribute__((address_space(3))) v4s lds_v4s;
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q));
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q + 4 * PITCH));  // same 8-row block
+    uint4 u;
+    u.x = (uint32_t)(uint16_t)lo[0] | ((uint32_t)(uint16_t)lo[1] << 16);
+    u.y = (uint32_t)(uint16_t)lo[2] | ((uint32_t)(uint16_t)lo[3] << 16);
+    u.z = (uint32_t)(uint16_t)hi[0] | ((uint32_t)(uint16_t)hi[1] << 16);
+    u.w = (uint32_t)(uint16_t)hi[2] | ((uint32_t)(uint16_t)hi[3] << 16);
+    return as_frag(u);
+}
+
 template <int BO, int BK, int PC, int WOW>
 __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
     constexpr int PO = BO + 16, PK = BK + 16;
@@ -852,8 +877,8 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
     static_assert(GV >= 1 && XV >= 1, "tile too small for the loader");
     static_assert(256 % GVR == 0 && 256 % XVR == 0 && PC % (256 / GVR) == 0 && PC % (256 / XVR) == 0,
                   "the loader steps rows by 256 / (vectors per row) and must tile the chunk exactly");
-    __shared__ __attribute__((aligned(16))) bf16_t Gs[2][PC][PO];
-    __shared__ __attribute__((aligned(16))) bf16_t Xs[2][PC][PK];
+    __shared__ __attribute__((aligned(16))) bf16_t Gs[2][PC * PO + PC / 8 * 32];  // rows as pad_row
+    __shared__ __attribute__((aligned(16))) bf16_t Xs[2][PC * PK + PC / 8 * 32];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     // flat grid: the k and channel tiles of one pixel slab are adjacent
     const int L = xcd_block(blockIdx.x, gridDim.x);
@@ -897,9 +922,11 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int j = 0; j < GV; ++j) *reinterpret_cast<uint4*>(&Gs[buf][grow + j * (256 / GVR)][gcol]) = gv[j];
+        for (int j = 0; j < GV; ++j)
+            *reinterpret_cast<uint4*>(&Gs[buf][pad_row(grow + j * (256 / GVR), PO) + gcol]) = gv[j];
 #pragma unroll
-        for (int j = 0; j < XV; ++j) *reinterpret_cast<uint4*>(&Xs[buf][xrow + j * (256 / XVR)][xcol]) = xv[j];
+        for (int j = 0; j < XV; ++j)
+            *reinterpret_cast<uint4*>(&Xs[buf][pad_row(xrow + j * (256 / XVR), PK) + xcol]) = xv[j];
     };
     f32x4 acc[MT][NT];
 #pragma unroll
@@ -918,9 +945,9 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
         for (int ks = 0; ks < PC; ks += 32) {
             bf16x8 A[MT], B[NT];
 #pragma unroll
-            for (int m = 0; m < MT; ++m) A[m] = tr_frag<PO>(Gs[buf], ks, wo + 16 * m, lane);
+            for (int m = 0; m < MT; ++m) A[m] = tr_frag_pad<PO>(Gs[buf], ks, wo + 16 * m, lane);
 #pragma unroll
-            for (int n = 0; n < NT; ++n) B[n] = tr_frag<PK>(Xs[buf], ks, wk + 16 * n, lane);
+            for (int n = 0; n < NT; ++n) B[n] = tr_frag_pad<PK>(Xs[buf], ks, wk + 16 * n, lane);
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -951,21 +978,27 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
 // of all nine taps out of LDS: for 8 consecutive pixels of a tile row the tap-shifted
 // halo pixels are consecutive rows, so the transposing read (as in k_wgrad_tr) yields
 // the MFMA fragment directly.  Each input value is therefore read once per output
-// tile, where the im2col form reads it once per tap.  Row pitches OC + 16 (g) and 48
-// (halo) elements keep the 4 rows of one read on distinct bank groups.  The 18 column
-// blocks (9 taps x 2 halves of the 32 input channels) are dealt to the four
-// wavefronts round robin, each for all OC / 16 output blocks, so a halo fragment
+// tile, where the im2col form reads it once per tap.  LDS layout (bank conflicts): the
+// g tile as in tr_frag_pad, and halo pixels at a pitch of 48 elements plus 96 after
+// every halo row of 18, so that the eight 32-byte row pieces of every half-wavefront
+// read fall on distinct banks for every tap, input-channel half and reduction step.
+// The 18 column blocks (9 taps x 2 halves of the 32 input channels) are dealt to the
+// four wavefronts round robin, each for all OC / 16 output blocks, so a halo fragment
 // feeds OC / 16 MFMAs.  The next tile's loads are held in registers while the current
 // tile's MFMAs run.  The bias gradient is summed per thread (FP32) over the g values
 // it loads and combined in a fixed order.  The partial sums per slab go to the same
 // [slab][C_out][Kt] layout as the other forms.
-constexpr int kWgPitch = 48;
+constexpr int kWgPitch = 48;                  // elements per halo pixel
+constexpr int kWgHaloRow = 18 * kWgPitch + 96;  // elements per halo row of 18 pixels
+
+// LDS element offset of halo pixel (hr, hc); g-tile pixel q (row-major 16 wide) sits at
+// pad_row(q, GP), and reduction step ks covers pixels 32 ks .. + 31 dealt as frag_px
+__device__ __forceinline__ int hs_at(int hr, int hc) { return hr * kWgHaloRow + hc * kWgPitch; }
 
 __device__ __forceinline__ bf16x8 halo_frag(const bf16_t* Hs, int ks, int dy, int dx, int c0, int lane) {
     const int g = lane >> 4, i = lane & 15;
-    const int px0 = ks * 32 + 8 * g;  // 8 consecutive tile pixels within one tile row
-    const int hb = ((px0 >> 4) + dy) * 18 + (px0 & 15) + dx;
-    const bf16_t* q = Hs + (hb + (i >> 2)) * kWgPitch + c0 + 4 * (i & 3);
+    const int px0 = frag_px(ks * 32, g);  // 8 consecutive tile pixels within one tile row
+    const bf16_t* q = Hs + hs_at((px0 >> 4) + dy, (px0 & 15) + dx + (i >> 2)) + c0 + 4 * (i & 3);
     typedef __attribute__((address_space(3))) v4s lds_v4s;
     const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q));
     const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(q + 4 * kWgPitch));
@@ -980,12 +1013,12 @@ __device__ __forceinline__ bf16x8 halo_frag(const bf16_t* Hs, int ks, int dy, in
 template <int OC>
 __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
     constexpr int NCB = 5;  // column blocks per wavefront (18 over 4: 5, 5, 4, 4)
-    constexpr int GP = OC + 16;     // row pitch of the g tile (OC channels + 16: distinct bank groups)
+    constexpr int GP = OC + 16;     // row pitch of the g tile (rows at pad_row(q, GP))
     constexpr int PPR = OC / 8;     // 16-byte pieces per pixel of g
     constexpr int RP = 256 / PPR;   // g pixels loaded per pass of the workgroup
     constexpr int MH = OC / 16;     // 16-row output blocks
-    __shared__ __attribute__((aligned(16))) bf16_t Gs[256 * GP];
-    __shared__ __attribute__((aligned(16))) bf16_t Hs[kHalo * kWgPitch];
+    __shared__ __attribute__((aligned(16))) bf16_t Gs[256 * GP + 32 * 32];
+    __shared__ __attribute__((aligned(16))) bf16_t Hs[18 * kWgHaloRow];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     // flat grid: input-channel blocks, then output-channel blocks, then slabs
     const int L = xcd_block(blockIdx.x, gridDim.x);
@@ -1033,7 +1066,7 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
 #pragma unroll
         for (int i = 0; i < PPR; ++i) {
             const int q = t / PPR + RP * i;
-            *reinterpret_cast<uint4*>(&Gs[q * GP + 8 * gpiece]) = gv[i];
+            *reinterpret_cast<uint4*>(&Gs[pad_row(q, GP) + 8 * gpiece]) = gv[i];
             float f[8];
             unpack8(gv[i], f);
 #pragma unroll
@@ -1044,7 +1077,8 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
             const int v = t + 256 * i;
             if (v < kHalo * 4) {
                 const int h = v >> 2, piece = v & 3;
-                *reinterpret_cast<uint4*>(&Hs[h * kWgPitch + 8 * piece]) = hv[i];
+                const int hr = h / 18, hc = h - 18 * hr;
+                *reinterpret_cast<uint4*>(&Hs[hs_at(hr, hc) + 8 * piece]) = hv[i];
             }
         }
         __syncthreads();
@@ -1054,7 +1088,7 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
             bf16x8 A[MH];
 #pragma unroll
             for (int h = 0; h < MH; ++h)
-                A[h] = tr_frag<GP>(reinterpret_cast<const bf16_t(*)[GP]>(Gs), ks * 32, 16 * h, lane);
+                A[h] = tr_frag_pad<GP>(Gs, ks * 32, 16 * h, lane);
 #pragma unroll
             for (int i = 0; i < NCB; ++i) {
                 const int cb = wave + 4 * i;
