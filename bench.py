@@ -574,6 +574,31 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 10) -> int:
     return 0
 
 
+def hbm_probe(nbytes: int = 1 << 30, reps: int = 20) -> int:
+    """Reference HBM rates on this GPU with plain library kernels over nbytes: a copy
+    (nbytes read + nbytes written), a read-only reduction and a write-only fill, each
+    timed with events over reps launches after one untimed launch."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn, moved in (("copy", lambda: dst.copy_(src), 2 * nbytes),
+                            ("read", lambda: src.sum(), nbytes),
+                            ("write", lambda: dst.fill_(0.5), nbytes)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "TB_s": round(moved / (ms * 1e-3) / 1e12, 3)}
+    print(json.dumps({"hbm_probe_bytes": nbytes, "reps": reps, **out}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -616,11 +641,15 @@ def main() -> int:
     ap.add_argument("--columns-per-lane", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only time a plain 1 GiB copy, read-only reduction and write-only fill (reference HBM rates)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.hbm_probe:
+        return hbm_probe()
     if args.precision is None:
         args.precision = "f64" if args.workload == "stefan" else "f32"
     if args.gpus != 1:

@@ -326,6 +326,30 @@ def test_flat_interface_coexistence_matches_maxwell(model, profile_table):
     assert np.abs(uy).max() < 1e-5 * model.d.cs
 
 
+@pytest.mark.slow
+def test_flat_interface_coexistence_matches_maxwell_vdw():
+    """P11 for the van der Waals workload's EOS (a = 9/49, b = 2/21, R = 1, K_EOS = 1, the
+    paper's K_INT, T/Tc 0.8): the flat slab equilibrates to the Maxwell densities of that
+    EOS at its own bulk temperature within 1e-3, and its 5%-95% width to the flat
+    square-gradient width of that EOS (9.708 nodes) within 1 %."""
+    model = lbm.Model.build(thermo.vdw_eos(), thermo.Params())
+    d = model.d
+    table = thermo.flat_profile_table(model.eos, d.T0, d.kappa, 120)
+    rho, ux, uy, T = _slab_run(model, table)
+    ny = rho.shape[0]
+    rl, rv = rho[ny // 2, 0], rho[0, 0]
+    Tb = 0.5 * (T[ny // 2, 0] + T[0, 0])
+    mv, ml, _ = thermo.maxwell(model.eos, Tb)
+    assert abs(rl / float(ml) - 1) < 1e-3
+    assert abs(rv / float(mv) - 1) < 1e-3
+    half = rho[: ny // 2 + 1, 0]
+    ys = np.arange(len(half))
+    W = np.interp(rv + 0.95 * (rl - rv), half, ys) - np.interp(rv + 0.05 * (rl - rv), half, ys)
+    Wref = float(thermo.interface_width(model.eos, Tb, d.kappa))
+    assert abs(W / Wref - 1) < 0.01
+    assert np.abs(uy).max() < 1e-5 * d.cs
+
+
 # --- mutation checks: plant mistakes in the oracle and show a pin catches each ---------------
 
 def test_mutation_sign_in_S_breaks_equivariance(model, monkeypatch):
