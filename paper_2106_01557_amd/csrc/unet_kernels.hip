@@ -452,10 +452,15 @@ __device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&a
 // 4 x 16-byte pieces swizzled as in k_conv_lds (the 16 lanes of a fragment read 16
 // consecutive halo pixels); the bf16 epilogue is the same.  Accumulation order: per
 // output, channel block outer, taps inner.
+//
+// kOne: the layer has one channel block (C_in = 32).  Then there is no next block to
+// prefetch, the loads' registers are free once the tile is in LDS, and the kernel asks
+// for three wavefronts per SIMD (three workgroups per CU), so that more tiles' loads are
+// in flight while others compute; the arithmetic is the same.
 constexpr int kHalo = 18 * 18;
 
-template <bool kF32>
-__global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
+template <bool kF32, bool kOne>
+__global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs a) {
     constexpr int BM = 256, BN = 32, WTM = 64, MT = 4, NT = 2;
     constexpr int OP = BN + 8;
     static_assert(BM * OP <= kHalo * 32, "output tile fits the halo buffer");
@@ -524,7 +529,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(const ConvArgs a) {
     if (c0 > 0) __syncthreads();  // the previous channel block's fragments have been read
     lstore();
     __syncthreads();
-    if (c0 + 32 < a.Cin) gload(c0 + 32);
+    if (!kOne && c0 + 32 < a.Cin) gload(c0 + 32);
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - 3 * (tap / 3);  // offsets into the halo (0..2)
         uint4 A[MT], B[NT];
@@ -1704,8 +1709,13 @@ bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
     // 16 x 16 pixel tiles: H and W multiples of 16
     if (a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
         const dim3 grid((a.P / 256) * (a.Cout / 32));
-        if (f32) hipLaunchKernelGGL((k_conv_halo<true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_conv_halo<false>), grid, dim3(256), 0, s, a);
+        if (a.Cin == 32) {
+            if (f32) hipLaunchKernelGGL((k_conv_halo<true, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv_halo<false, true>), grid, dim3(256), 0, s, a);
+        } else {
+            if (f32) hipLaunchKernelGGL((k_conv_halo<true, false>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv_halo<false, false>), grid, dim3(256), 0, s, a);
+        }
         return true;
     }
     if (a.Cout % 128 == 0 && a.P % 128 == 0) {
