@@ -459,11 +459,18 @@ __device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&a
 // in flight while others compute; the arithmetic is the same.
 constexpr int kHalo = 18 * 18;
 
-template <bool kF32, bool kOne>
+//
+// BN = 64 (C_out a multiple of 64, several channel blocks): a workgroup owns 64 output
+// channels, so each staged halo byte feeds twice the MFMAs (166 instead of 120 FLOP per
+// byte staged in LDS); 57 KB of LDS, still two workgroups per CU.  The bfloat16 output
+// tile is staged in the weight buffer, whose 9 x 64 x 32 elements are exactly 256 rows
+// of 72.
+template <bool kF32, bool kOne, int BN>
 __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs a) {
-    constexpr int BM = 256, BN = 32, WTM = 64, MT = 4, NT = 2;
+    constexpr int BM = 256, WTM = 64, MT = 4, NT = BN / 16;
     constexpr int OP = BN + 8;
-    static_assert(BM * OP <= kHalo * 32, "output tile fits the halo buffer");
+    static_assert(BN == 32 || BN == 64, "32 or 64 output channels per workgroup");
+    static_assert(BM * OP <= (BN == 32 ? kHalo * 32 : 9 * BN * 32), "output tile fits its staging buffer");
     __shared__ __attribute__((aligned(16))) bf16_t Ah[kHalo * 32];
     __shared__ __attribute__((aligned(16))) bf16_t Bh[9 * BN * 32];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -572,8 +579,8 @@ __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs 
             }
         }
     } else {
-        __syncthreads();  // every wavefront is done with the halo tile
-        bf16_t* Os = Ah;
+        __syncthreads();  // every wavefront is done with the halo and weight tiles
+        bf16_t* Os = BN == 32 ? Ah : Bh;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
             const int c = 16 * n + r16;
@@ -1710,11 +1717,15 @@ bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
     if (a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
         const dim3 grid((a.P / 256) * (a.Cout / 32));
         if (a.Cin == 32) {
-            if (f32) hipLaunchKernelGGL((k_conv_halo<true, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_conv_halo<false, true>), grid, dim3(256), 0, s, a);
+            if (f32) hipLaunchKernelGGL((k_conv_halo<true, true, 32>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv_halo<false, true, 32>), grid, dim3(256), 0, s, a);
+        } else if (a.Cout % 64 == 0) {
+            const dim3 grid64((a.P / 256) * (a.Cout / 64));
+            if (f32) hipLaunchKernelGGL((k_conv_halo<true, false, 64>), grid64, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv_halo<false, false, 64>), grid64, dim3(256), 0, s, a);
         } else {
-            if (f32) hipLaunchKernelGGL((k_conv_halo<true, false>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_conv_halo<false, false>), grid, dim3(256), 0, s, a);
+            if (f32) hipLaunchKernelGGL((k_conv_halo<true, false, 32>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv_halo<false, false, 32>), grid, dim3(256), 0, s, a);
         }
         return true;
     }

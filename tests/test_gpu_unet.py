@@ -94,28 +94,30 @@ def test_conv3x3_forward_fp32_output(case):
     assert (err <= bound + 1e-30).all(), float((err / (bound + 1e-30)).max())
 
 
-def test_conv3x3_relu_mask_bf16_and_strided_output():
-    """ReLU and a mask in the epilogue, bfloat16 output written into channels 16..47 of a
-    64-channel buffer whose other channels must stay untouched."""
+@pytest.mark.parametrize("N,H,W,ci,co", [(2, 8, 16, 32, 32), (1, 16, 16, 64, 64)], ids=["32to32", "64to64"])
+def test_conv3x3_relu_mask_bf16_and_strided_output(N, H, W, ci, co):
+    """ReLU and a mask in the epilogue, bfloat16 output written into channels 16 .. 16 +
+    C_out - 1 of a buffer whose other channels must stay untouched (one 32-channel block
+    with 32 outputs per workgroup; two blocks with 64 outputs per workgroup)."""
     import torch
-    say("case: conv3x3 relu + mask + strided bf16 output")
+    say(f"case: conv3x3 relu + mask + strided bf16 output, {ci} -> {co}")
     u = lib()
-    N, H, W, ci, co = 2, 8, 16, 32, 32
-    x = bf((N, H, W, 48), 4)      # input read from channels 8..39 of a 48-channel tensor
+    ld_in, ld_out = ci + 16, co + 32
+    x = bf((N, H, W, ld_in), 4)      # input read from channels 8 .. 8 + C_in - 1
     w, b = bf((co, 3, 3, ci), 5, 0.3), bf(co, 6)
     m = bf((N, H, W, co), 7)
-    ref = U.conv3x3(x[..., 8:40], w, b)
+    ref = U.conv3x3(x[..., 8:8 + ci], w, b)
     ref = np.where(m > 0, np.maximum(ref, 0), 0.0)
-    y = torch.full((N, H, W, 64), 7.0, dtype=torch.bfloat16, device="cuda")
+    y = torch.full((N, H, W, ld_out), 7.0, dtype=torch.bfloat16, device="cuda")
     xd, wd, bd, md = dev_bf16(x), dev_bf16(w), dev_f32(b), dev_bf16(m)
-    ck(u.library().unet_conv3x3_fwd(u.ptr(xd), 48, 8, u.ptr(wd), u.ptr(bd), u.ptr(y), 64, 16, u.ptr(md), co, 0, N, H,
-                                    W, ci, co, u.RELU, None))
+    ck(u.library().unet_conv3x3_fwd(u.ptr(xd), ld_in, 8, u.ptr(wd), u.ptr(bd), u.ptr(y), ld_out, 16, u.ptr(md), co, 0,
+                                    N, H, W, ci, co, u.RELU, None))
     got = host(y)
-    assert (got[..., :16] == 7.0).all() and (got[..., 48:] == 7.0).all()
+    assert (got[..., :16] == 7.0).all() and (got[..., 16 + co:] == 7.0).all()
     want = U.bf16_round(ref)
     step = np.abs(want) * 2.0 ** -7 + 1e-30
-    assert (np.abs(got[..., 16:48] - want) <= step).all()
-    assert (got[..., 16:48][ref == 0] == 0).all()
+    assert (np.abs(got[..., 16:16 + co] - want) <= step).all()
+    assert (got[..., 16:16 + co][ref == 0] == 0).all()
 
 
 @pytest.mark.parametrize("case", [(2, 8, 16, 32, 32), (1, 16, 16, 96, 32), (2, 8, 8, 64, 128), (2, 16, 16, 64, 128)],
