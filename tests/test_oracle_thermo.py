@@ -108,10 +108,14 @@ def test_time_step_reproduces_fig1_snapshot_times(golden):
 
 
 def test_stefan_root_small_ste_limit():
-    """For Ste -> 0, Eq. (21) gives k ~ sqrt(Ste / 2) (erf k ~ 2k/sqrt(pi), exp k^2 ~ 1)."""
-    for ste in (1e-4, 0.005):
+    """For Ste -> 0, Eq. (21) gives k ~ sqrt(Ste / 2) (erf k ~ 2k/sqrt(pi), exp k^2 ~ 1).
+    One order further, sqrt(pi) k exp(k^2) erf(k) = 2k^2 + (4/3) k^4 + O(k^6), so
+    k = sqrt(Ste / 2) (1 - Ste / 6) + O(Ste^(5/2)); the root found must agree to that
+    order at every small Ste (measured remainder 0.064 Ste^2 relative)."""
+    for ste in (1e-4, 1e-3, 0.005, 0.02):
         k = thermo.stefan_root(ste)
         assert abs(k / (ste / 2) ** 0.5 - 1) < 2 * ste
+        assert abs(k / ((ste / 2) ** 0.5 * (1 - ste / 6)) - 1) < 0.1 * ste ** 2
     assert thermo.stefan_root(0.05) > thermo.stefan_root(0.005)
 
 
