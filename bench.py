@@ -40,9 +40,14 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2106_01557_amd", "csrc", n) for n in ("
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
-def kernel_sha() -> str:
+# the bounded-domain kernel's source (the Stefan workload)
+BOUNDED_SRCS = [os.path.join(ROOT, "paper_2106_01557_amd", "csrc", n) for n in ("lbm_bounded.hip", "lbm_model.hpp")]
+PEAK_FP64_CU_GFLOPS = 78.6e3 / 256  # one CU's share of the FP64 vector peak (78.6 TFLOP/s over 256 CUs)
+
+
+def kernel_sha(srcs=None) -> str:
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for path in (KERNEL_SRCS if srcs is None else srcs):
         with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -65,6 +70,25 @@ def measured_traffic(tag: str, shape: tuple):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_flops(tag: str, srcs) -> float | None:
+    """Executed FP64 FLOPs per step from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"flops_{tag}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_sha(srcs):
+        return None
+    try:
+        return float(kv["flops_per_step"])
     except (KeyError, ValueError):
         return None
 
@@ -515,12 +539,18 @@ def run_stefan(args) -> dict:
                                "CS EOS with the paper's K_EOS/K_INT", "nx": nx, "ny": ny},
         "roofline": None,
         "roofline_note": ("one workgroup advances the whole domain (up to 8192 nodes) for thousands of steps per "
-                          "launch, with two workgroup barriers per step; at this size the step is set by the "
-                          "arithmetic of one CU and the barrier latency, not by any chip-wide peak"),
+                          "launch, with two workgroup barriers per step, so the peak is one CU's share of the "
+                          "FP64 vector peak; executed FP64 FLOPs per step come from a committed counter summary"),
         "kernel_ms_per_step": round(ms, 6),
         "checks": {"mass_out_of_domain_per_step": (inv1["mass"] - inv0["mass"]) / inv0["mass"] / max(1, args.steps + args.warmup),
                    "bad_nodes": inv1["bad_nodes"]},
     }
+    flops = measured_flops(f"step_bounded_{args.precision}_{nx}x{ny}", BOUNDED_SRCS) if args.precision == "f64" else None
+    if flops is not None:
+        achieved = flops / (ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_FP64_CU_GFLOPS, 2),
+                           "unit": "GFLOP/s", "frac": round(achieved / PEAK_FP64_CU_GFLOPS, 4), "traffic": None,
+                           "kernel": "k_step_bounded<double> (one workgroup)", "flops_per_step": flops}
     if args.stefan_physics > 0:
         ste = 0.005
         k = neumann_k(ste)

@@ -34,3 +34,16 @@ def test_committed_traffic_summaries_match_the_kernel_source_and_default_shapes(
         kv = dict(line.strip().split("=", 1) for line in fh if "=" in line and not line.startswith("#"))
     assert kv["kernel_source_sha"] == bench.kernel_sha()
     assert kv["launch_shape"].endswith("q0")  # grid mode, as the autotuner picked it
+
+
+def test_committed_flop_summary_matches_the_bounded_kernel_source():
+    """The Stefan workload's ALU roofline uses executed FP64 FLOPs per step from a committed
+    rocprofv3 counter summary taken on the current bounded-kernel source: about 500 FP64
+    operations per node of the 1024-node lattice (the pointwise model of the periodic
+    update plus the boundary extrapolation)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    fl = bench.measured_flops("step_bounded_f64_1024x1", bench.BOUNDED_SRCS)
+    assert fl is not None
+    assert 300 * 1024 < fl < 800 * 1024
+    assert abs(bench.PEAK_FP64_CU_GFLOPS - 307.03) < 0.01
