@@ -72,6 +72,20 @@ def test_moving_two_phase_field_between_walls_matches_oracle(prec, tol):
     assert_close(g, o, d, tol, f"{prec} bounded 37x5")
 
 
+def test_largest_bounded_lattice_matches_oracle():
+    """The largest lattice the bounded update takes, 8192 nodes (512 x 16: eight nodes per
+    thread of its one workgroup), a moving two-phase field between the walls, FP64 within
+    1e-12 of the oracle after 200 steps."""
+    model = oracle_model("cs")
+    d = model.d
+    say("case: f64 bounded 512x16 (8192 nodes, the maximum) moving two-phase field, 200 steps")
+    f = inputs.random_smooth(512, 16, 0.5 * (d.rho_l + d.rho_v), d.T0, 0.6, 0.05 * d.cs, 0.03, seed=43)
+    o = _oracle(model, f, 200, Tr_wall=0.85, Tr_far=0.82)
+    g, s = _gpu(512, 16, f, 200, dict(WALL, Tr_far=0.82, precision="f64"))
+    assert s.invariants()["bad_nodes"] == 0
+    assert_close(g, o, d, 1e-12, "f64 bounded 512x16")
+
+
 def test_bounded_stepping_is_chunk_and_restart_invariant(tmp_path):
     say("case: bounded 1024x4 FP32, 5000 steps at once vs in pieces vs through a checkpoint file")
     model = oracle_model("cs")
