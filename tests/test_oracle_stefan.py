@@ -12,8 +12,12 @@ one-dimensional Stefan problem, Eqs. (20)-(21)), against what the physics fixes:
 The boundary rule itself stands in for a scheme the paper cites without stating it; the
 comparison that fixes the whole bounded update against the paper is the interface
 position against the Neumann solution, a long run made on the GPU
-(test_gpu_stefan.py).  Parity unpinned beyond these checks: the boundary populations'
-non-equilibrium part (a plain equilibrium boundary also passes the conduction check).
+(test_gpu_stefan.py).
+* the boundary populations' non-equilibrium part, which steady conduction does not see
+  (a plain equilibrium boundary also passes it), carries the wall's shear stress: a
+  tangential shear mode between the no-slip far wall and the free-slip outflow side
+  decays at the viscous rate, with second-order convergence in the channel width; a
+  mutation test drops that part and shows the pin fail.
 """
 import mpmath as mp
 import numpy as np
@@ -100,3 +104,65 @@ def test_interface_position_interpolates_the_mid_density():
     row = np.array([0.02, 0.02, 0.05, 0.2, 0.3, 0.3])
     X = stefan.interface_position(row, 0.02, 0.3)
     assert X == pytest.approx(2 + (0.16 - 0.05) / 0.15)
+
+
+def _shear_decay_ratio(model, nx, steps):
+    """Decay rate of the lowest tangential shear mode in uniform vapour between the two
+    boundary columns (both at T0, outflow at p_s), over the viscous rate nu k^2.  The far
+    wall imposes u = 0 at its node (x = nx - 1); the outflow side copies the velocity of
+    column 1 (zero gradient midway, x = 1/2).  So the mode is U cos(k (x - 1/2)) with
+    k = pi / (2 L), L = nx - 3/2, and nu = c_s^2 dt (1/s_p - 1/2) is the shear viscosity
+    of the momentum rows' relaxation."""
+    d = model.d
+    w = stefan.walls(model, float(d.T0 / d.Tc), float(d.T0 / d.Tc))
+    x = np.arange(nx, dtype=float)
+    L = (nx - 1) - 0.5
+    shape = np.cos(np.pi * (x - 0.5) / (2 * L))
+    rho, zero, T = np.full((1, nx), d.rho_v), np.zeros((1, nx)), np.full((1, nx), d.T0)
+    st = stefan.init_state(model, rho, zero, 1e-3 * d.cs * shape[None, :], T)
+    ts, amps = [], []
+    for n in range(0, steps + 1, steps // 10):
+        if n:
+            st = stefan.run(model, w, st, steps // 10)
+        vy = stefan.moments(model, w, st)[2][0, 1:-1]
+        amps.append((vy * shape[1:-1]).sum() / (shape[1:-1] ** 2).sum())
+        ts.append(n * d.dt)
+    rate = -np.polyfit(ts[2:], np.log(amps[2:]), 1)[0]
+    nu = d.cs ** 2 * d.dt * (1 / d.s_p - 0.5)
+    return rate / (nu * (np.pi / (2 * L)) ** 2)
+
+
+def check_wall_shear(model):
+    r18 = _shear_decay_ratio(model, 18, 1000)
+    r34 = _shear_decay_ratio(model, 34, 2000)
+    # measured 1.00089 and 1.00024: second order in 1/L
+    assert abs(r18 - 1) < 4e-3
+    assert abs(r18 - 1) / abs(r34 - 1) > 3
+
+
+def test_tangential_shear_decays_at_the_viscous_rate_between_the_walls(model):
+    """The boundary populations' non-equilibrium part carries the wall's shear stress:
+    the lowest shear mode between the no-slip far wall and the free-slip outflow side
+    decays at nu k^2 to 0.09 % on 16 fluid columns, and the error falls with the square
+    of the width (second-order walls)."""
+    check_wall_shear(model)
+
+
+def test_mutation_equilibrium_only_boundary_breaks_the_wall_shear(model, monkeypatch):
+    """Planted in the oracle: boundary populations set to the equilibrium at the boundary
+    state alone (the neighbour's non-equilibrium part dropped).  Steady conduction does
+    not see this, but the wall's shear stress is then wrong: the mode decays 1.5 % too
+    fast on 16 columns, and only first order in 1/L."""
+    def step_eq(m, w, st):
+        mac, full = stefan.macros(m, w, st)
+        fbar, gbar = lbm.collide(m, full, mac)
+        for col in (0, -1):
+            fe, ge = stefan._eq_pops(m, mac.rho[:, col], mac.ux[:, col], mac.uy[:, col], mac.T[:, col])
+            fbar[:, :, col], gbar[:, :, col] = fe, ge
+        f, g = lbm.stream(fbar), lbm.stream(gbar)
+        f[:, :, 0] = f[:, :, -1] = np.nan
+        g[:, :, 0] = g[:, :, -1] = np.nan
+        return lbm.State(f, g, st.step + 1)
+    monkeypatch.setattr(stefan, "step", step_eq)
+    with pytest.raises(AssertionError):
+        check_wall_shear(model)
