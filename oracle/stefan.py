@@ -31,13 +31,12 @@ left out: with Ste = 0.005 the flow is slow (|u| / c_s ~ 1e-3), where those term
 negligible.
 
 Pins (tests/test_oracle_stefan.py): the wall density, a uniform wall state staying
-steady, steady conduction (linear temperature, no flow), and the f populations'
+steady, steady conduction (linear temperature, no flow), the f populations'
 non-equilibrium part through the viscous decay of a shear mode between the walls
-(second order in the width; dropping that part fails it).  Parity unpinned: the g
-populations' non-equilibrium part (the wall heat flux) has no CPU pin of its own; a
-transient temperature mode between the walls is not an exact reference (its decay
-couples to expansion and sound), and steady conduction does not see it.  The whole
-bounded update is compared with the Neumann solution of Eq. (20) on the GPU.
+(second order in the width), and the g populations' non-equilibrium part through the
+conduction profile's slope at the default vapour conductivity (no temperature jump at
+either wall).  Dropping either part fails its pin (mutation tests).  The whole bounded
+update is compared with the Neumann solution of Eq. (20) on the GPU.
 """
 from __future__ import annotations
 

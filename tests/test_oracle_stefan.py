@@ -13,11 +13,12 @@ The boundary rule itself stands in for a scheme the paper cites without stating 
 comparison that fixes the whole bounded update against the paper is the interface
 position against the Neumann solution, a long run made on the GPU
 (test_gpu_stefan.py).
-* the boundary populations' non-equilibrium part, which steady conduction does not see
-  (a plain equilibrium boundary also passes it), carries the wall's shear stress: a
-  tangential shear mode between the no-slip far wall and the free-slip outflow side
-  decays at the viscous rate, with second-order convergence in the channel width; a
-  mutation test drops that part and shows the pin fail.
+* the boundary populations' non-equilibrium part carries the walls' shear stress (f)
+  and heat flux (g): a tangential shear mode between the no-slip far wall and the
+  free-slip outflow side decays at the viscous rate, with second-order convergence in
+  the channel width, and at the default vapour conductivity the conduction profile
+  through the fluid meets the wall temperatures (no jump); mutation tests drop each
+  part and show its pin fail.
 """
 import mpmath as mp
 import numpy as np
@@ -166,3 +167,46 @@ def test_mutation_equilibrium_only_boundary_breaks_the_wall_shear(model, monkeyp
     monkeypatch.setattr(stefan, "step", step_eq)
     with pytest.raises(AssertionError):
         check_wall_shear(model)
+
+
+def _conduction_slope_ratio(model, steps=3000, nx=32):
+    """Slope of the temperature through the fluid nodes over the wall-to-wall gradient,
+    from the isobaric linear state between the heated wall (T_r 0.85) and a wall at
+    T_r 0.81."""
+    w = stefan.walls(model, 0.85, Tr_far=0.81)
+    x = np.arange(nx, dtype=float)
+    lin = w.T_wall + (w.T_far - w.T_wall) * x / (nx - 1)
+    rho = _isobaric_vapour(model, w, lin)[None, :]
+    st = stefan.run(model, w, stefan.init_state(model, rho, 0 * rho, 0 * rho, lin[None, :]), steps)
+    T = stefan.moments(model, w, st)[3][0]
+    return np.polyfit(x[1:-1], T[1:-1], 1)[0] / ((w.T_far - w.T_wall) / (nx - 1))
+
+
+def test_conduction_slope_meets_the_wall_temperatures_at_the_default_conductivity(model):
+    """The boundary g populations' non-equilibrium part carries the heat flux through the
+    walls.  At the default tau_j,v = 0.1 (heat-flux rows relaxed at 1/0.6, so their
+    non-equilibrium part survives the collision) the conduction profile through the
+    fluid nodes has the wall-to-wall slope within 0.3 % (measured 0.05 %): no temperature
+    jump at either wall.  (At tau_j,v = 0.5 those rows relax to equilibrium in one step
+    and the boundary's g non-equilibrium part vanishes, so the test above cannot see it.)"""
+    assert abs(_conduction_slope_ratio(model) - 1) < 3e-3
+
+
+def test_mutation_equilibrium_g_at_the_boundary_breaks_the_conduction_slope(model, monkeypatch):
+    """Planted in the oracle: the boundary g populations set to the equilibrium alone (f
+    keeps its extrapolation).  The walls then show temperature jumps and the profile
+    through the fluid is 2.5 % too steep."""
+    def step_geq(m, w, st):
+        mac, full = stefan.macros(m, w, st)
+        fbar, gbar = lbm.collide(m, full, mac)
+        for col, nb in ((0, 1), (-1, -2)):
+            fe_b, ge_b = stefan._eq_pops(m, mac.rho[:, col], mac.ux[:, col], mac.uy[:, col], mac.T[:, col])
+            fe_n, _ = stefan._eq_pops(m, mac.rho[:, nb], mac.ux[:, nb], mac.uy[:, nb], mac.T[:, nb])
+            fbar[:, :, col] = fe_b + fbar[:, :, nb] - fe_n
+            gbar[:, :, col] = ge_b
+        f, g = lbm.stream(fbar), lbm.stream(gbar)
+        f[:, :, 0] = f[:, :, -1] = np.nan
+        g[:, :, 0] = g[:, :, -1] = np.nan
+        return lbm.State(f, g, st.step + 1)
+    monkeypatch.setattr(stefan, "step", step_geq)
+    assert abs(_conduction_slope_ratio(model) - 1) > 3e-3
