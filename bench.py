@@ -54,24 +54,24 @@ def kernel_sha(srcs=None) -> str:
 
 
 def measured_traffic(tag: str, shape: tuple):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was taken on
-    the current kernel source in the same launch shape (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.txt")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if "=" in line and not line.lstrip().startswith("#"):
-            k, v = line.split("=", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha") != kernel_sha():
-        return None
-    if kv.get("launch_shape") != "x".join(str(v) for v in shape):
-        return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    """HBM bytes per launch from a committed rocprofv3 counter summary taken on the current
+    kernel source in the same launch shape (profiles/traffic_<tag>.txt, or one file per
+    shape, traffic_<tag>_<shape>.txt), else None."""
+    import glob
+    want = "x".join(str(v) for v in shape)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_{tag}*.txt"))):
+        kv = {}
+        for line in open(path):
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha") != kernel_sha() or kv.get("launch_shape") != want:
+            continue
+        try:
+            return float(kv["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            return None
+    return None
 
 
 def measured_flops(tag: str, srcs) -> float | None:

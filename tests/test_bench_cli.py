@@ -34,6 +34,13 @@ def test_committed_traffic_summaries_match_the_kernel_source_and_default_shapes(
         kv = dict(line.strip().split("=", 1) for line in fh if "=" in line and not line.startswith("#"))
     assert kv["kernel_source_sha"] == bench.kernel_sha()
     assert kv["launch_shape"].endswith("q0")  # grid mode, as the autotuner picked it
+    # the shapes the autotuner has picked between runs each have a summary of their own
+    alg_batch = 36 * 4 * 27_590_656
+    for rows, waves in ((4, 2), (4, 4), (4, 1), (8, 2)):
+        t = bench.measured_traffic("step_ab_batch_f32_batch64", (rows, f"{waves}q0"))
+        assert t is not None, (rows, waves)
+        assert 1.0 <= t / alg_batch < 1.1
+    assert bench.measured_traffic("step_ab_batch_f32_batch64", (2, "2q0")) is None
 
 
 def test_committed_flop_summary_matches_the_bounded_kernel_source():
