@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense bf16 MFMA
 # the fused kernel's source: its own file and the pointwise model pieces it includes
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2106_01557_amd", "csrc", n) for n in ("lbm_kernels.hip", "lbm_model.hpp")]
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
@@ -347,6 +348,41 @@ def unet_step_flops(widths, in_channels, N, H, W) -> float:
     return tot
 
 
+def unet_step_bound_ms(widths, in_channels, N, H, W, outputs=2) -> float:
+    """Lower bound on one training step's time, pass by pass: each pass takes at least
+    the longer of its dense FLOPs at the bf16 MFMA peak and its compulsory HBM bytes
+    (bfloat16 activations and gradients read and written once) at the HBM peak.  The
+    convolutions' weights and partial sums, and launch gaps, are left out."""
+    from paper_2106_01557_amd import unet
+    peak_f, peak_b = PEAK_BF16_TFLOPS * 1e12, PEAK_HBM_GBS * 1e9
+    t = 0.0
+    for name, ci, co in unet.conv_layers(widths, in_channels):
+        lvl = int(name[1])
+        P = N * (H >> lvl) * (W >> lvl)
+        fl = 2.0 * P * 9 * ci * co
+        io = 2.0 * P * (ci + co)
+        t += max(fl / peak_f, io / peak_b)                       # forward
+        if name != "e0a":                                          # input gradient (the
+            mask = 2.0 * P * ci if name.endswith("b") else 0.0    # b layers' ReLU mask)
+            t += max(fl / peak_f, (io + mask) / peak_b)
+        t += max(fl / peak_f, io / peak_b)                       # weight gradient
+    bw = 0.0
+    for lvl in range(len(widths) - 1):
+        c, cu = widths[lvl], widths[lvl + 1]
+        P = N * (H >> lvl) * (W >> lvl)
+        bw += 2.0 * (P * c + P // 4 * c)                 # max pool forward
+        bw += 2.0 * (3 * P * c + P // 4 * c)             # max pool backward (x, skip gradient, dx; dy)
+        bw += 2.0 * (P // 4 * cu + P * cu)               # upsample forward
+        bw += 2.0 * (P * cu + 2 * (P // 4) * cu)         # upsample backward (gradient, gate; dx)
+    P0, c0 = N * H * W, widths[0]
+    bw += 2 * (8.0 * P0 * 2 + 2.0 * P0 * in_channels + 4.0 * P0 * 2)   # inputs and targets prepared
+    bw += 2.0 * P0 * c0 + 4.0 * P0 * 2 * 2 + 4.0 * P0 * outputs * 2   # head forward and loss
+    bw += 2.0 * P0 * c0 * 2 + 4.0 * P0 * outputs                        # head backward
+    nparam = sum(9 * ci * co + co for _, ci, co in unet.conv_layers(widths, in_channels))
+    bw += nparam * (4 * 4 + 3 * 4 + 2 + 2 * 2)           # Adam (p, g, m, v in; p, m, v, bf16 out) and flips
+    return (t + bw / peak_b) * 1e3
+
+
 def run_warmstart(args) -> dict:
     """Learned warm start on 256 x 256 problems: generation of training data by the
     batched solver, training of the U-Net on the matrix cores, held-out loss against the
@@ -419,8 +455,8 @@ def run_warmstart(args) -> dict:
                         f"{args.horizon} steps; U-Net widths {list(net.widths)}, batch {B}, {args.epochs} epochs",
             "batch": B, "epochs": args.epochs,
         },
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": round(achieved / 2500.0, 4), "traffic": None,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
                      "kernel": "one training step (all 3x3 convolution kernels, dense FLOPs)",
                      "flops_per_step": flops},
         "data_generation": {"runs": len(specs), "non_finite_runs": len(failed),
@@ -446,7 +482,7 @@ def run_unet_step(args) -> dict:
     specs = ws.sample_specs(args.batch, seed=3, side=256)
     run = ws.Runner(specs)
     rho0, T0f = run.initial_density(), run.uniform_T()
-    net = unet.UNet(seed=0, stream=torch.cuda.current_stream())
+    net = unet.UNet(seed=0, stream=torch.cuda.current_stream(), overlap_wgrad=not args.unet_serial)
     a = [rho0, T0f, rho0, T0f, run.rho_v, run.rho_l, run.T0, run.cond]
     for _ in range(args.warmup):
         net.train_step(*a, lr=args.lr)
@@ -461,6 +497,7 @@ def run_unet_step(args) -> dict:
     run.close()
     flops = unet_step_flops(net.widths, net.in_channels, args.batch, 256, 256)
     achieved = flops / (step_ms * 1e-3) / 1e12
+    bound = unet_step_bound_ms(net.widths, net.in_channels, args.batch, 256, 256, net.K)
     return {
         "metric": "U-Net training samples/s (256x256, fwd+bwd+Adam)",
         "value": round(args.batch / (step_ms * 1e-3), 2), "unit": "samples/s",
@@ -468,11 +505,12 @@ def run_unet_step(args) -> dict:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 (FP32 accumulate, FP32 master weights)", "data": "synthetic",
         "config": {"workload": f"U-Net widths {list(net.widths)} on {args.batch} seeded 256x256 droplet problems",
-                   "batch": args.batch},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": round(achieved / 2500.0, 4), "traffic": None,
+                   "batch": args.batch, "weight_gradients_on_second_stream": net.overlap_wgrad},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
                      "kernel": "one training step (all 3x3 convolution kernels, dense FLOPs)",
-                     "flops_per_step": flops},
+                     "flops_per_step": flops,
+                     "step_bound_ms": round(bound, 4), "frac_of_step_bound": round(bound / step_ms, 4)},
     }
 
 
@@ -670,6 +708,8 @@ def main() -> int:
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--columns-per-lane", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unet-serial", action="store_true",
+                    help="unet_step: run the weight gradients on the main stream, after each input gradient's inputs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--hbm-probe", action="store_true",
                     help="only time a plain 1 GiB copy, read-only reduction and write-only fill (reference HBM rates)")

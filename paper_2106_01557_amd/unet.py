@@ -98,7 +98,7 @@ class UNet:
     gradient) and per-batch-shape activation buffers on one device."""
 
     def __init__(self, widths=(32, 64, 128, 256), in_channels=8, outputs=2, theta_scale=0.1, seed=0, device=None,
-                 stream=None):
+                 stream=None, overlap_wgrad=True):
         import torch
         self.torch = torch
         self.widths = tuple(int(w) for w in widths)
@@ -111,6 +111,11 @@ class UNet:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.s = ctypes.c_void_p(self.stream.cuda_stream)
+        # weight gradients (and their reductions) run on a second stream beside the input
+        # gradients: the two only read the same activations and output gradients
+        self.overlap_wgrad = bool(overlap_wgrad)
+        self.wstream = torch.cuda.Stream(self.device) if self.overlap_wgrad else self.stream
+        self.ws = ctypes.c_void_p(self.wstream.cuda_stream)
         self.t = 0
         rng = np.random.Generator(np.random.PCG64(seed))
         p = {}
@@ -283,8 +288,12 @@ class UNet:
 
         def wgrad(name, x, ldx, offx, gy, ldg, h, w):
             ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
+            if self.overlap_wgrad:
+                # gy (and every earlier write) is complete on the main stream before the
+                # weight-gradient stream reads it
+                self.wstream.wait_stream(self.stream)
             _ck(_lib.unet_conv3x3_wgrad(ptr(x), ldx, offx, ptr(gy), ldg, 0, ptr(g[name + ".w"]), ptr(g[name + ".b"]),
-                                        ptr(wp), nwp, N, h, w, ci, co, self.s))
+                                        ptr(wp), nwp, N, h, w, ci, co, self.ws))
 
         def dgrad(name, gy, ldg, dx, lddx, h, w, mask=None, ldm=0, offm=0):
             ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
@@ -328,6 +337,10 @@ class UNet:
                     dgrad(f"e{lvl}a", b[f"ge{lvl}a"], c, b[f"dpool{lvl - 1}"], cp, h, w)
                 else:
                     wgrad("e0a", b["x0"], self.in_channels, 0, b["ge0a"], c, h, w)
+            if self.overlap_wgrad:
+                # every weight gradient is in place before anything later on the main
+                # stream (the optimizer, the next step's passes) runs
+                self.stream.wait_stream(self.wstream)
         return g
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -472,6 +472,38 @@ def test_unet_end_to_end_against_reference(widths, hw, bars, exact_bars):
         assert _rel(gg, gref[k]) < grad_bar and _cos(gg, gref[k]) > cos_bar, (k, _rel(gg, gref[k]))
 
 
+def test_weight_gradients_on_a_second_stream_equal_one_stream():
+    """The weight gradients and their reductions run on a second stream beside the input
+    gradients.  Over three training steps (forward, backward, Adam) of the full network on
+    four 64 x 64 problems, every loss, gradient and updated parameter is bitwise the same
+    as with every kernel on one stream: the kernels' sums are in a fixed order, so any
+    difference would be a missing dependency between the streams."""
+    import torch
+    from paper_2106_01557_amd import unet
+    say("case: U-Net widths (32, 64, 128, 256), 4 x 64 x 64, overlapped against serial weight gradients")
+    N, hw = 4, 64
+    nets = [unet.UNet(widths=(32, 64, 128, 256), seed=5, overlap_wgrad=o) for o in (False, True)]
+    assert nets[1].wstream is not nets[1].stream and nets[0].wstream is nets[0].stream
+    rng = np.random.Generator(np.random.PCG64(8))
+    yy, xx = np.meshgrid(np.arange(hw), np.arange(hw), indexing="ij")
+    rho = np.stack([0.3 + 0.25 * np.tanh((12 + n - np.hypot(xx - 32, yy - 32)) / 2) for n in range(N)])
+    rho += 0.01 * rng.standard_normal(rho.shape)
+    T0 = np.array([0.07, 0.075, 0.08, 0.085])
+    Tf = T0[:, None, None] * (1 + 0.002 * rng.standard_normal(rho.shape))
+    tgt = rho + 0.02 * rng.standard_normal(rho.shape)
+    rv, rl, cond = np.full(N, 0.02), np.full(N, 0.55), np.linspace(-0.1, 0.1, N)
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64).cuda()  # noqa: E731
+    args = [T(a) for a in (rho, Tf, tgt, Tf, rv, rl, T0, cond)]
+    for step in range(3):
+        losses = [host(net.train_step(*args)).copy() for net in nets]
+        torch.cuda.synchronize()
+        assert np.array_equal(losses[0], losses[1]), (step, losses)
+        assert torch.equal(nets[0].gflat, nets[1].gflat), step
+        assert torch.equal(nets[0].flat, nets[1].flat), step
+        assert torch.equal(nets[0].w16flat, nets[1].w16flat), step
+    assert float(nets[1].gflat.abs().max()) > 0
+
+
 LARGE_CONV = [  # N, H, W, Cin, Cout: thousands of pixels, every LDS tile shape, XCD-ordered grids
     (2, 64, 64, 32, 32),     # halo-tile form (C_in = 32), four image rows per tile
     (1, 64, 64, 64, 64),
