@@ -482,7 +482,7 @@ def run_unet_step(args) -> dict:
     specs = ws.sample_specs(args.batch, seed=3, side=256)
     run = ws.Runner(specs)
     rho0, T0f = run.initial_density(), run.uniform_T()
-    net = unet.UNet(seed=0, stream=torch.cuda.current_stream(), overlap_wgrad=not args.unet_serial)
+    net = unet.UNet(seed=0, stream=torch.cuda.current_stream(), wgrad_streams=args.wgrad_streams)
     a = [rho0, T0f, rho0, T0f, run.rho_v, run.rho_l, run.T0, run.cond]
     for _ in range(args.warmup):
         net.train_step(*a, lr=args.lr)
@@ -505,7 +505,7 @@ def run_unet_step(args) -> dict:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 (FP32 accumulate, FP32 master weights)", "data": "synthetic",
         "config": {"workload": f"U-Net widths {list(net.widths)} on {args.batch} seeded 256x256 droplet problems",
-                   "batch": args.batch, "weight_gradients_on_second_stream": net.overlap_wgrad},
+                   "batch": args.batch, "weight_gradient_streams": net.wgrad_streams},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
                      "kernel": "one training step (all 3x3 convolution kernels, dense FLOPs)",
@@ -708,8 +708,8 @@ def main() -> int:
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--columns-per-lane", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--unet-serial", action="store_true",
-                    help="unet_step: run the weight gradients on the main stream, after each input gradient's inputs")
+    ap.add_argument("--wgrad-streams", type=int, default=2,
+                    help="unet_step: streams for the weight gradients beside the input gradients (0: one stream)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--hbm-probe", action="store_true",
                     help="only time a plain 1 GiB copy, read-only reduction and write-only fill (reference HBM rates)")

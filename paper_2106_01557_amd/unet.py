@@ -98,7 +98,7 @@ class UNet:
     gradient) and per-batch-shape activation buffers on one device."""
 
     def __init__(self, widths=(32, 64, 128, 256), in_channels=8, outputs=2, theta_scale=0.1, seed=0, device=None,
-                 stream=None, overlap_wgrad=True):
+                 stream=None, wgrad_streams=2):
         import torch
         self.torch = torch
         self.widths = tuple(int(w) for w in widths)
@@ -111,11 +111,14 @@ class UNet:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.s = ctypes.c_void_p(self.stream.cuda_stream)
-        # weight gradients (and their reductions) run on a second stream beside the input
-        # gradients: the two only read the same activations and output gradients
-        self.overlap_wgrad = bool(overlap_wgrad)
-        self.wstream = torch.cuda.Stream(self.device) if self.overlap_wgrad else self.stream
-        self.ws = ctypes.c_void_p(self.wstream.cuda_stream)
+        # weight gradients (and their reductions) run on wgrad_streams streams of their
+        # own, layer by layer in turn, beside the input gradients: a layer's two gradients
+        # only read the same activations and output gradient.  0: everything on `stream`.
+        if int(wgrad_streams) < 0:
+            raise UnetError("wgrad_streams must be >= 0")
+        self.wgrad_streams = int(wgrad_streams)
+        self.wstreams = [torch.cuda.Stream(self.device) for _ in range(self.wgrad_streams)] or [self.stream]
+        self.ws = [ctypes.c_void_p(st.cuda_stream) for st in self.wstreams]
         self.t = 0
         rng = np.random.Generator(np.random.PCG64(seed))
         p = {}
@@ -223,7 +226,8 @@ class UNet:
                 need = max(need, nb.value)
             nb = _S()
             _ck(_lib.unet_head_partial_bytes(N, H, W, self.widths[0], self.K, ctypes.byref(nb)))
-            b["wpart"] = torch.empty(need, dtype=torch.uint8, device=self.device)
+            # one partial-sum buffer per weight-gradient stream
+            b["wpart"] = [torch.empty(need, dtype=torch.uint8, device=self.device) for _ in self.wstreams]
             b["hpart"] = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
             b["loss"] = f32(1)
         self.buf = b
@@ -284,16 +288,19 @@ class UNet:
         torch = self.torch
         N, H, W = self._shape
         b, g, L, wd = self.buf, self.g, len(self.widths), self.widths
-        wp, nwp = b["wpart"], b["wpart"].numel()
+        turn = [0]
 
         def wgrad(name, x, ldx, offx, gy, ldg, h, w):
             ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
-            if self.overlap_wgrad:
+            k = turn[0] % len(self.wstreams)
+            turn[0] += 1
+            wp = b["wpart"][k]
+            if self.wgrad_streams:
                 # gy (and every earlier write) is complete on the main stream before the
                 # weight-gradient stream reads it
-                self.wstream.wait_stream(self.stream)
+                self.wstreams[k].wait_stream(self.stream)
             _ck(_lib.unet_conv3x3_wgrad(ptr(x), ldx, offx, ptr(gy), ldg, 0, ptr(g[name + ".w"]), ptr(g[name + ".b"]),
-                                        ptr(wp), nwp, N, h, w, ci, co, self.ws))
+                                        ptr(wp), wp.numel(), N, h, w, ci, co, self.ws[k]))
 
         def dgrad(name, gy, ldg, dx, lddx, h, w, mask=None, ldm=0, offm=0):
             ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
@@ -337,10 +344,11 @@ class UNet:
                     dgrad(f"e{lvl}a", b[f"ge{lvl}a"], c, b[f"dpool{lvl - 1}"], cp, h, w)
                 else:
                     wgrad("e0a", b["x0"], self.in_channels, 0, b["ge0a"], c, h, w)
-            if self.overlap_wgrad:
+            if self.wgrad_streams:
                 # every weight gradient is in place before anything later on the main
                 # stream (the optimizer, the next step's passes) runs
-                self.stream.wait_stream(self.wstream)
+                for st in self.wstreams:
+                    self.stream.wait_stream(st)
         return g
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -472,18 +472,20 @@ def test_unet_end_to_end_against_reference(widths, hw, bars, exact_bars):
         assert _rel(gg, gref[k]) < grad_bar and _cos(gg, gref[k]) > cos_bar, (k, _rel(gg, gref[k]))
 
 
-def test_weight_gradients_on_a_second_stream_equal_one_stream():
-    """The weight gradients and their reductions run on a second stream beside the input
-    gradients.  Over three training steps (forward, backward, Adam) of the full network on
-    four 64 x 64 problems, every loss, gradient and updated parameter is bitwise the same
-    as with every kernel on one stream: the kernels' sums are in a fixed order, so any
-    difference would be a missing dependency between the streams."""
+def test_weight_gradients_on_their_own_streams_equal_one_stream():
+    """The weight gradients and their reductions run on streams of their own (one or two,
+    layer by layer in turn) beside the input gradients.  Over three training steps
+    (forward, backward, Adam) of the full network on four 64 x 64 problems, every loss,
+    gradient and updated parameter is bitwise the same as with every kernel on one
+    stream: the kernels' sums are in a fixed order, so any difference would be a missing
+    dependency between the streams."""
     import torch
     from paper_2106_01557_amd import unet
-    say("case: U-Net widths (32, 64, 128, 256), 4 x 64 x 64, overlapped against serial weight gradients")
+    say("case: U-Net widths (32, 64, 128, 256), 4 x 64 x 64, weight gradients on 0, 1 and 2 streams of their own")
     N, hw = 4, 64
-    nets = [unet.UNet(widths=(32, 64, 128, 256), seed=5, overlap_wgrad=o) for o in (False, True)]
-    assert nets[1].wstream is not nets[1].stream and nets[0].wstream is nets[0].stream
+    nets = [unet.UNet(widths=(32, 64, 128, 256), seed=5, wgrad_streams=k) for k in (0, 1, 2)]
+    assert nets[0].wstreams == [nets[0].stream] and len(nets[2].wstreams) == 2
+    assert all(st is not nets[2].stream for st in nets[2].wstreams)
     rng = np.random.Generator(np.random.PCG64(8))
     yy, xx = np.meshgrid(np.arange(hw), np.arange(hw), indexing="ij")
     rho = np.stack([0.3 + 0.25 * np.tanh((12 + n - np.hypot(xx - 32, yy - 32)) / 2) for n in range(N)])
@@ -497,11 +499,12 @@ def test_weight_gradients_on_a_second_stream_equal_one_stream():
     for step in range(3):
         losses = [host(net.train_step(*args)).copy() for net in nets]
         torch.cuda.synchronize()
-        assert np.array_equal(losses[0], losses[1]), (step, losses)
-        assert torch.equal(nets[0].gflat, nets[1].gflat), step
-        assert torch.equal(nets[0].flat, nets[1].flat), step
-        assert torch.equal(nets[0].w16flat, nets[1].w16flat), step
-    assert float(nets[1].gflat.abs().max()) > 0
+        for i, other in enumerate(nets[1:], 1):
+            assert np.array_equal(losses[0], losses[i]), step
+            assert torch.equal(nets[0].gflat, other.gflat), step
+            assert torch.equal(nets[0].flat, other.flat), step
+            assert torch.equal(nets[0].w16flat, other.w16flat), step
+    assert float(nets[2].gflat.abs().max()) > 0
 
 
 LARGE_CONV = [  # N, H, W, Cin, Cout: thousands of pixels, every LDS tile shape, XCD-ordered grids
