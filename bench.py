@@ -351,8 +351,11 @@ def unet_step_flops(widths, in_channels, N, H, W) -> float:
 def unet_step_bound_ms(widths, in_channels, N, H, W, outputs=2) -> float:
     """Lower bound on one training step's time, pass by pass: each pass takes at least
     the longer of its dense FLOPs at the bf16 MFMA peak and its compulsory HBM bytes
-    (bfloat16 activations and gradients read and written once) at the HBM peak.  The
-    convolutions' weights and partial sums, and launch gaps, are left out."""
+    (bfloat16 activations and gradients read and written once) at the HBM peak.  A
+    decoder convolution's input is [upsample2(lower level) | skip], read as the two
+    tensors (the lower level at half size); its input gradient is written whole and then
+    summed 2x2 by the upsampling gradient.  The convolutions' weights and partial sums,
+    and launch gaps, are left out."""
     from paper_2106_01557_amd import unet
     peak_f, peak_b = PEAK_BF16_TFLOPS * 1e12, PEAK_HBM_GBS * 1e9
     t = 0.0
@@ -361,6 +364,13 @@ def unet_step_bound_ms(widths, in_channels, N, H, W, outputs=2) -> float:
         P = N * (H >> lvl) * (W >> lvl)
         fl = 2.0 * P * 9 * ci * co
         io = 2.0 * P * (ci + co)
+        if name[0] == "d" and name[2] == "a":                    # [upsample2(lower) | skip] input
+            cu = widths[lvl + 1]
+            xin = 2.0 * (P // 4 * cu + P * (ci - cu))
+            t += max(fl / peak_f, (xin + 2.0 * P * co) / peak_b)     # forward
+            t += max(fl / peak_f, io / peak_b)                       # input gradient, written whole
+            t += max(fl / peak_f, (xin + 2.0 * P * co) / peak_b)     # weight gradient
+            continue
         t += max(fl / peak_f, io / peak_b)                       # forward
         if name != "e0a":                                          # input gradient (the
             mask = 2.0 * P * ci if name.endswith("b") else 0.0    # b layers' ReLU mask)
@@ -372,7 +382,6 @@ def unet_step_bound_ms(widths, in_channels, N, H, W, outputs=2) -> float:
         P = N * (H >> lvl) * (W >> lvl)
         bw += 2.0 * (P * c + P // 4 * c)                 # max pool forward
         bw += 2.0 * (3 * P * c + P // 4 * c)             # max pool backward (x, skip gradient, dx; dy)
-        bw += 2.0 * (P // 4 * cu + P * cu)               # upsample forward
         bw += 2.0 * (P * cu + 2 * (P // 4) * cu)         # upsample backward (gradient, gate; dx)
     P0, c0 = N * H * W, widths[0]
     bw += 2 * (8.0 * P0 * 2 + 2.0 * P0 * in_channels + 4.0 * P0 * 2)   # inputs and targets prepared

@@ -47,6 +47,24 @@ int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, co
                      int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, int32_t flags,
                      void* stream);
 
+/* The same convolution with its input the channel concatenation of two tensors and its
+ * output split between two, without either being stored whole: the U-Net decoder's
+ * [upsample2(lower level) | skip connection] input, and its input gradient, whose two
+ * channel ranges go back to the two branches.  Input channels [0, C_x) come from x,
+ * which is [N,H,W] x C_x, or with half != 0 [N,H/2,W/2] x C_x read through the nearest
+ * 2x upsampling (pixel (Y, X) reads (Y/2, X/2)); channels [C_x, C_in) come from x2
+ * ([N,H,W] x (C_in - C_x); NULL when C_x = C_in).  Output channels [0, C_y) go to y,
+ * [C_y, C_out) to y2 (NULL when C_y = C_out), each with its own ld/off; the mask, if
+ * any, is one [N,H,W] x C_out tensor.  C_x and C_y are multiples of 8 in [8, C_in] and
+ * [8, C_out], and C_x a multiple of 32 when C_in is.  Results are bitwise those of unet_conv3x3_fwd on the concatenated input
+ * with the output stored whole.  unet_conv3x3_fwd(...) is this call with C_x = C_in,
+ * half = 0, x2 = NULL, C_y = C_out, y2 = NULL. */
+int unet_conv3x3_fwd_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, int32_t half,
+                         const void* x2, int32_t ldx2, int32_t offx2, const void* w, const float* bias,
+                         void* y, int32_t ldy, int32_t offy, int32_t C_y, void* y2, int32_t ldy2,
+                         int32_t offy2, const void* mask, int32_t ldm, int32_t offm, int32_t N, int32_t H,
+                         int32_t W, int32_t C_in, int32_t C_out, int32_t flags, void* stream);
+
 /* wf[i][t][o] = w[o][8-t][i]: the weights of the input-gradient convolution
  * (dx = conv3x3_fwd(g, wf) with C_in and C_out exchanged). */
 int unet_flip_weights(const void* w, void* wf, int32_t C_out, int32_t C_in, void* stream);
@@ -66,6 +84,15 @@ int unet_wgrad_partial_bytes(int32_t N, int32_t H, int32_t W, int32_t C_in, int3
 int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg,
                        float* dw, float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H,
                        int32_t W, int32_t C_in, int32_t C_out, void* stream);
+
+/* The same gradients with the layer input the concatenation of two tensors, as in
+ * unet_conv3x3_fwd_cat (x: channels [0, C_x), at half size when half != 0; x2: channels
+ * [C_x, C_in), NULL when C_x = C_in).  Results are bitwise those of unet_conv3x3_wgrad
+ * on the concatenated input; the partials size is unet_wgrad_partial_bytes(C_in, C_out). */
+int unet_conv3x3_wgrad_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, int32_t half,
+                           const void* x2, int32_t ldx2, int32_t offx2, const void* g, int32_t ldg,
+                           int32_t offg, float* dw, float* db, void* partials, size_t partial_bytes,
+                           int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, void* stream);
 
 /* The same weight and bias gradients for callers that cannot allocate device memory
  * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the

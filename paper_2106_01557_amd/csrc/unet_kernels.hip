@@ -74,17 +74,64 @@ __device__ __forceinline__ uint4 sel(bool keep, uint4 v) {
 // ---------------------------------------------------------------------------
 // 3x3 convolution (forward; also the input gradient with flipped weights)
 // ---------------------------------------------------------------------------
+// The input may be the channel concatenation of two tensors and the output may go to
+// two: input channels below `split` come from x (at half the size when `half`: the
+// nearest-neighbour 2x upsampling), the rest from x2; output channels below `ysplit`
+// go to y, the rest to y2.  One tensor each: split = C_in, ysplit = C_out.
 struct ConvArgs {
     const bf16_t* x;      // offset applied
+    const bf16_t* x2;     // offset applied (channels split ..)
     const bf16_t* w;      // [C_out][9 C_in]
     const float* bias;    // nullable
     void* y;              // offset applied (elements of the output type)
+    void* y2;             // offset applied (channels ysplit ..)
     const bf16_t* mask;   // nullable, offset applied
-    int ldx, ldy, ldm;
+    int ldx, ldx2, ldy, ldy2, ldm;
+    int split, half, ysplit;
     int lh, lw;           // log2 H, log2 W
     int P;                // N H W
     int Cin, Cout, relu;
 };
+
+// Flat index at half the size of full-size pixel p: (y, x) of image n reads (y / 2, x / 2)
+// of image n (nearest-neighbour 2x upsampling).
+__device__ __forceinline__ int half_px(int p, int lh, int lw) {
+    const int x = p & ((1 << lw) - 1), y = (p >> lw) & ((1 << lh) - 1), n = p >> (lh + lw);
+    return (n << (lh + lw - 2)) + ((y >> 1) << (lw - 1)) + (x >> 1);
+}
+
+// Address of input channels ch .. ch + 7 of full-size pixel p (ch and split are
+// multiples of 8, so a vector of 8 channels never straddles the two tensors).
+template <class Args>
+__device__ __forceinline__ const bf16_t* src_at(const Args& a, int p, int ch) {
+    if (ch < a.split) return a.x + (size_t)(a.half ? half_px(p, a.lh, a.lw) : p) * a.ldx + ch;
+    return a.x2 + (size_t)p * a.ldx2 + (ch - a.split);
+}
+
+// Source of the 32-channel block at c0 in the tiled kernels, uniform across a workgroup
+// (there C_in % 32 == 0 and split % 32 == 0 when the input has two tensors), and the
+// pixel it reads for full-size image offset img, row yy, column xx.
+struct BlockSrc {
+    const bf16_t* p;
+    int ld;
+    bool half;
+};
+template <class Args>
+__device__ __forceinline__ BlockSrc block_src(const Args& a, int c0) {
+    if (c0 < a.split) return BlockSrc{a.x + c0, a.ldx, a.half != 0};
+    return BlockSrc{a.x2 + (c0 - a.split), a.ldx2, false};
+}
+__device__ __forceinline__ const bf16_t* block_at(const BlockSrc& b, int img, int yy, int xx, int lw) {
+    const int q = b.half ? (img >> 2) + ((yy >> 1) << (lw - 1)) + (xx >> 1) : img + (yy << lw) + xx;
+    return b.p + (size_t)q * b.ld;
+}
+
+// Address of output channel co (and the next 7 for vector stores) of pixel p.
+template <class T>
+__device__ __forceinline__ T* dst_at(const ConvArgs& a, size_t p, int co) {
+    if (co < a.ysplit) return static_cast<T*>(a.y) + p * a.ldy + co;
+    return static_cast<T*>(a.y2) + p * a.ldy2 + (co - a.ysplit);
+}
 
 // A wavefront computes (16 MT) pixels x (16 NT) output channels; a workgroup of four
 // wavefronts covers 64 MT consecutive pixels.  kTapOuter (C_in % 32 == 0): each
@@ -128,17 +175,17 @@ __global__ void __launch_bounds__(256) k_conv3x3(const ConvArgs a) {
     if (kTapOuter) {
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
-            const bf16_t* xa[MT];
+            int pa[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 const int ys = (py[m] + dy) & Hm, xs = (px[m] + dx) & Wm;
-                xa[m] = a.x + (size_t)(pimg[m] + (ys << a.lw) + xs) * a.ldx + 8 * grp;
+                pa[m] = pimg[m] + (ys << a.lw) + xs;
             }
             const int kb = tap * a.Cin + 8 * grp;
             for (int c = 0; c < a.Cin; c += 32) {
                 uint4 A[MT], B[NT];
 #pragma unroll
-                for (int m = 0; m < MT; ++m) A[m] = ld16(xa[m] + c);
+                for (int m = 0; m < MT; ++m) A[m] = ld16(src_at(a, pa[m], c + 8 * grp));
 #pragma unroll
                 for (int n = 0; n < NT; ++n) B[n] = ld16(wrow[n] + kb + c);
 #pragma unroll
@@ -164,7 +211,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(const ConvArgs a) {
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 const int ys = (py[m] + dy) & Hm, xs = (px[m] + dx) & Wm;
-                A[m] = ld16(a.x + (size_t)(pimg[m] + (ys << a.lw) + xs) * a.ldx + ci);
+                A[m] = ld16(src_at(a, pimg[m] + (ys << a.lw) + xs, ci));
             }
 #pragma unroll
             for (int n = 0; n < NT; ++n) B[n] = ld16(wrow[n] + (kv ? k0 : 0));
@@ -195,8 +242,8 @@ __global__ void __launch_bounds__(256) k_conv3x3(const ConvArgs a) {
                 float v = acc[m][n][r] + b;
                 if (a.relu) v = fmaxf(v, 0.f);
                 if (a.mask && !(bf2f(a.mask[(size_t)p * a.ldm + co]) > 0.f)) v = 0.f;
-                if (kF32) static_cast<float*>(a.y)[(size_t)p * a.ldy + co] = v;
-                else static_cast<bf16_t*>(a.y)[(size_t)p * a.ldy + co] = (bf16_t)f2bf(v);
+                if (kF32) *dst_at<float>(a, p, co) = v;
+                else *dst_at<bf16_t>(a, p, co) = (bf16_t)f2bf(v);
             }
         }
     }
@@ -258,10 +305,11 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     auto load = [&](int ch) {
         const int tap = ch / cpt, c0 = (ch - tap * cpt) << 5;
         const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
+        const BlockSrc src = block_src(a, c0);
 #pragma unroll
         for (int j = 0; j < AV; ++j) {
             const int ys = (py[j] + dy) & Hm, xs = (px[j] + dx) & Wm;
-            ra[j] = ld16(a.x + (size_t)(pimg[j] + (ys << a.lw) + xs) * a.ldx + c0 + 8 * lv);
+            ra[j] = ld16(block_at(src, pimg[j], ys, xs, a.lw) + 8 * lv);
         }
 #pragma unroll
         for (int j = 0; j < BV; ++j)
@@ -326,7 +374,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
                     float v = acc[m][n][r] + b;
                     if (a.relu) v = fmaxf(v, 0.f);
                     if (a.mask && !(bf2f(a.mask[(size_t)p * a.ldm + co]) > 0.f)) v = 0.f;
-                    static_cast<float*>(a.y)[(size_t)p * a.ldy + co] = v;
+                    *dst_at<float>(a, p, co) = v;
                 }
             }
         }
@@ -367,7 +415,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
                 }
                 o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
             }
-            st16(static_cast<bf16_t*>(a.y) + p * a.ldy + co, o);
+            st16(dst_at<bf16_t>(a, p, co), o);
         }
     }
 }
@@ -396,7 +444,7 @@ __device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&a
                     float v = acc[m][n][r] + b;
                     if (a.relu) v = fmaxf(v, 0.f);
                     if (a.mask && !(bf2f(a.mask[p * a.ldm + co]) > 0.f)) v = 0.f;
-                    static_cast<float*>(a.y)[p * a.ldy + co] = v;
+                    *dst_at<float>(a, p, co) = v;
                 }
             }
         }
@@ -433,7 +481,7 @@ __device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&a
                 }
                 o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
             }
-            st16(static_cast<bf16_t*>(a.y) + p * a.ldy + co, o);
+            st16(dst_at<bf16_t>(a, p, co), o);
         }
     }
 }
@@ -493,6 +541,7 @@ __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs 
     constexpr int HV = (kHalo * 4 + 255) / 256, WV = (9 * BN * 4 + 255) / 256;
     uint4 hv[HV], wv[WV];
     auto gload = [&](int c0) {
+        const BlockSrc src = block_src(a, c0);
 #pragma unroll
         for (int i = 0; i < HV; ++i) {
             const int v = t + 256 * i;
@@ -500,7 +549,7 @@ __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs 
                 const int h = v >> 2, piece = v & 3;
                 const int hr = h / 18, hc = h - 18 * hr;
                 const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
-                hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + c0 + 8 * piece);
+                hv[i] = ld16(block_at(src, img, yy, xx, a.lw) + 8 * piece);
             }
         }
 #pragma unroll
@@ -574,7 +623,7 @@ __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs 
                     float v = acc[m][n][r] + b;
                     if (a.relu) v = fmaxf(v, 0.f);
                     if (a.mask && !(bf2f(a.mask[p * a.ldm + co]) > 0.f)) v = 0.f;
-                    static_cast<float*>(a.y)[p * a.ldy + co] = v;
+                    *dst_at<float>(a, p, co) = v;
                 }
             }
         }
@@ -613,7 +662,7 @@ __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs 
                 }
                 o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
             }
-            st16(static_cast<bf16_t*>(a.y) + p * a.ldy + co, o);
+            st16(dst_at<bf16_t>(a, p, co), o);
         }
     }
 }
@@ -648,7 +697,7 @@ __global__ void __launch_bounds__(256) k_conv_halo8(const ConvArgs a) {
         if (v < kHalo) {
             const int hr = v / 18, hc = v - 18 * hr;
             const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
-            hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx);
+            hv[i] = ld16(block_at(block_src(a, 0), img, yy, xx, a.lw));
         }
         if (v < BN * 12) {  // output channel v / 12, tap v % 12
             const int n = v / 12, tap = v - 12 * n;
@@ -733,9 +782,11 @@ __global__ void k_flip(const bf16_t* __restrict__ w, bf16_t* __restrict__ wf, in
 // range is split into slabs (grid z) whose partial sums are stored separately.
 struct WgArgs {
     const bf16_t* x;
+    const bf16_t* x2;     // input channels split .. (see ConvArgs)
     const bf16_t* g;
     float* part;          // [slabs][Cout][Kt]
-    int ldx, ldg;
+    int ldx, ldx2, ldg;
+    int split, half;
     int lh, lw, P, Cin, Cout, K, Kt, slab;
     int ktiles, ctiles;   // k_wgrad_tr's flat grid: ktiles x ctiles x slabs
 };
@@ -776,7 +827,7 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgArgs a) {
         if (mode == 0) {
             const int base = (q >> (a.lw + a.lh)) << (a.lw + a.lh);
             const int ys = ((q >> a.lw) + dy) & Hm, xs = ((q & Wm) + dx) & Wm;
-            xv = ld16(a.x + (size_t)(base + (ys << a.lw) + xs) * a.ldx + ci);
+            xv = ld16(src_at(a, base + (ys << a.lw) + xs, ci));
         } else if (mode == 1) {
             xv.x = 0x3f80u;  // bfloat16 1.0 in element 0 (k == K), zeros after it
         }
@@ -925,7 +976,7 @@ __global__ void __launch_bounds__(256) k_wgrad_tr(const WgArgs a) {
             if (mode == 0) {
                 const int base = (q >> (a.lw + a.lh)) << (a.lw + a.lh);
                 const int ys = ((q >> a.lw) + dy) & Hm, xs = ((q & Wm) + dx) & Wm;
-                v = ld16(a.x + (size_t)(base + (ys << a.lw) + xs) * a.ldx + ci);
+                v = ld16(src_at(a, base + (ys << a.lw) + xs, ci));
             } else if (mode == 1) {
                 v.x = 0x3f80u;  // bfloat16 1.0 in column K: the bias gradient
             }
@@ -1036,6 +1087,7 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
     const int L = xcd_block(blockIdx.x, gridDim.x);
     const int cc = L % a.ktiles, rest = L / a.ktiles, ob = rest % a.ctiles, z = rest / a.ctiles;
     const int c0 = cc * 32, o0 = ob * OC;
+    const BlockSrc src = block_src(a, c0);
     const int tb = z * a.slab, te = min(a.P >> 8, tb + a.slab);
     const int Hm = (1 << a.lh) - 1, Wm = (1 << a.lw) - 1;
     const int txs = a.lw - 4, tys = a.lh - 4;
@@ -1068,7 +1120,7 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
                 const int h = v >> 2, piece = v & 3;
                 const int hr = h / 18, hc = h - 18 * hr;
                 const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
-                hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx + c0 + 8 * piece);
+                hv[i] = ld16(block_at(src, img, yy, xx, a.lw) + 8 * piece);
             }
         }
     };
@@ -1210,7 +1262,7 @@ __global__ void __launch_bounds__(256) k_wgrad_halo8(const WgArgs a) {
             if (h < kHalo) {
                 const int hr = h / 18, hc = h - 18 * hr;
                 const int yy = (ty0 - 1 + hr) & Hm, xx = (tx0 - 1 + hc) & Wm;
-                hv[i] = ld16(a.x + (size_t)(img + (yy << a.lw) + xx) * a.ldx);
+                hv[i] = ld16(block_at(block_src(a, 0), img, yy, xx, a.lw));
             }
         }
     };
@@ -1706,6 +1758,7 @@ void launch_lds(const ConvArgs& a, bool f32, hipStream_t s) {
 // bf16 output is written in 16-byte vectors: it needs an aligned output and stride.
 bool launch_conv_lds(const ConvArgs& a, bool f32, hipStream_t s) {
     if (!f32 && (!aligned16(a.y) || a.ldy % 8)) return false;
+    if (!f32 && a.ysplit < a.Cout && (!aligned16(a.y2) || a.ldy2 % 8)) return false;
     if (a.Cin == 8 && a.lw >= 4 && a.lh >= 4 && a.Cout % 32 == 0) {
         const dim3 grid((a.P / 256) * (a.Cout / 32));
         if (f32) hipLaunchKernelGGL((k_conv_halo8<true>), grid, dim3(256), 0, s, a);
@@ -1794,28 +1847,57 @@ using namespace unet_dev;
 
 extern "C" {
 
-int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, const float* bias, void* y,
-                     int32_t ldy, int32_t offy, const void* mask, int32_t ldm, int32_t offm, int32_t N, int32_t H,
-                     int32_t W, int32_t C_in, int32_t C_out, int32_t flags, void* stream) {
+int unet_conv3x3_fwd_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, int32_t half, const void* x2,
+                         int32_t ldx2, int32_t offx2, const void* w, const float* bias, void* y, int32_t ldy,
+                         int32_t offy, int32_t C_y, void* y2, int32_t ldy2, int32_t offy2, const void* mask,
+                         int32_t ldm, int32_t offm, int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out,
+                         int32_t flags, void* stream) {
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
     if (C_in < 8 || C_in % 8 || C_out < 16 || C_out % 16)
         return fail(UNET_EINVAL, "C_in must be a multiple of 8 and C_out of 16 (got %d, %d)", C_in, C_out);
     if (flags & ~(UNET_RELU | UNET_OUT_F32)) return fail(UNET_EINVAL, "unknown flags %d", flags);
-    if ((r = check_tensor("x", x, ldx, offx, C_in, false))) return r;
+    if (C_x < 8 || C_x > C_in || C_x % 8 || (C_in % 32 == 0 && C_x % 32))
+        return fail(UNET_EINVAL, "C_x must be a multiple of 8 in [8, C_in], of 32 when C_in is (got %d, C_in %d)",
+                    C_x, C_in);
+    if (C_y < 8 || C_y > C_out || C_y % 8)
+        return fail(UNET_EINVAL, "C_y must be a multiple of 8 in [8, C_out] (got %d, C_out %d)", C_y, C_out);
+    if ((r = check_tensor("x", x, ldx, offx, C_x, false))) return r;
+    if (C_x < C_in) {
+        if ((r = check_tensor("x2", x2, ldx2, offx2, C_in - C_x, false))) return r;
+    } else if (x2) {
+        return fail(UNET_EINVAL, "x2 must be NULL when C_x = C_in");
+    }
     if ((r = check_tensor("mask", mask, ldm, offm, C_out, true))) return r;
     if (!w || !aligned16(w)) return fail(UNET_EINVAL, "w must be non-NULL and 16-byte aligned");
-    if (!y || ldy < offy + C_out || offy < 0) return fail(UNET_EINVAL, "y: need ld >= off + C_out");
+    if (!y || ldy < offy + C_y || offy < 0) return fail(UNET_EINVAL, "y: need ld >= off + C_y");
+    if (C_y < C_out) {
+        if (!y2 || ldy2 < offy2 + (C_out - C_y) || offy2 < 0)
+            return fail(UNET_EINVAL, "y2: need ld >= off + C_out - C_y");
+    } else if (y2) {
+        return fail(UNET_EINVAL, "y2 must be NULL when C_y = C_out");
+    }
     const bool f32 = flags & UNET_OUT_F32;
+    auto out = [&](void* base, int off) -> void* {
+        if (!base) return nullptr;
+        return f32 ? (void*)(static_cast<float*>(base) + off) : (void*)(static_cast<bf16_t*>(base) + off);
+    };
     ConvArgs a;
     a.x = static_cast<const bf16_t*>(x) + offx;
+    a.x2 = x2 ? static_cast<const bf16_t*>(x2) + offx2 : nullptr;
     a.w = static_cast<const bf16_t*>(w);
     a.bias = bias;
-    a.y = f32 ? (void*)(static_cast<float*>(y) + offy) : (void*)(static_cast<bf16_t*>(y) + offy);
+    a.y = out(y, offy);
+    a.y2 = out(y2, offy2);
     a.mask = mask ? static_cast<const bf16_t*>(mask) + offm : nullptr;
     a.ldx = ldx;
+    a.ldx2 = ldx2;
     a.ldy = ldy;
+    a.ldy2 = ldy2;
     a.ldm = ldm;
+    a.split = C_x;
+    a.half = half ? 1 : 0;
+    a.ysplit = C_y;
     a.lh = lh;
     a.lw = lw;
     a.P = N * H * W;
@@ -1829,6 +1911,15 @@ int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, co
         else launch_conv<4, 2>(a, tap_outer, f32, s);
     }
     return launched("conv3x3 launch");
+}
+
+int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, const float* bias, void* y,
+                     int32_t ldy, int32_t offy, const void* mask, int32_t ldm, int32_t offm, int32_t N, int32_t H,
+                     int32_t W, int32_t C_in, int32_t C_out, int32_t flags, void* stream) {
+    if (C_in < 8 || C_in % 8 || C_out < 16 || C_out % 16)
+        return fail(UNET_EINVAL, "C_in must be a multiple of 8 and C_out of 16 (got %d, %d)", C_in, C_out);
+    return unet_conv3x3_fwd_cat(x, ldx, offx, C_in, 0, nullptr, 0, 0, w, bias, y, ldy, offy, C_out, nullptr, 0, 0,
+                                mask, ldm, offm, N, H, W, C_in, C_out, flags, stream);
 }
 
 int unet_flip_weights(const void* w, void* wf, int32_t C_out, int32_t C_in, void* stream) {
@@ -1880,11 +1971,28 @@ namespace {
 
 // Checks the arguments shared by both weight-gradient entry points; *need gets the
 // partials size of this shape.
-int wgrad_check(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, const float* dw,
-                int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, size_t* need) {
+// The layer input of a weight gradient: channels [0, C_x) from x (at half the size when
+// half), [C_x, C_in) from x2 (NULL when C_x = C_in); offsets not yet applied.
+struct WgIn {
+    const void* x;
+    int32_t ldx, offx, C_x, half;
+    const void* x2;
+    int32_t ldx2, offx2;
+};
+
+int wgrad_check(const WgIn& in, const void* g, int32_t ldg, int32_t offg, const float* dw, int32_t N, int32_t H,
+                int32_t W, int32_t C_in, int32_t C_out, size_t* need) {
     int r;
     if ((r = unet_wgrad_partial_bytes(N, H, W, C_in, C_out, need))) return r;
-    if ((r = check_tensor("x", x, ldx, offx, C_in, false))) return r;
+    if (in.C_x < 8 || in.C_x > C_in || in.C_x % 8 || (C_in % 32 == 0 && in.C_x % 32))
+        return fail(UNET_EINVAL, "C_x must be a multiple of 8 in [8, C_in], of 32 when C_in is (got %d, C_in %d)",
+                    in.C_x, C_in);
+    if ((r = check_tensor("x", in.x, in.ldx, in.offx, in.C_x, false))) return r;
+    if (in.C_x < C_in) {
+        if ((r = check_tensor("x2", in.x2, in.ldx2, in.offx2, C_in - in.C_x, false))) return r;
+    } else if (in.x2) {
+        return fail(UNET_EINVAL, "x2 must be NULL when C_x = C_in");
+    }
     if ((r = check_tensor("g", g, ldg, offg, C_out, false))) return r;
     if (!dw) return fail(UNET_EINVAL, "dw is NULL");
     return UNET_OK;
@@ -1892,18 +2000,21 @@ int wgrad_check(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t
 
 // Launches the split weight gradient with its partial sums in `partials` (device memory
 // of at least the checked size) and the fixed-order reduction.
-int wgrad_launch(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, float* dw,
-                 float* db, void* partials, int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out,
-                 void* stream) {
+int wgrad_launch(const WgIn& in, const void* g, int32_t ldg, int32_t offg, float* dw, float* db, void* partials,
+                 int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, void* stream) {
     int r;
     int lh, lw;
     check_geo(N, H, W, &lh, &lw);
     const WgPlan p = wgrad_plan(N * H * W, lh, lw, C_in, C_out);
     WgArgs a;
-    a.x = static_cast<const bf16_t*>(x) + offx;
+    a.x = static_cast<const bf16_t*>(in.x) + in.offx;
+    a.x2 = in.x2 ? static_cast<const bf16_t*>(in.x2) + in.offx2 : nullptr;
     a.g = static_cast<const bf16_t*>(g) + offg;
     a.part = static_cast<float*>(partials);
-    a.ldx = ldx;
+    a.ldx = in.ldx;
+    a.ldx2 = in.ldx2;
+    a.split = in.C_x;
+    a.half = in.half ? 1 : 0;
     a.ldg = ldg;
     a.lh = lh;
     a.lw = lw;
@@ -1970,29 +2081,39 @@ int scratch_on_current_device(float** out) {
 
 extern "C" {
 
+int unet_conv3x3_wgrad_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, int32_t half, const void* x2,
+                           int32_t ldx2, int32_t offx2, const void* g, int32_t ldg, int32_t offg, float* dw, float* db,
+                           void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C_in,
+                           int32_t C_out, void* stream) {
+    const WgIn in{x, ldx, offx, C_x, half, x2, ldx2, offx2};
+    size_t need = 0;
+    int r;
+    if ((r = wgrad_check(in, g, ldg, offg, dw, N, H, W, C_in, C_out, &need))) return r;
+    if (!partials || partial_bytes < need) return fail(UNET_EINVAL, "partials: %zu bytes needed", need);
+    return wgrad_launch(in, g, ldg, offg, dw, db, partials, N, H, W, C_in, C_out, stream);
+}
+
 int unet_conv3x3_wgrad(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg, float* dw,
                        float* db, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C_in,
                        int32_t C_out, void* stream) {
-    size_t need = 0;
-    int r;
-    if ((r = wgrad_check(x, ldx, offx, g, ldg, offg, dw, N, H, W, C_in, C_out, &need))) return r;
-    if (!partials || partial_bytes < need) return fail(UNET_EINVAL, "partials: %zu bytes needed", need);
-    return wgrad_launch(x, ldx, offx, g, ldg, offg, dw, db, partials, N, H, W, C_in, C_out, stream);
+    return unet_conv3x3_wgrad_cat(x, ldx, offx, C_in, 0, nullptr, 0, 0, g, ldg, offg, dw, db, partials,
+                                  partial_bytes, N, H, W, C_in, C_out, stream);
 }
 
 int unet_conv3x3_wgrad_noalloc(const void* x, int32_t ldx, int32_t offx, const void* g, int32_t ldg, int32_t offg,
                                float* dw, float* db, int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out,
                                void* stream) {
+    const WgIn in{x, ldx, offx, C_in, 0, nullptr, 0, 0};
     size_t need = 0;
     int r;
-    if ((r = wgrad_check(x, ldx, offx, g, ldg, offg, dw, N, H, W, C_in, C_out, &need))) return r;
+    if ((r = wgrad_check(in, g, ldg, offg, dw, N, H, W, C_in, C_out, &need))) return r;
     if (need > UNET_WGRAD_SCRATCH_BYTES)
         return fail(UNET_EINVAL, "wgrad_noalloc: this shape needs %zu bytes of partial sums, above the %zu-byte "
                                  "static scratch; use unet_conv3x3_wgrad with a caller workspace",
                     need, (size_t)UNET_WGRAD_SCRATCH_BYTES);
     float* part = nullptr;
     if ((r = scratch_on_current_device(&part))) return r;
-    return wgrad_launch(x, ldx, offx, g, ldg, offg, dw, db, part, N, H, W, C_in, C_out, stream);
+    return wgrad_launch(in, g, ldg, offg, dw, db, part, N, H, W, C_in, C_out, stream);
 }
 
 int unet_maxpool2_fwd(const void* x, int32_t ldx, int32_t offx, void* y, int32_t ldy, int32_t offy, int32_t N,

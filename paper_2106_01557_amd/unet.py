@@ -26,8 +26,8 @@ from . import lbm as _lbm
 _lib = _lbm.library()
 _P, _I, _F, _V, _S = ctypes.POINTER, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
 
-EXPORTED = ["unet_conv3x3_fwd", "unet_flip_weights", "unet_flip_weights_many", "unet_wgrad_partial_bytes",
-            "unet_conv3x3_wgrad", "unet_conv3x3_wgrad_noalloc",
+EXPORTED = ["unet_conv3x3_fwd", "unet_conv3x3_fwd_cat", "unet_flip_weights", "unet_flip_weights_many",
+            "unet_wgrad_partial_bytes", "unet_conv3x3_wgrad", "unet_conv3x3_wgrad_cat", "unet_conv3x3_wgrad_noalloc",
             "unet_maxpool2_fwd", "unet_maxpool2_bwd", "unet_upsample2_fwd", "unet_upsample2_bwd",
             "unet_prepare_input", "unet_output_fields", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd", "unet_adam",
             "unet_to_bf16", "unet_to_f32", "unet_last_error"]
@@ -35,11 +35,15 @@ EXPORTED = ["unet_conv3x3_fwd", "unet_flip_weights", "unet_flip_weights_many", "
 RELU, OUT_F32 = 1, 2
 
 _lib.unet_conv3x3_fwd.argtypes = [_V, _I, _I, _V, _V, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_conv3x3_fwd_cat.argtypes = [_V, _I, _I, _I, _I, _V, _I, _I, _V, _V, _V, _I, _I, _I, _V, _I, _I, _V, _I, _I,
+                                      _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_flip_weights.argtypes = [_V, _V, _I, _I, _V]
 _lib.unet_flip_weights_many.argtypes = [ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.POINTER(_I),
                                         ctypes.POINTER(_I), _I, _V]
 _lib.unet_wgrad_partial_bytes.argtypes = [_I, _I, _I, _I, _I, _P(_S)]
 _lib.unet_conv3x3_wgrad.argtypes = [_V, _I, _I, _V, _I, _I, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
+_lib.unet_conv3x3_wgrad_cat.argtypes = [_V, _I, _I, _I, _I, _V, _I, _I, _V, _I, _I, _V, _V, _V, _S, _I, _I, _I, _I, _I,
+                                        _V]
 _lib.unet_conv3x3_wgrad_noalloc.argtypes = [_V, _I, _I, _V, _I, _I, _V, _V, _I, _I, _I, _I, _I, _V]
 _lib.unet_maxpool2_fwd.argtypes = [_V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_maxpool2_bwd.argtypes = [_V, _I, _I, _V, _I, _I, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _V]
@@ -205,19 +209,20 @@ class UNet:
             b["out"], b["dout"] = f32(self.K, N, H, W), f32(self.K, N, H, W)
             for lvl, c in enumerate(self.widths):
                 h, w = H >> lvl, W >> lvl
-                b[f"e{lvl}a"] = bf(N, h, w, c)
+                b[f"e{lvl}a"], b[f"e{lvl}b"] = bf(N, h, w, c), bf(N, h, w, c)
                 b[f"ge{lvl}a"] = bf(N, h, w, c)
                 b[f"ge{lvl}b"] = bf(N, h, w, c)
                 if lvl < L - 1:
                     cu = self.widths[lvl + 1]
-                    b[f"cat{lvl}"] = bf(N, h, w, cu + c)     # [upsampled lower level | e{lvl}b]
-                    b[f"dcat{lvl}"] = bf(N, h, w, cu + c)
+                    # the decoder's input [upsample2(lower level) | e{lvl}b] is never stored:
+                    # its convolution reads the two tensors; its input gradient goes to the
+                    # upsampled branch (dup, full size) and the skip branch (dskip)
+                    b[f"dup{lvl}"] = bf(N, h, w, cu)
+                    b[f"dskip{lvl}"] = bf(N, h, w, c)
                     b[f"pool{lvl}"] = bf(N, h // 2, w // 2, c)
                     b[f"dpool{lvl}"] = bf(N, h // 2, w // 2, c)
                     b[f"d{lvl}a"], b[f"d{lvl}b"] = bf(N, h, w, c), bf(N, h, w, c)
                     b[f"gd{lvl}a"], b[f"gd{lvl}b"] = bf(N, h, w, c), bf(N, h, w, c)
-                else:
-                    b[f"e{lvl}b"] = bf(N, h, w, c)
             need = 0
             for name, ci, co in self.layers:
                 lvl = int(name[1])
@@ -261,22 +266,21 @@ class UNet:
             for lvl in range(L):
                 h, w, c = H >> lvl, W >> lvl, wd[lvl]
                 self._conv(f"e{lvl}a", x, ldx, offx, b[f"e{lvl}a"], c, 0, N, h, w)
+                self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"e{lvl}b"], c, 0, N, h, w)
                 if lvl < L - 1:
-                    cu = wd[lvl + 1]
-                    cat = b[f"cat{lvl}"]
-                    self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, cat, cu + c, cu, N, h, w)
-                    _ck(_lib.unet_maxpool2_fwd(ptr(cat), cu + c, cu, ptr(b[f"pool{lvl}"]), c, 0, N, h, w, c, self.s))
+                    _ck(_lib.unet_maxpool2_fwd(ptr(b[f"e{lvl}b"]), c, 0, ptr(b[f"pool{lvl}"]), c, 0, N, h, w, c,
+                                               self.s))
                     x, ldx, offx = b[f"pool{lvl}"], c, 0
-                else:
-                    self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"e{lvl}b"], c, 0, N, h, w)
-            low, ldl = b[f"e{L - 1}b"], wd[L - 1]
+            low = b[f"e{L - 1}b"]
             for lvl in reversed(range(L - 1)):
                 h, w, c, cu = H >> lvl, W >> lvl, wd[lvl], wd[lvl + 1]
-                cat = b[f"cat{lvl}"]
-                _ck(_lib.unet_upsample2_fwd(ptr(low), ldl, 0, ptr(cat), cu + c, 0, N, h // 2, w // 2, cu, self.s))
-                self._conv(f"d{lvl}a", cat, cu + c, 0, b[f"d{lvl}a"], c, 0, N, h, w)
+                # input [upsample2(low) | e{lvl}b], read from the two tensors
+                _ck(_lib.unet_conv3x3_fwd_cat(ptr(low), cu, 0, cu, 1, ptr(b[f"e{lvl}b"]), c, 0,
+                                              ptr(self.w16[f"d{lvl}a"]), ptr(self.p[f"d{lvl}a.b"]),
+                                              ptr(b[f"d{lvl}a"]), c, 0, c, None, 0, 0, None, 0, 0,
+                                              N, h, w, cu + c, c, RELU, self.s))
                 self._conv(f"d{lvl}b", b[f"d{lvl}a"], c, 0, b[f"d{lvl}b"], c, 0, N, h, w)
-                low, ldl = b[f"d{lvl}b"], c
+                low = b[f"d{lvl}b"]
             tgt = b["target"] if target_rho is not None else None
             _ck(_lib.unet_head_fwd(ptr(low), wd[0], ptr(self.p["head.w"]), ptr(self.p["head.b"]), ptr(b["rin"]),
                                    ptr(tgt), ptr(b["out"]), ptr(b["dout"]), ptr(b["loss"]), ptr(b["hpart"]),
@@ -290,7 +294,8 @@ class UNet:
         b, g, L, wd = self.buf, self.g, len(self.widths), self.widths
         turn = [0]
 
-        def wgrad(name, x, ldx, offx, gy, ldg, h, w):
+        def wgrad(name, x, ldx, offx, gy, ldg, h, w, skip=None):
+            """skip: the layer input is [upsample2(x) | skip] (x at half size, ldx channels)."""
             ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
             k = turn[0] % len(self.wstreams)
             turn[0] += 1
@@ -299,8 +304,13 @@ class UNet:
                 # gy (and every earlier write) is complete on the main stream before the
                 # weight-gradient stream reads it
                 self.wstreams[k].wait_stream(self.stream)
-            _ck(_lib.unet_conv3x3_wgrad(ptr(x), ldx, offx, ptr(gy), ldg, 0, ptr(g[name + ".w"]), ptr(g[name + ".b"]),
-                                        ptr(wp), wp.numel(), N, h, w, ci, co, self.ws[k]))
+            if skip is None:
+                _ck(_lib.unet_conv3x3_wgrad(ptr(x), ldx, offx, ptr(gy), ldg, 0, ptr(g[name + ".w"]),
+                                            ptr(g[name + ".b"]), ptr(wp), wp.numel(), N, h, w, ci, co, self.ws[k]))
+            else:
+                _ck(_lib.unet_conv3x3_wgrad_cat(ptr(x), ldx, offx, ldx, 1, ptr(skip), ci - ldx, 0, ptr(gy), ldg, 0,
+                                                ptr(g[name + ".w"]), ptr(g[name + ".b"]), ptr(wp), wp.numel(), N, h, w,
+                                                ci, co, self.ws[k]))
 
         def dgrad(name, gy, ldg, dx, lddx, h, w, mask=None, ldm=0, offm=0):
             ci, co = next((c_, o_) for n_, c_, o_ in self.layers if n_ == name)
@@ -318,24 +328,27 @@ class UNet:
                 h, w, c, cu = H >> lvl, W >> lvl, wd[lvl], wd[lvl + 1]
                 wgrad(f"d{lvl}b", b[f"d{lvl}a"], c, 0, b[f"gd{lvl}b"], c, h, w)
                 dgrad(f"d{lvl}b", b[f"gd{lvl}b"], c, b[f"gd{lvl}a"], c, h, w, mask=b[f"d{lvl}a"], ldm=c)
-                wgrad(f"d{lvl}a", b[f"cat{lvl}"], cu + c, 0, b[f"gd{lvl}a"], c, h, w)
-                dgrad(f"d{lvl}a", b[f"gd{lvl}a"], c, b[f"dcat{lvl}"], cu + c, h, w)
-                # gradient of the lower level's output, gated by its ReLU
                 if lvl + 1 < L - 1:
                     low, dlow = b[f"d{lvl + 1}b"], b[f"gd{lvl + 1}b"]
                 else:
                     low, dlow = b[f"e{lvl + 1}b"], b[f"ge{lvl + 1}b"]
-                _ck(_lib.unet_upsample2_bwd(ptr(b[f"dcat{lvl}"]), cu + c, 0, ptr(low), cu, 0, ptr(dlow), cu, 0, N,
+                wgrad(f"d{lvl}a", low, cu, 0, b[f"gd{lvl}a"], c, h, w, skip=b[f"e{lvl}b"])
+                # input gradient, split between the upsampled branch and the skip branch
+                _ck(_lib.unet_conv3x3_fwd_cat(ptr(b[f"gd{lvl}a"]), c, 0, c, 0, None, 0, 0,
+                                              ptr(self.wf16[f"d{lvl}a"]), None, ptr(b[f"dup{lvl}"]), cu, 0, cu,
+                                              ptr(b[f"dskip{lvl}"]), c, 0, None, 0, 0, N, h, w, c, cu + c, 0,
+                                              self.s))
+                # gradient of the lower level's output, gated by its ReLU
+                _ck(_lib.unet_upsample2_bwd(ptr(b[f"dup{lvl}"]), cu, 0, ptr(low), cu, 0, ptr(dlow), cu, 0, N,
                                             h // 2, w // 2, cu, self.s))
             # encoder, bottleneck first
             for lvl in reversed(range(L)):
                 h, w, c = H >> lvl, W >> lvl, wd[lvl]
                 if lvl < L - 1:
-                    cu = wd[lvl + 1]
-                    cat = b[f"cat{lvl}"]
                     # pooled-path gradient plus the skip-connection gradient, gated by e{lvl}b > 0
-                    _ck(_lib.unet_maxpool2_bwd(ptr(cat), cu + c, cu, ptr(b[f"dpool{lvl}"]), c, 0, ptr(b[f"dcat{lvl}"]),
-                                               cu + c, cu, ptr(b[f"ge{lvl}b"]), c, 0, 1, N, h, w, c, self.s))
+                    _ck(_lib.unet_maxpool2_bwd(ptr(b[f"e{lvl}b"]), c, 0, ptr(b[f"dpool{lvl}"]), c, 0,
+                                               ptr(b[f"dskip{lvl}"]), c, 0, ptr(b[f"ge{lvl}b"]), c, 0, 1, N, h, w, c,
+                                               self.s))
                 wgrad(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"ge{lvl}b"], c, h, w)
                 dgrad(f"e{lvl}b", b[f"ge{lvl}b"], c, b[f"ge{lvl}a"], c, h, w, mask=b[f"e{lvl}a"], ldm=c)
                 if lvl > 0:

@@ -57,6 +57,31 @@ def test_network_calls_validate_before_launching(lbm):
     assert lib.unet_conv3x3_fwd(buf, 12, 0, buf, None, buf, 16, 0, None, 0, 0, 1, 8, 8, 8, 16, 0, None) == -1
     assert lib.unet_conv3x3_fwd(buf, 8, 0, buf, None, buf, 16, 0, None, 0, 0, 1, 8, 8, 8, 16, 8, None) == -1
     assert "flags" in lib.unet_last_error().decode()
+    # two-tensor input and split output: channel ranges and the second tensors checked first
+    cat = lib.unet_conv3x3_fwd_cat
+    # arguments: x ld off C_x half, x2 ld off, w bias, y ld off C_y, y2 ld off, mask ld off, N H W C_in C_out flags
+    assert cat(buf, 64, 0, 104, 1, buf, 32, 0, buf, None, buf, 32, 0, 32, None, 0, 0, None, 0, 0, 1, 8, 8, 96, 32, 0,
+               None) == -1
+    assert "C_x" in lib.unet_last_error().decode()
+    assert cat(buf, 64, 0, 48, 1, buf, 48, 0, buf, None, buf, 32, 0, 32, None, 0, 0, None, 0, 0, 1, 8, 8, 96, 32, 0,
+               None) == -1
+    assert "of 32" in lib.unet_last_error().decode()
+    assert cat(buf, 64, 0, 64, 1, None, 32, 0, buf, None, buf, 32, 0, 32, None, 0, 0, None, 0, 0, 1, 8, 8, 96, 32, 0,
+               None) == -1
+    assert "x2" in lib.unet_last_error().decode()
+    assert cat(buf, 96, 0, 96, 0, buf, 32, 0, buf, None, buf, 32, 0, 32, None, 0, 0, None, 0, 0, 1, 8, 8, 96, 32, 0,
+               None) == -1
+    assert "x2 must be NULL" in lib.unet_last_error().decode()
+    assert cat(buf, 32, 0, 32, 0, None, 0, 0, buf, None, buf, 64, 0, 64, None, 0, 0, None, 0, 0, 1, 8, 8, 32, 96, 0,
+               None) == -1
+    assert "y2" in lib.unet_last_error().decode()
+    assert cat(buf, 32, 0, 32, 0, None, 0, 0, buf, None, buf, 64, 0, 64, buf, 16, 0, None, 0, 0, 1, 8, 8, 32, 96, 0,
+               None) == -1  # y2's ld below the 32 channels it receives
+    wcat = lib.unet_conv3x3_wgrad_cat
+    assert wcat(buf, 64, 0, 60, 1, buf, 36, 0, buf, 32, 0, buf, buf, buf, 1 << 30, 2, 64, 64, 96, 32, None) == -1
+    assert "C_x" in lib.unet_last_error().decode()
+    assert wcat(buf, 64, 0, 64, 1, None, 32, 0, buf, 32, 0, buf, buf, buf, 1 << 30, 2, 64, 64, 96, 32, None) == -1
+    assert "x2" in lib.unet_last_error().decode()
     nb = ctypes.c_size_t()
     assert lib.unet_wgrad_partial_bytes(2, 64, 64, 32, 32, ctypes.byref(nb)) == 0 and nb.value > 0
     assert lib.unet_conv3x3_wgrad(buf, 32, 0, buf, 32, 0, buf, buf, buf, nb.value - 1, 2, 64, 64, 32, 32, None) == -1

@@ -169,6 +169,106 @@ def test_conv3x3_weight_gradient(case):
     assert (np.abs(host(db) - db_ref) <= gamma(P) * bb + 1e-30).all()
 
 
+CAT_CASES = [  # N, H, W, C_x (upsampled from half size), C_skip, C_out
+    (2, 32, 32, 64, 32, 32),    # halo-tile form, 32 output channels, three channel blocks
+    (1, 32, 32, 128, 64, 64),   # halo-tile form, 64 output channels
+    (2, 16, 8, 64, 32, 32),     # LDS-staged form (rows of 8 pixels: no 16 x 16 tiles)
+    (3, 8, 8, 32, 16, 16),      # generic form: C_in = 48 (chunks straddle taps), 16 output channels
+    (1, 16, 16, 48, 32, 48),    # generic form: C_in = 80
+]
+
+
+def _upcat(low, skip):
+    """[upsample2(low) | skip], stored whole (the reference input of the two-tensor calls)."""
+    import torch
+    up = low.repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)
+    return torch.cat([up, skip], dim=3).contiguous()
+
+
+@pytest.mark.parametrize("case", CAT_CASES, ids=lambda c: "x".join(map(str, c)))
+def test_conv_of_upsampled_concatenation_equals_the_stored_concatenation(case):
+    """unet_conv3x3_fwd_cat with the input [upsample2(low) | skip] read from the two
+    tensors (low at half size) equals unet_conv3x3_fwd on that concatenation stored
+    whole, bitwise; and that result against the FP64 reference.  Then the input-gradient
+    form: the output split between two tensors equals the whole output, bitwise."""
+    import torch
+    N, H, W, cx, cs, co = case
+    ci = cx + cs
+    say(f"case: two-tensor convolution {case}")
+    u = lib()
+    low, skip = bf((N, H // 2, W // 2, cx), 30), bf((N, H, W, cs), 31)
+    w, bias = bf((co, 3, 3, ci), 32, 0.2), bf((co,), 33, 0.1)
+    lowd, skipd, wd = dev_bf16(low), dev_bf16(skip), dev_bf16(w)
+    biasd = dev_f32(bias)
+    cat = _upcat(lowd, skipd)
+    y_ref = torch.empty((N, H, W, co), dtype=torch.bfloat16, device="cuda")
+    y_cat = torch.full((N, H, W, co), 7.0, dtype=torch.bfloat16, device="cuda")
+    ck(u.library().unet_conv3x3_fwd(u.ptr(cat), ci, 0, u.ptr(wd), u.ptr(biasd), u.ptr(y_ref), co, 0, None, 0, 0, N, H,
+                                    W, ci, co, u.RELU, None))
+    ck(u.library().unet_conv3x3_fwd_cat(u.ptr(lowd), cx, 0, cx, 1, u.ptr(skipd), cs, 0, u.ptr(wd), u.ptr(biasd),
+                                        u.ptr(y_cat), co, 0, co, None, 0, 0, None, 0, 0, N, H, W, ci, co, u.RELU,
+                                        None))
+    torch.cuda.synchronize()
+    assert torch.equal(y_cat.view(torch.int16), y_ref.view(torch.int16))
+    xin = np.concatenate([np.repeat(np.repeat(low, 2, axis=1), 2, axis=2), skip], axis=3)
+    want = U.relu(U.conv3x3(xin, w, bias))
+    bound = gamma(9 * ci + 1) * (U.conv3x3(np.abs(xin), np.abs(w)) + np.abs(bias))
+    tol = 2.0 ** -7 * np.abs(want) + 2 * bound + 1e-38
+    assert (np.abs(host(y_cat) - want) <= tol).all()
+    # split output: the gradient convolution from co channels back to the ci of the two branches
+    g = dev_bf16(bf((N, H, W, co), 34))
+    wf = dev_bf16(bf((ci, 3, 3, co), 35, 0.2))
+    whole = torch.empty((N, H, W, ci), dtype=torch.bfloat16, device="cuda")
+    ya = torch.full((N, H, W, cx), 3.0, dtype=torch.bfloat16, device="cuda")
+    yb = torch.full((N, H, W, cs + 8), 3.0, dtype=torch.bfloat16, device="cuda")  # ld above its channels
+    ck(u.library().unet_conv3x3_fwd(u.ptr(g), co, 0, u.ptr(wf), None, u.ptr(whole), ci, 0, None, 0, 0, N, H, W, co, ci,
+                                    0, None))
+    ck(u.library().unet_conv3x3_fwd_cat(u.ptr(g), co, 0, co, 0, None, 0, 0, u.ptr(wf), None, u.ptr(ya), cx, 0, cx,
+                                        u.ptr(yb), cs + 8, 8, None, 0, 0, N, H, W, co, ci, 0, None))
+    torch.cuda.synchronize()
+    assert torch.equal(ya.view(torch.int16), whole[..., :cx].contiguous().view(torch.int16))
+    assert torch.equal(yb[..., 8:].contiguous().view(torch.int16), whole[..., cx:].contiguous().view(torch.int16))
+    assert bool((yb[..., :8] == 3.0).all())  # channels below the offset untouched
+
+
+@pytest.mark.parametrize("case", CAT_CASES + [(2, 16, 8, 64, 32, 64)], ids=lambda c: "x".join(map(str, c)))
+def test_weight_gradient_of_upsampled_concatenation_equals_the_stored_concatenation(case):
+    """unet_conv3x3_wgrad_cat with the layer input [upsample2(low) | skip] read from the
+    two tensors equals unet_conv3x3_wgrad on the concatenation stored whole, bitwise
+    (halo-tile, transposing-read and generic forms), and the FP64 reference."""
+    import ctypes
+    import torch
+    N, H, W, cx, cs, co = case
+    ci = cx + cs
+    say(f"case: two-tensor weight gradient {case}")
+    u = lib()
+    low, skip, g = bf((N, H // 2, W // 2, cx), 40), bf((N, H, W, cs), 41), bf((N, H, W, co), 42)
+    lowd, skipd, gd = dev_bf16(low), dev_bf16(skip), dev_bf16(g)
+    cat = _upcat(lowd, skipd)
+    nb = ctypes.c_size_t()
+    ck(u.library().unet_wgrad_partial_bytes(N, H, W, ci, co, ctypes.byref(nb)))
+    out = []
+    for two in (False, True):
+        part = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        dw = torch.full((co * 9 * ci,), 5.0, dtype=torch.float32, device="cuda")
+        db = torch.full((co,), 5.0, dtype=torch.float32, device="cuda")
+        if two:
+            ck(u.library().unet_conv3x3_wgrad_cat(u.ptr(lowd), cx, 0, cx, 1, u.ptr(skipd), cs, 0, u.ptr(gd), co, 0,
+                                                  u.ptr(dw), u.ptr(db), u.ptr(part), nb.value, N, H, W, ci, co, None))
+        else:
+            ck(u.library().unet_conv3x3_wgrad(u.ptr(cat), ci, 0, u.ptr(gd), co, 0, u.ptr(dw), u.ptr(db), u.ptr(part),
+                                              nb.value, N, H, W, ci, co, None))
+        torch.cuda.synchronize()
+        out.append((dw.clone(), db.clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    xin = np.concatenate([np.repeat(np.repeat(low, 2, axis=1), 2, axis=2), skip], axis=3)
+    dw_ref, db_ref = U.conv3x3_grad_weight(xin, g)
+    bw, bb = U.conv3x3_grad_weight(np.abs(xin), np.abs(g))
+    P = N * H * W
+    assert (np.abs(host(out[1][0]).reshape(co, 3, 3, ci) - dw_ref) <= gamma(P) * bw + 1e-30).all()
+    assert (np.abs(host(out[1][1]) - db_ref) <= gamma(P) * bb + 1e-30).all()
+
+
 @pytest.mark.parametrize("C", [8, 16, 24, 64])
 def test_pool_upsample_and_their_gradients(C):
     """Channel counts from one 16-byte group per pixel to eight, including an odd group
@@ -372,19 +472,15 @@ def test_unet_every_layer_teacher_forced(widths, hw):
     inp = b["x0"]
     for lvl in range(L):
         conv_check(f"e{lvl}a", inp, p[f"e{lvl}a.w"], p[f"e{lvl}a.b"], b[f"e{lvl}a"])
+        conv_check(f"e{lvl}b", b[f"e{lvl}a"], p[f"e{lvl}b.w"], p[f"e{lvl}b.b"], b[f"e{lvl}b"])
         if lvl < L - 1:
-            cu = wd[lvl + 1]
-            eb = b[f"cat{lvl}"][..., cu:]
-            conv_check(f"e{lvl}b", b[f"e{lvl}a"], p[f"e{lvl}b.w"], p[f"e{lvl}b.b"], eb)
-            assert np.array_equal(b[f"pool{lvl}"], U.maxpool2(eb))
+            assert np.array_equal(b[f"pool{lvl}"], U.maxpool2(b[f"e{lvl}b"]))
             inp = b[f"pool{lvl}"]
-        else:
-            conv_check(f"e{lvl}b", b[f"e{lvl}a"], p[f"e{lvl}b.w"], p[f"e{lvl}b.b"], b[f"e{lvl}b"])
     low = b[f"e{L - 1}b"]
+    cats = {}
     for lvl in reversed(range(L - 1)):
-        cu = wd[lvl + 1]
-        cat = b[f"cat{lvl}"]
-        assert np.array_equal(cat[..., :cu], U.upsample2(low))
+        # the decoder input [upsample2(lower level) | skip], never stored on the GPU
+        cat = cats[lvl] = np.concatenate([U.upsample2(low), b[f"e{lvl}b"]], axis=3)
         conv_check(f"d{lvl}a", cat, p[f"d{lvl}a.w"], p[f"d{lvl}a.b"], b[f"d{lvl}a"])
         conv_check(f"d{lvl}b", b[f"d{lvl}a"], p[f"d{lvl}b.w"], p[f"d{lvl}b.b"], b[f"d{lvl}b"])
         low = b[f"d{lvl}b"]
@@ -406,17 +502,17 @@ def test_unet_every_layer_teacher_forced(widths, hw):
         cu, c = wd[lvl + 1], wd[lvl]
         wgrad_check(f"d{lvl}b", b[f"d{lvl}a"], b[f"gd{lvl}b"])
         dgrad_check(f"dgrad d{lvl}b", b[f"gd{lvl}b"], p[f"d{lvl}b.w"], b[f"gd{lvl}a"], gate=b[f"d{lvl}a"])
-        wgrad_check(f"d{lvl}a", b[f"cat{lvl}"], b[f"gd{lvl}a"])
-        dgrad_check(f"dgrad d{lvl}a", b[f"gd{lvl}a"], p[f"d{lvl}a.w"], b[f"dcat{lvl}"])
+        wgrad_check(f"d{lvl}a", cats[lvl], b[f"gd{lvl}a"])
+        dcat = np.concatenate([b[f"dup{lvl}"], b[f"dskip{lvl}"]], axis=3)
+        dgrad_check(f"dgrad d{lvl}a", b[f"gd{lvl}a"], p[f"d{lvl}a.w"], dcat)
         lowv, dlow = (b[f"d{lvl + 1}b"], b[f"gd{lvl + 1}b"]) if lvl + 1 < L - 1 else (b[f"e{L - 1}b"], b[f"ge{L - 1}b"])
-        want = U.relu_grad(U.upsample2_grad(b[f"dcat{lvl}"][..., :cu]), lowv)
-        _within_bf16(dlow, want, gamma(4) * U.upsample2_grad(ab(b[f"dcat{lvl}"][..., :cu])), f"upsample grad {lvl}")
+        want = U.relu_grad(U.upsample2_grad(b[f"dup{lvl}"]), lowv)
+        _within_bf16(dlow, want, gamma(4) * U.upsample2_grad(ab(b[f"dup{lvl}"])), f"upsample grad {lvl}")
     for lvl in reversed(range(L)):
         c = wd[lvl]
         if lvl < L - 1:
-            cu = wd[lvl + 1]
-            eb = b[f"cat{lvl}"][..., cu:]
-            want = U.relu_grad(U.maxpool2_grad(eb, b[f"dpool{lvl}"]) + b[f"dcat{lvl}"][..., cu:], eb)
+            eb = b[f"e{lvl}b"]
+            want = U.relu_grad(U.maxpool2_grad(eb, b[f"dpool{lvl}"]) + b[f"dskip{lvl}"], eb)
             _within_bf16(b[f"ge{lvl}b"], want, gamma(2) * ab(want), f"pool grad {lvl}")
         wgrad_check(f"e{lvl}b", b[f"e{lvl}a"], b[f"ge{lvl}b"])
         dgrad_check(f"dgrad e{lvl}b", b[f"ge{lvl}b"], p[f"e{lvl}b.w"], b[f"ge{lvl}a"], gate=b[f"e{lvl}a"])
