@@ -165,6 +165,16 @@ int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout
                   float* dhb, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W,
                   int32_t C, int32_t K, void* stream);
 
+/* unet_head_fwd with a target followed by unet_head_bwd, in one pass over d (training):
+ * out, dout, loss, g, dhw and dhb as those two calls define them, with the same
+ * partials size.  The K outputs of a pixel are summed in another order (8 channels per
+ * lane, then across lanes), so out and what follows from it may differ from the two
+ * calls in the last bits of FP32.  C / 8 must be a power of two dividing 256. */
+int unet_head_train(const void* d, int32_t ldd, const float* hw, const float* hb, const float* rin,
+                    const float* target, float* out, float* dout, float* loss, void* g, float* dhw,
+                    float* dhb, void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W,
+                    int32_t C, int32_t K, void* stream);
+
 /* Adam step t >= 1 on n FP32 parameters: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).  p16 (nullable) receives the
  * bfloat16 rounding of the updated p. */

@@ -1634,6 +1634,108 @@ __global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ld
     }
 }
 
+// Forward and backward of the head in one pass, for training.  Per pixel: the K outputs
+// s_k = hw_k . d + hb_k + rin_k, dout_k = 2 (s_k - target_k) / (K P) and the gradient of d,
+// g = sum_k dout_k hw_k where d > 0 (the ReLU of the last convolution).  Per workgroup:
+// the sums of dout_k d and of dout_k (weight and bias gradients) combined as in
+// k_head_bwd, in rows part[b][K (C + 1)], and the sum of (s_k - target_k)^2 in
+// lpart[b].  Thread layout of k_head_bwd: the C / 8 channel groups of a pixel on
+// consecutive lanes, each with its 8 products per output, summed across the pixel's
+// lanes by a fixed xor butterfly (C / 8 a power of two).  d is read once where the two
+// separate passes read it twice, and dout is not read back.
+template <int KK>
+__global__ void __launch_bounds__(kHeadBlock) k_head_train(const bf16_t* d, int ldd, const float* hw, const float* hb,
+                                                           const float* rin, const float* target, float* out,
+                                                           float* dout, bf16_t* g, float* part, float* lpart, int C,
+                                                           int P) {
+    constexpr int K = KK;
+    __shared__ float red[kHeadBlock * 9];
+    const int G = C >> 3, t = threadIdx.x;
+    const int cg = t % G, c = 8 * cg;
+    const int per_block = kHeadBlock / G;
+    const int p0 = blockIdx.x * per_block + t / G, stride = gridDim.x * per_block;
+    const float scale = 2.f / (float)((size_t)K * P);
+    float w[KK][8], acc[KK][8], bs[KK], r2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        bs[k] = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            acc[k][j] = 0.f;
+            w[k][j] = hw[k * C + c + j];
+        }
+    }
+    // two pixels per iteration, every load of both issued before any arithmetic
+    auto pixel = [&](int p, const float (&v)[8], const float (&ri)[KK], const float (&tg)[KK]) {
+        float dp[KK], o[8];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            float sk = 0.f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sk += w[k][j] * v[j];
+            // the pixel's G lanes are consecutive and G-aligned: partners are in the group
+            for (int m = 1; m < G; m <<= 1) sk += __shfl_xor(sk, m, 64);
+            sk += hb[k] + ri[k];
+            const float r = sk - tg[k];
+            dp[k] = scale * r;
+            if (cg == 0) {
+                out[(size_t)k * P + p] = sk;
+                dout[(size_t)k * P + p] = dp[k];
+                r2 += r * r;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float sg = 0.f;
+#pragma unroll
+            for (int k = 0; k < KK; ++k) sg += dp[k] * w[k][j];
+            o[j] = v[j] > 0.f ? sg : 0.f;
+#pragma unroll
+            for (int k = 0; k < KK; ++k) acc[k][j] += dp[k] * v[j];
+        }
+        st16(g + (size_t)p * C + c, pack8(o));
+#pragma unroll
+        for (int k = 0; k < KK; ++k) bs[k] += dp[k];
+    };
+    for (int p = p0; p < P; p += 2 * stride) {
+        const int pb = p + stride;
+        const bool two = pb < P;  // the same for the pixel's G lanes
+        float va[8], vb[8], ra[KK], ta[KK], rb[KK], tb[KK];
+        unpack8(ld16(d + (size_t)p * ldd + c), va);
+        unpack8(ld16(d + (size_t)(two ? pb : p) * ldd + c), vb);
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            ra[k] = rin[(size_t)k * P + p];
+            ta[k] = target[(size_t)k * P + p];
+            rb[k] = two ? rin[(size_t)k * P + pb] : 0.f;
+            tb[k] = two ? target[(size_t)k * P + pb] : 0.f;
+        }
+        pixel(p, va, ra, ta);
+        if (two) pixel(pb, vb, rb, tb);
+    }
+    const float lb = block_sum(r2, red);
+    if (t == 0) lpart[blockIdx.x] = lb;
+    const int m = K * (C + 1);
+    float* row = part + (size_t)blockIdx.x * m;
+    for (int k = 0; k < K; ++k) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[t * 9 + j] = acc[k][j];
+        red[t * 9 + 8] = bs[k];
+        __syncthreads();
+        for (int e = t; e < C + 1; e += kHeadBlock) {
+            float sm = 0.f;
+            if (e < C) {
+                const int eg = e >> 3, ej = e & 7;
+                for (int u = eg; u < kHeadBlock; u += G) sm += red[u * 9 + ej];
+            } else {
+                for (int u = 0; u < kHeadBlock; u += G) sm += red[u * 9 + 8];
+            }
+            row[k * (C + 1) + e] = sm;
+        }
+    }
+}
+
 // out[j] = sum over blocks of part[b][j] (j < m) times scale, one workgroup per j:
 // thread t sums rows t, t + 256, ... in order, then a fixed tree combines the 256
 // partial sums (deterministic).  With stride > 0 the entries j % stride == stride - 1
@@ -2259,6 +2361,48 @@ int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout
     const int m = K * (C + 1);
     hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(256), 0, s, static_cast<const float*>(partials), blocks, m,
                        1.0f, dhw, dhb, C + 1);
+    return launched("head reduce launch");
+}
+
+int unet_head_train(const void* d, int32_t ldd, const float* hw, const float* hb, const float* rin,
+                    const float* target, float* out, float* dout, float* loss, void* g, float* dhw, float* dhb,
+                    void* partials, size_t partial_bytes, int32_t N, int32_t H, int32_t W, int32_t C, int32_t K,
+                    void* stream) {
+    size_t need = 0;
+    int r;
+    if ((r = unet_head_partial_bytes(N, H, W, C, K, &need))) return r;
+    if ((r = check_tensor("d", d, ldd, 0, C, false)) || (r = check_tensor("g", g, C, 0, C, false))) return r;
+    if (!hw || !hb || !rin || !target || !out || !dout || !loss || !dhw || !dhb || !partials || partial_bytes < need)
+        return fail(UNET_EINVAL, "head train: NULL argument or partials below %zu bytes", need);
+    const int G = C / 8;
+    if (kHeadBlock % G != 0 || (G & (G - 1)))
+        return fail(UNET_EINVAL, "head train: C / 8 must be a power of two dividing %d (got C = %d)", kHeadBlock, C);
+    const int P = N * H * W;
+    // weight rows then one loss entry per workgroup: within the partials size, which
+    // allows (kHeadBlock / 64) rows per forward workgroup
+    const int blocks = std::min((P + kHeadBlock - 1) / kHeadBlock, kHeadBwdBlocks);
+    const int m = K * (C + 1);
+    float* part = static_cast<float*>(partials);
+    float* lpart = part + (size_t)blocks * m;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto* gb = static_cast<bf16_t*>(g);
+    const auto* db = static_cast<const bf16_t*>(d);
+    switch (K) {
+        case 1: hipLaunchKernelGGL(k_head_train<1>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
+                                   out, dout, gb, part, lpart, C, P); break;
+        case 2: hipLaunchKernelGGL(k_head_train<2>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
+                                   out, dout, gb, part, lpart, C, P); break;
+        case 3: hipLaunchKernelGGL(k_head_train<3>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
+                                   out, dout, gb, part, lpart, C, P); break;
+        default: hipLaunchKernelGGL(k_head_train<4>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
+                                    out, dout, gb, part, lpart, C, P); break;
+    }
+    if ((r = launched("head train launch"))) return r;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, static_cast<const float*>(lpart), blocks, 1,
+                       1.0f / (float)((size_t)K * P), loss, (float*)nullptr, 0);
+    if ((r = launched("loss reduce launch"))) return r;
+    hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(256), 0, s, static_cast<const float*>(part), blocks, m, 1.0f,
+                       dhw, dhb, C + 1);
     return launched("head reduce launch");
 }
 

@@ -29,7 +29,8 @@ _P, _I, _F, _V, _S = ctypes.POINTER, ctypes.c_int32, ctypes.c_float, ctypes.c_vo
 EXPORTED = ["unet_conv3x3_fwd", "unet_conv3x3_fwd_cat", "unet_flip_weights", "unet_flip_weights_many",
             "unet_wgrad_partial_bytes", "unet_conv3x3_wgrad", "unet_conv3x3_wgrad_cat", "unet_conv3x3_wgrad_noalloc",
             "unet_maxpool2_fwd", "unet_maxpool2_bwd", "unet_upsample2_fwd", "unet_upsample2_bwd",
-            "unet_prepare_input", "unet_output_fields", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd", "unet_adam",
+            "unet_prepare_input", "unet_output_fields", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd",
+            "unet_head_train", "unet_adam",
             "unet_to_bf16", "unet_to_f32", "unet_last_error"]
 
 RELU, OUT_F32 = 1, 2
@@ -55,6 +56,7 @@ _lib.unet_output_fields.argtypes = [_V, _I, _V, _V, _V, _D, _V, _V, _I, _I, _I, 
 _lib.unet_head_partial_bytes.argtypes = [_I, _I, _I, _I, _I, _P(_S)]
 _lib.unet_head_fwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
 _lib.unet_head_bwd.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
+_lib.unet_head_train.argtypes = [_V, _I, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V, _S, _I, _I, _I, _I, _I, _V]
 _lib.unet_adam.argtypes = [_V, _V, _V, _V, _V, _S, _F, _F, _F, _F, _I, _V]
 _lib.unet_to_bf16.argtypes = [_V, _V, _S, _V]
 _lib.unet_to_f32.argtypes = [_V, _V, _S, _V]
@@ -134,6 +136,7 @@ class UNet:
         p["head.b"] = np.zeros(self.K)
         self.load_params(p)
         self._shape = None
+        self._head_done = False
 
     # -- parameters ------------------------------------------------------------------
     def _f32(self, a):
@@ -244,12 +247,14 @@ class UNet:
         _ck(_lib.unet_conv3x3_fwd(ptr(x), ldx, offx, ptr(self.w16[name]), ptr(self.p[name + ".b"]), ptr(y), ldy,
                                   offy, ptr(mask), ldm, offm, N, h, w, ci, co, flags, self.s))
 
-    def forward(self, rho, T, rho_v, rho_l, T0, cond, target_rho=None, target_T=None):
+    def forward(self, rho, T, rho_v, rho_l, T0, cond, target_rho=None, target_T=None, train=False):
         """rho, T: FP64 [N, H, W] device fields (T may be None: T = T0); rho_v, rho_l, T0,
         cond: FP64 [N] device tensors (normalisation and the conditioning channel);
         target_rho, target_T: FP64 [N, H, W] device fields or None.  Returns the
         normalised prediction (FP32 [K, N, H, W], a view into the model's buffer) and,
-        with a target, the loss tensor."""
+        with a target, the loss tensor.  train (with a target): the head's backward pass
+        runs here too, in the same pass over the last activation, and backward() then
+        starts below the head."""
         torch = self.torch
         N, H, W = rho.shape
         self._alloc(N, H, W)
@@ -282,9 +287,17 @@ class UNet:
                 self._conv(f"d{lvl}b", b[f"d{lvl}a"], c, 0, b[f"d{lvl}b"], c, 0, N, h, w)
                 low = b[f"d{lvl}b"]
             tgt = b["target"] if target_rho is not None else None
-            _ck(_lib.unet_head_fwd(ptr(low), wd[0], ptr(self.p["head.w"]), ptr(self.p["head.b"]), ptr(b["rin"]),
-                                   ptr(tgt), ptr(b["out"]), ptr(b["dout"]), ptr(b["loss"]), ptr(b["hpart"]),
-                                   b["hpart"].numel(), N, H, W, wd[0], self.K, self.s))
+            self._head_done = bool(train and tgt is not None)
+            if self._head_done:
+                g = self.g
+                _ck(_lib.unet_head_train(ptr(low), wd[0], ptr(self.p["head.w"]), ptr(self.p["head.b"]), ptr(b["rin"]),
+                                         ptr(tgt), ptr(b["out"]), ptr(b["dout"]), ptr(b["loss"]), ptr(b["gd0b"]),
+                                         ptr(g["head.w"]), ptr(g["head.b"]), ptr(b["hpart"]), b["hpart"].numel(),
+                                         N, H, W, wd[0], self.K, self.s))
+            else:
+                _ck(_lib.unet_head_fwd(ptr(low), wd[0], ptr(self.p["head.w"]), ptr(self.p["head.b"]), ptr(b["rin"]),
+                                       ptr(tgt), ptr(b["out"]), ptr(b["dout"]), ptr(b["loss"]), ptr(b["hpart"]),
+                                       b["hpart"].numel(), N, H, W, wd[0], self.K, self.s))
         return (b["out"], b["loss"]) if target_rho is not None else b["out"]
 
     def backward(self):
@@ -320,9 +333,11 @@ class UNet:
 
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             top = b["d0b"]
-            _ck(_lib.unet_head_bwd(ptr(top), wd[0], ptr(self.p["head.w"]), ptr(b["dout"]), ptr(b["gd0b"]),
-                                   ptr(g["head.w"]), ptr(g["head.b"]), ptr(b["hpart"]), b["hpart"].numel(), N, H, W,
-                                   wd[0], self.K, self.s))
+            if not self._head_done:
+                _ck(_lib.unet_head_bwd(ptr(top), wd[0], ptr(self.p["head.w"]), ptr(b["dout"]), ptr(b["gd0b"]),
+                                       ptr(g["head.w"]), ptr(g["head.b"]), ptr(b["hpart"]), b["hpart"].numel(), N, H,
+                                       W, wd[0], self.K, self.s))
+            self._head_done = False
             # decoder, top level first
             for lvl in range(L - 1):
                 h, w, c, cu = H >> lvl, W >> lvl, wd[lvl], wd[lvl + 1]
@@ -374,7 +389,7 @@ class UNet:
             _ck(_lib.unet_flip_weights_many(*self._flip, self.s))
 
     def train_step(self, rho0, T0f, rhoT, TT, rho_v, rho_l, T0, cond, lr=1e-3):
-        _, loss = self.forward(rho0, T0f, rho_v, rho_l, T0, cond, rhoT, TT)
+        _, loss = self.forward(rho0, T0f, rho_v, rho_l, T0, cond, rhoT, TT, train=True)
         self.backward()
         self.adam_step(lr)
         return loss

@@ -373,6 +373,81 @@ def test_head_loss_adam_and_conversions():
     assert np.array_equal(host(vf), U.bf16_round(host(v)))
 
 
+@pytest.mark.parametrize("case", [(2, 16, 16, 32, 2), (3, 32, 64, 16, 1), (16, 256, 256, 32, 2), (1, 8, 8, 64, 2)],
+                         ids=lambda c: "x".join(map(str, c)))
+def test_head_train_against_the_reference_and_the_two_passes(case):
+    """unet_head_train (forward and backward of the head in one pass) against the FP64
+    reference (outputs within the FP32 bound of their sums, loss, dout, the gated
+    gradient within a bfloat16 step, weight and bias gradients) and against
+    unet_head_fwd + unet_head_bwd, which sum each output in another order: agreement to
+    FP32 rounding.  The 16 x 256^2 case is the training batch (several pixels per thread,
+    2048 workgroups); the others leave threads without pixels."""
+    import ctypes
+    import torch
+    N, H, W, C, K = case
+    say(f"case: fused head {case}")
+    u = lib()
+    L = u.library()
+    d = bf((N, H, W, C), 50)                        # both signs: the ReLU gate is exercised
+    hw, hb = bf((K, C), 51), bf((K,), 52, 0.5)
+    rin, tgt = bf((N, H, W, K), 53), bf((N, H, W, K), 54)
+    planes = lambda a: np.ascontiguousarray(np.moveaxis(a, 3, 0))  # noqa: E731
+    nb = ctypes.c_size_t()
+    ck(L.unet_head_partial_bytes(N, H, W, C, K, ctypes.byref(nb)))
+    dd, hwd, hbd = dev_bf16(d), dev_f32(hw), dev_f32(hb)
+    rind, tgtd = dev_f32(planes(rin)), dev_f32(planes(tgt))
+    res = []
+    for fused in (False, True):
+        part = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        out = torch.empty((K, N, H, W), dtype=torch.float32, device="cuda")
+        dout = torch.empty_like(out)
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        g = torch.empty((N, H, W, C), dtype=torch.bfloat16, device="cuda")
+        dhw = torch.empty(K * C, dtype=torch.float32, device="cuda")
+        dhb = torch.empty(K, dtype=torch.float32, device="cuda")
+        if fused:
+            ck(L.unet_head_train(u.ptr(dd), C, u.ptr(hwd), u.ptr(hbd), u.ptr(rind), u.ptr(tgtd), u.ptr(out),
+                                 u.ptr(dout), u.ptr(loss), u.ptr(g), u.ptr(dhw), u.ptr(dhb), u.ptr(part), nb.value,
+                                 N, H, W, C, K, None))
+        else:
+            ck(L.unet_head_fwd(u.ptr(dd), C, u.ptr(hwd), u.ptr(hbd), u.ptr(rind), u.ptr(tgtd), u.ptr(out),
+                               u.ptr(dout), u.ptr(loss), u.ptr(part), nb.value, N, H, W, C, K, None))
+            ck(L.unet_head_bwd(u.ptr(dd), C, u.ptr(hwd), u.ptr(dout), u.ptr(g), u.ptr(dhw), u.ptr(dhb), u.ptr(part),
+                               nb.value, N, H, W, C, K, None))
+        res.append({k: host(v) for k, v in dict(out=out, dout=dout, loss=loss, g=g, dhw=dhw, dhb=dhb).items()})
+    two, one = res
+    out_ref = U.head(d, hw, hb, rin)
+    loss_ref, dout_ref = U.mse(out_ref, tgt)
+    P = N * H * W
+    bound = planes(gamma(C + 2) * (np.abs(d) @ np.abs(hw).T + np.abs(hb) + np.abs(rin)))
+    assert (np.abs(planes(out_ref) - one["out"]) <= bound).all()
+    assert one["loss"][0] == pytest.approx(loss_ref, rel=1e-5)
+    # dout = 2 (out - target) / (K P): the output's error carries over, scaled
+    dtol = 2.0 / (K * P) * bound * 1.001 + 4 * 2.0 ** -24 * np.abs(planes(dout_ref)) + 1e-30
+    assert (np.abs(one["dout"] - planes(dout_ref)) <= dtol).all()
+    dh = np.moveaxis(one["dout"], 0, 3)
+    want = U.bf16_round((dh @ hw) * (d > 0))
+    acc = gamma(K) * (np.abs(dh) @ np.abs(hw))
+    assert (np.abs(one["g"] - want) <= np.abs(want) * 2.0 ** -7 + 2 * acc + 1e-30).all()
+    wref = dh.reshape(-1, K).T @ d.reshape(-1, C)
+    wbound = gamma(P) * (np.abs(dh).reshape(-1, K).T @ np.abs(d).reshape(-1, C))
+    assert (np.abs(one["dhw"].reshape(K, C) - wref) <= wbound + 1e-30).all()
+    bbound = gamma(P) * np.abs(dh).reshape(-1, K).sum(axis=0)
+    assert (np.abs(one["dhb"] - dh.reshape(-1, K).sum(axis=0)) <= bbound + 1e-30).all()
+    # against the two separate passes: each within its bound of the exact values, and
+    # what follows from dout within the effect of the two douts' difference
+    assert (np.abs(one["out"] - two["out"]) <= 2 * bound).all()
+    assert (np.abs(one["dout"] - two["dout"]) <= 2 * dtol).all()
+    assert one["loss"][0] == pytest.approx(two["loss"][0], rel=1e-5)
+    ddiff = np.abs(np.moveaxis(one["dout"] - two["dout"], 0, 3)).reshape(-1, K)
+    assert (np.abs(one["dhw"] - two["dhw"]).reshape(K, C) <= 2 * wbound + ddiff.T @ np.abs(d).reshape(-1, C)
+            + 1e-30).all()
+    assert (np.abs(one["dhb"] - two["dhb"]) <= 2 * bbound + ddiff.sum(axis=0) + 1e-30).all()
+    gdiff = (ddiff @ np.abs(hw)).reshape(N, H, W, C)
+    step = np.maximum(np.abs(two["g"]), np.abs(one["g"])) * 2.0 ** -7
+    assert (np.abs(one["g"] - two["g"]) <= step + 2 * acc + gdiff + 1e-30).all()
+
+
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
