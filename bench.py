@@ -351,42 +351,44 @@ def unet_step_flops(widths, in_channels, N, H, W) -> float:
 def unet_step_bound_ms(widths, in_channels, N, H, W, outputs=2) -> float:
     """Lower bound on one training step's time, pass by pass: each pass takes at least
     the longer of its dense FLOPs at the bf16 MFMA peak and its compulsory HBM bytes
-    (bfloat16 activations and gradients read and written once) at the HBM peak.  A
-    decoder convolution's input is [upsample2(lower level) | skip], read as the two
-    tensors (the lower level at half size); its input gradient is written whole and then
-    summed 2x2 by the upsampling gradient.  The convolutions' weights and partial sums,
-    and launch gaps, are left out."""
+    (bfloat16 activations and gradients read and written once) at the HBM peak, with the
+    passes as the step runs them: a decoder convolution reads [upsample2(lower level) |
+    skip] as the two tensors (the lower level at half size), and its input gradient
+    stores the skip branch's gradient and, through the upsampling's gradient, the lower
+    level's (at half size, gated by it); the encoder's second convolution also stores
+    its 2x2 max pooling.  The convolutions' weights and partial sums, and launch gaps,
+    are left out."""
     from paper_2106_01557_amd import unet
     peak_f, peak_b = PEAK_BF16_TFLOPS * 1e12, PEAK_HBM_GBS * 1e9
+    L = len(widths)
     t = 0.0
     for name, ci, co in unet.conv_layers(widths, in_channels):
         lvl = int(name[1])
         P = N * (H >> lvl) * (W >> lvl)
         fl = 2.0 * P * 9 * ci * co
-        io = 2.0 * P * (ci + co)
-        if name[0] == "d" and name[2] == "a":                    # [upsample2(lower) | skip] input
+        pass_t = lambda nbytes: max(fl / peak_f, nbytes / peak_b)  # noqa: E731
+        if name[0] == "d" and name[2] == "a":                    # input [upsample2(lower) | skip]
             cu = widths[lvl + 1]
             xin = 2.0 * (P // 4 * cu + P * (ci - cu))
-            t += max(fl / peak_f, (xin + 2.0 * P * co) / peak_b)     # forward
-            t += max(fl / peak_f, io / peak_b)                       # input gradient, written whole
-            t += max(fl / peak_f, (xin + 2.0 * P * co) / peak_b)     # weight gradient
+            t += pass_t(xin + 2.0 * P * co)                                    # forward
+            t += pass_t(2.0 * P * co + 2.0 * P * (ci - cu) + 4.0 * (P // 4) * cu)  # input gradient
+            t += pass_t(xin + 2.0 * P * co)                                    # weight gradient
             continue
-        t += max(fl / peak_f, io / peak_b)                       # forward
-        if name != "e0a":                                          # input gradient (the
-            mask = 2.0 * P * ci if name.endswith("b") else 0.0    # b layers' ReLU mask)
-            t += max(fl / peak_f, (io + mask) / peak_b)
-        t += max(fl / peak_f, io / peak_b)                       # weight gradient
+        io = 2.0 * P * (ci + co)
+        pooled = 2.0 * (P // 4) * co if (name[0] == "e" and name[2] == "b" and lvl < L - 1) else 0.0
+        t += pass_t(io + pooled)                                 # forward (+ its pooling)
+        if name != "e0a":                                        # input gradient (the b layers
+            mask = 2.0 * P * ci if name.endswith("b") else 0.0  # read their ReLU mask)
+            t += pass_t(io + mask)
+        t += pass_t(io)                                          # weight gradient
     bw = 0.0
-    for lvl in range(len(widths) - 1):
-        c, cu = widths[lvl], widths[lvl + 1]
+    for lvl in range(L - 1):
+        c = widths[lvl]
         P = N * (H >> lvl) * (W >> lvl)
-        bw += 2.0 * (P * c + P // 4 * c)                 # max pool forward
-        bw += 2.0 * (3 * P * c + P // 4 * c)             # max pool backward (x, skip gradient, dx; dy)
-        bw += 2.0 * (P * cu + 2 * (P // 4) * cu)         # upsample backward (gradient, gate; dx)
+        bw += 2.0 * (3 * P * c + P // 4 * c)             # max pool gradient (x, skip gradient, dx; dy)
     P0, c0 = N * H * W, widths[0]
     bw += 2 * (8.0 * P0 * 2 + 2.0 * P0 * in_channels + 4.0 * P0 * 2)   # inputs and targets prepared
-    bw += 2.0 * P0 * c0 + 4.0 * P0 * 2 * 2 + 4.0 * P0 * outputs * 2   # head forward and loss
-    bw += 2.0 * P0 * c0 * 2 + 4.0 * P0 * outputs                        # head backward
+    bw += 2.0 * P0 * c0 * 2 + 4.0 * P0 * 2 * 2 + 4.0 * P0 * outputs * 2  # head forward and backward in one pass
     nparam = sum(9 * ci * co + co for _, ci, co in unet.conv_layers(widths, in_channels))
     bw += nparam * (4 * 4 + 3 * 4 + 2 + 2 * 2)           # Adam (p, g, m, v in; p, m, v, bf16 out) and flips
     return (t + bw / peak_b) * 1e3

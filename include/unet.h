@@ -19,7 +19,9 @@
  *  - Every pointer is device memory owned by the caller; nothing is allocated.
  *    Calls are asynchronous on `stream` (a hipStream_t; NULL = null stream).
  *  - Returns 0 on success, UNET_EINVAL (-1) for a bad argument (checked before any
- *    launch), UNET_EHIP (-3) when a launch fails; unet_last_error() explains.
+ *    launch), UNET_ESHAPE (-2) when a fused call does not cover valid arguments of that
+ *    shape (nothing launched; the separate calls it replaces do), UNET_EHIP (-3) when a
+ *    launch fails; unet_last_error() explains.
  */
 #ifndef UNET_H
 #define UNET_H
@@ -33,6 +35,7 @@ extern "C" {
 
 #define UNET_OK 0
 #define UNET_EINVAL (-1)
+#define UNET_ESHAPE (-2)
 #define UNET_EHIP (-3)
 
 /* y = epilogue(conv3x3(x, w) + bias): y[n,p,o] = bias[o] + sum_{t,i} w[o,t,i] x[n,p+off_t,i].
@@ -64,6 +67,32 @@ int unet_conv3x3_fwd_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, 
                          void* y, int32_t ldy, int32_t offy, int32_t C_y, void* y2, int32_t ldy2,
                          int32_t offy2, const void* mask, int32_t ldm, int32_t offm, int32_t N, int32_t H,
                          int32_t W, int32_t C_in, int32_t C_out, int32_t flags, void* stream);
+
+/* unet_conv3x3_fwd (bfloat16 output, no mask) followed by unet_maxpool2_fwd of its
+ * output, in one pass: y as unet_conv3x3_fwd stores it and yp ([N,H/2,W/2] x C_out, its
+ * own ld/off) bitwise as the pooling call computes it from y (the encoder's convolution
+ * before the U-Net's 2x2 max pooling).  UNET_ESHAPE unless H, W >= 16 and C_in, C_out
+ * are multiples of 32; UNET_EINVAL for UNET_OUT_F32. */
+int unet_conv3x3_fwd_pool(const void* x, int32_t ldx, int32_t offx, const void* w, const float* bias,
+                          void* y, int32_t ldy, int32_t offy, void* yp, int32_t ldyp, int32_t offyp,
+                          int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out, int32_t flags,
+                          void* stream);
+
+/* Input gradient of the U-Net decoder's convolution, whose input is [upsample2(low) |
+ * skip], through to the lower level: dx = conv3x3(g, wf) (C_g -> C_in channels, wf the
+ * flipped weights); channels [C_low, C_in) are the skip branch's gradient, stored in
+ * dskip ([N,H,W] x (C_in - C_low)); channels [0, C_low) go through the upsampling's
+ * gradient and the lower level's ReLU: the sum over each 2x2 block, zeroed where
+ * low <= 0, stored in dlow ([N,H/2,W/2] x C_low; low the same shape).  Bitwise the
+ * result of unet_conv3x3_fwd_cat with the output split at C_low followed by
+ * unet_upsample2_bwd, without the full-size gradient of the upsampled branch ever
+ * being stored.  UNET_ESHAPE unless H, W >= 16, C_g and C_in are multiples of 32 and
+ * C_low a multiple of the kernel's output-channel width (64 when C_g != 32 and
+ * C_in % 64 == 0, else 32). */
+int unet_conv3x3_bwd_upcat(const void* g, int32_t ldg, int32_t offg, const void* wf, void* dlow,
+                           int32_t lddl, int32_t offdl, const void* low, int32_t ldlow, int32_t offlow,
+                           int32_t C_low, void* dskip, int32_t ldds, int32_t offds, int32_t N, int32_t H,
+                           int32_t W, int32_t C_g, int32_t C_in, void* stream);
 
 /* wf[i][t][o] = w[o][8-t][i]: the weights of the input-gradient convolution
  * (dx = conv3x3_fwd(g, wf) with C_in and C_out exchanged). */

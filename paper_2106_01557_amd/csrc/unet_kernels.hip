@@ -86,7 +86,13 @@ struct ConvArgs {
     void* y;              // offset applied (elements of the output type)
     void* y2;             // offset applied (channels ysplit ..)
     const bf16_t* mask;   // nullable, offset applied
-    int ldx, ldx2, ldy, ldy2, ldm;
+    // 2x2 work on the output tile (k_conv_halo only): down = 1 also stores the 2x2 max
+    // pooling of the stored output to yp (half size); down = 2 stores, for the output
+    // channels below ysplit, the upsampling gradient (2x2 sums, zeroed where gate <= 0)
+    // to y at half size instead of the full-size output
+    void* yp;
+    const bf16_t* gate;
+    int ldx, ldx2, ldy, ldy2, ldm, ldyp, ldgt, down;
     int split, half, ysplit;
     int lh, lw;           // log2 H, log2 W
     int P;                // N H W
@@ -420,13 +426,15 @@ __global__ void __launch_bounds__(256) k_conv_lds(const ConvArgs a) {
     }
 }
 
-// Epilogue of a 16 x 16 pixel tile x 32 output channels (the same steps as k_conv_halo's
-// own): bias, ReLU, mask, then FP32 stores, or bfloat16 through the staging tile Os
-// (256 rows of 40) as 16-byte stores.
-template <bool kF32, int MT, int NT>
+// Epilogue of a 16 x 16 pixel tile x BN output channels (k_conv_halo, k_conv_halo8):
+// bias, ReLU, mask, then FP32 stores, or bfloat16 through the staging tile Os (256 rows
+// of BN + 8) as 16-byte stores, and with a.down the 2x2 work of ConvArgs on the staged
+// tile (the tile holds whole 2x2 blocks: 16 x 16 tiles at even offsets).
+template <bool kF32, int BN, int MT, int NT>
 __device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&acc)[MT][NT], bf16_t* Os, int co0,
                                               int img, int ty0, int tx0, int wm, int lane, int t) {
-    constexpr int BM = 256, BN = 32, OP = BN + 8;
+    constexpr int BM = 256, OP = BN + 8;
+    static_assert(NT * 16 == BN, "NT 16-wide blocks per BN");
     const int r16 = lane & 15;
     // image pixel of tile pixel q (row q >> 4, column q & 15)
     auto pixel = [&](int q) { return (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15)); };
@@ -465,6 +473,33 @@ __device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&a
         }
         __syncthreads();
         constexpr int VR = BN / 8;
+        // half-size pixel of 2x2 block q (row q >> 3, column q & 7) of the tile, whose tile
+        // rows are r0, r0 + 1, r0 + 16, r0 + 17 with r0 = 32 (q >> 3) + 2 (q & 7)
+        auto half_pixel = [&](int q) {
+            return (size_t)((img >> 2) + (((ty0 >> 1) + (q >> 3)) << (a.lw - 1)) + (tx0 >> 1) + (q & 7));
+        };
+        if (a.down == 2 && co0 < a.ysplit) {
+            // upsampling gradient: the 2x2 sums in block order, as k_up_bwd adds them
+            for (int v = t; v < 64 * VR; v += 256) {
+                const int q = v / VR, cv = v - q * VR, r0 = 32 * (q >> 3) + 2 * (q & 7);
+                const int rows[4] = {r0, r0 + 1, r0 + 16, r0 + 17};
+                float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, e[8], gt[8];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    unpack8(*reinterpret_cast<const uint4*>(&Os[rows[k] * OP + 8 * cv]), e);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) sum[c] += e[c];
+                }
+                const size_t hp = half_pixel(q);
+                const int co = co0 + 8 * cv;
+                unpack8(ld16(a.gate + hp * a.ldgt + co), gt);
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (!(gt[c] > 0.f)) sum[c] = 0.f;
+                st16(static_cast<bf16_t*>(a.y) + hp * a.ldy + co, pack8(sum));
+            }
+            return;
+        }
         for (int v = t; v < BM * VR; v += 256) {
             const int row = v / VR, cv = v - row * VR;
             const size_t p = pixel(row);
@@ -482,6 +517,22 @@ __device__ __forceinline__ void halo_epilogue(const ConvArgs& a, const f32x4 (&a
                 o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
             }
             st16(dst_at<bf16_t>(a, p, co), o);
+        }
+        if (a.down == 1) {
+            // 2x2 max pooling of the stored values, in k_pool_fwd's order
+            for (int v = t; v < 64 * VR; v += 256) {
+                const int q = v / VR, cv = v - q * VR, r0 = 32 * (q >> 3) + 2 * (q & 7);
+                const int rows[3] = {r0 + 1, r0 + 16, r0 + 17};
+                float m[8], e[8];
+                unpack8(*reinterpret_cast<const uint4*>(&Os[r0 * OP + 8 * cv]), m);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    unpack8(*reinterpret_cast<const uint4*>(&Os[rows[k] * OP + 8 * cv]), e);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) m[c] = e[c] > m[c] ? e[c] : m[c];
+                }
+                st16(static_cast<bf16_t*>(a.yp) + half_pixel(q) * a.ldyp + co0 + 8 * cv, pack8(m));
+            }
         }
     }
 }
@@ -607,64 +658,10 @@ __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs 
                 acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]), acc[m][n], 0, 0, 0);
     }
     }
-    // image pixel of tile pixel q (row q >> 4, column q & 15)
-    auto pixel = [&](int q) { return (size_t)(img + ((ty0 + (q >> 4)) << a.lw) + tx0 + (q & 15)); };
-    const int g4 = 4 * (lane >> 4);
-    if constexpr (kF32) {
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const int co = co0 + 16 * n + r16;
-            const float b = a.bias ? a.bias[co] : 0.f;
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const size_t p = pixel(wm + 16 * m + g4 + r);
-                    float v = acc[m][n][r] + b;
-                    if (a.relu) v = fmaxf(v, 0.f);
-                    if (a.mask && !(bf2f(a.mask[p * a.ldm + co]) > 0.f)) v = 0.f;
-                    *dst_at<float>(a, p, co) = v;
-                }
-            }
-        }
-    } else {
-        __syncthreads();  // every wavefront is done with the halo and weight tiles
-        bf16_t* Os = BN == 32 ? Ah : Bh;
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const int c = 16 * n + r16;
-            const float b = a.bias ? a.bias[co0 + c] : 0.f;
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = acc[m][n][r] + b;
-                    if (a.relu) v = fmaxf(v, 0.f);
-                    Os[(wm + 16 * m + g4 + r) * OP + c] = (bf16_t)f2bf_hw(v);
-                }
-            }
-        }
-        __syncthreads();
-        constexpr int VR = BN / 8;
-        for (int v = t; v < BM * VR; v += 256) {
-            const int row = v / VR, cv = v - row * VR;
-            const size_t p = pixel(row);
-            const int co = co0 + 8 * cv;
-            uint4 o = *reinterpret_cast<const uint4*>(&Os[row * OP + 8 * cv]);
-            if (a.mask) {
-                const uint4 mk = ld16(a.mask + p * a.ldm + co);
-                const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
-                uint32_t ow[4] = {o.x, o.y, o.z, o.w};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t keep = (lo(mw[j]) > 0.f ? 0xffffu : 0u) | (hi(mw[j]) > 0.f ? 0xffff0000u : 0u);
-                    ow[j] &= keep;
-                }
-                o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
-            }
-            st16(dst_at<bf16_t>(a, p, co), o);
-        }
-    }
+    // the bfloat16 output tile is staged in the halo or weight buffer: every wavefront
+    // must be done with them first
+    if constexpr (!kF32) __syncthreads();
+    halo_epilogue<kF32, BN, MT, NT>(a, acc, BN == 32 ? Ah : Bh, co0, img, ty0, tx0, wm, lane, t);
 }
 
 // Halo-tile form for C_in = 8 (the network's first layer; H, W multiples of 16).  As in
@@ -739,7 +736,7 @@ __global__ void __launch_bounds__(256) k_conv_halo8(const ConvArgs a) {
             for (int n = 0; n < NT; ++n)
                 acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_frag(A[m]), as_frag(B[n]), acc[m][n], 0, 0, 0);
     }
-    halo_epilogue<kF32, MT, NT>(a, acc, Os, co0, img, ty0, tx0, wm, lane, t);
+    halo_epilogue<kF32, 32, MT, NT>(a, acc, Os, co0, img, ty0, tx0, wm, lane, t);
 }
 
 // several layers in one launch: workgroup b works on the layer whose element range
@@ -1949,11 +1946,15 @@ using namespace unet_dev;
 
 extern "C" {
 
-int unet_conv3x3_fwd_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, int32_t half, const void* x2,
-                         int32_t ldx2, int32_t offx2, const void* w, const float* bias, void* y, int32_t ldy,
-                         int32_t offy, int32_t C_y, void* y2, int32_t ldy2, int32_t offy2, const void* mask,
-                         int32_t ldm, int32_t offm, int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out,
-                         int32_t flags, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks the arguments of the two-tensor convolution and fills *a (no 2x2 work).
+int conv_cat_args(const void* x, int32_t ldx, int32_t offx, int32_t C_x, int32_t half, const void* x2, int32_t ldx2,
+                  int32_t offx2, const void* w, const float* bias, void* y, int32_t ldy, int32_t offy, int32_t C_y,
+                  void* y2, int32_t ldy2, int32_t offy2, const void* mask, int32_t ldm, int32_t offm, int32_t N,
+                  int32_t H, int32_t W, int32_t C_in, int32_t C_out, int32_t flags, ConvArgs* out_args) {
     int lh, lw, r;
     if ((r = check_geo(N, H, W, &lh, &lw))) return r;
     if (C_in < 8 || C_in % 8 || C_out < 16 || C_out % 16)
@@ -1984,7 +1985,7 @@ int unet_conv3x3_fwd_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, 
         if (!base) return nullptr;
         return f32 ? (void*)(static_cast<float*>(base) + off) : (void*)(static_cast<bf16_t*>(base) + off);
     };
-    ConvArgs a;
+    ConvArgs& a = *out_args;
     a.x = static_cast<const bf16_t*>(x) + offx;
     a.x2 = x2 ? static_cast<const bf16_t*>(x2) + offx2 : nullptr;
     a.w = static_cast<const bf16_t*>(w);
@@ -2006,13 +2007,86 @@ int unet_conv3x3_fwd_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, 
     a.Cin = C_in;
     a.Cout = C_out;
     a.relu = (flags & UNET_RELU) ? 1 : 0;
+    a.yp = nullptr;
+    a.gate = nullptr;
+    a.ldyp = a.ldgt = a.down = 0;
+    return UNET_OK;
+}
+
+int conv_launch(const ConvArgs& a, bool f32, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool tap_outer = C_in % 32 == 0;
+    const bool tap_outer = a.Cin % 32 == 0;
     if (!launch_conv_lds(a, f32, s)) {
-        if (C_out % 64 == 0) launch_conv<2, 4>(a, tap_outer, f32, s);
+        if (a.Cout % 64 == 0) launch_conv<2, 4>(a, tap_outer, f32, s);
         else launch_conv<4, 2>(a, tap_outer, f32, s);
     }
     return launched("conv3x3 launch");
+}
+
+// The 2x2 forms run in k_conv_halo only: bfloat16 output, 16 x 16 tiles, C_in % 32 == 0,
+// C_out % 32 == 0, and (for the upsampling gradient) the split at a multiple of the
+// workgroup's output width, so that each workgroup's channels are all on one side.
+int halo_width(const ConvArgs& a) {
+    if (a.lh < 4 || a.lw < 4 || a.Cin % 32 || a.Cout % 32) return 0;
+    return (a.Cin != 32 && a.Cout % 64 == 0) ? 64 : 32;
+}
+
+}  // namespace
+
+extern "C" {
+
+int unet_conv3x3_fwd_cat(const void* x, int32_t ldx, int32_t offx, int32_t C_x, int32_t half, const void* x2,
+                         int32_t ldx2, int32_t offx2, const void* w, const float* bias, void* y, int32_t ldy,
+                         int32_t offy, int32_t C_y, void* y2, int32_t ldy2, int32_t offy2, const void* mask,
+                         int32_t ldm, int32_t offm, int32_t N, int32_t H, int32_t W, int32_t C_in, int32_t C_out,
+                         int32_t flags, void* stream) {
+    ConvArgs a;
+    const int r = conv_cat_args(x, ldx, offx, C_x, half, x2, ldx2, offx2, w, bias, y, ldy, offy, C_y, y2, ldy2, offy2,
+                                mask, ldm, offm, N, H, W, C_in, C_out, flags, &a);
+    return r ? r : conv_launch(a, flags & UNET_OUT_F32, stream);
+}
+
+int unet_conv3x3_fwd_pool(const void* x, int32_t ldx, int32_t offx, const void* w, const float* bias, void* y,
+                          int32_t ldy, int32_t offy, void* yp, int32_t ldyp, int32_t offyp, int32_t N, int32_t H,
+                          int32_t W, int32_t C_in, int32_t C_out, int32_t flags, void* stream) {
+    if (flags & UNET_OUT_F32) return fail(UNET_EINVAL, "conv + pool: bfloat16 output only");
+    ConvArgs a;
+    int r = conv_cat_args(x, ldx, offx, C_in, 0, nullptr, 0, 0, w, bias, y, ldy, offy, C_out, nullptr, 0, 0, nullptr,
+                          0, 0, N, H, W, C_in, C_out, flags, &a);
+    if (r) return r;
+    if ((r = check_tensor("y", y, ldy, offy, C_out, false)) || (r = check_tensor("yp", yp, ldyp, offyp, C_out, false)))
+        return r;
+    if (!halo_width(a)) return fail(UNET_ESHAPE, "conv + pool: needs H, W >= 16 and C_in, C_out multiples of 32");
+    a.down = 1;
+    a.yp = static_cast<bf16_t*>(yp) + offyp;
+    a.ldyp = ldyp;
+    return conv_launch(a, false, stream);
+}
+
+int unet_conv3x3_bwd_upcat(const void* g, int32_t ldg, int32_t offg, const void* wf, void* dlow, int32_t lddl,
+                           int32_t offdl, const void* low, int32_t ldlow, int32_t offlow, int32_t C_low, void* dskip,
+                           int32_t ldds, int32_t offds, int32_t N, int32_t H, int32_t W, int32_t C_g, int32_t C_in,
+                           void* stream) {
+    ConvArgs a;
+    if (C_low < 8 || C_low >= C_in || C_low % 8)
+        return fail(UNET_EINVAL, "bwd upcat: C_low must be a multiple of 8 below C_in (got %d, C_in %d)", C_low, C_in);
+    // the full-size tensor of the upsampled branch is never written: y gets the split
+    // only for the argument checks, the stores go to dlow at half size
+    int r = conv_cat_args(g, ldg, offg, C_g, 0, nullptr, 0, 0, wf, nullptr, dlow, lddl, offdl, C_low, dskip, ldds,
+                          offds, nullptr, 0, 0, N, H, W, C_g, C_in, 0, &a);
+    if (r) return r;
+    if ((r = check_tensor("dlow", dlow, lddl, offdl, C_low, false)) ||
+        (r = check_tensor("low", low, ldlow, offlow, C_low, false)) ||
+        (r = check_tensor("dskip", dskip, ldds, offds, C_in - C_low, false)))
+        return r;
+    const int bn = halo_width(a);
+    if (!bn || C_low % bn)
+        return fail(UNET_ESHAPE, "bwd upcat: needs H, W >= 16, C_g and C_in multiples of 32 and C_low of %d",
+                    bn ? bn : 32);
+    a.down = 2;
+    a.gate = static_cast<const bf16_t*>(low) + offlow;
+    a.ldgt = ldlow;
+    return conv_launch(a, false, stream);
 }
 
 int unet_conv3x3_fwd(const void* x, int32_t ldx, int32_t offx, const void* w, const float* bias, void* y,

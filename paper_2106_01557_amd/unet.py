@@ -26,7 +26,8 @@ from . import lbm as _lbm
 _lib = _lbm.library()
 _P, _I, _F, _V, _S = ctypes.POINTER, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
 
-EXPORTED = ["unet_conv3x3_fwd", "unet_conv3x3_fwd_cat", "unet_flip_weights", "unet_flip_weights_many",
+EXPORTED = ["unet_conv3x3_fwd", "unet_conv3x3_fwd_cat", "unet_conv3x3_fwd_pool", "unet_conv3x3_bwd_upcat",
+            "unet_flip_weights", "unet_flip_weights_many",
             "unet_wgrad_partial_bytes", "unet_conv3x3_wgrad", "unet_conv3x3_wgrad_cat", "unet_conv3x3_wgrad_noalloc",
             "unet_maxpool2_fwd", "unet_maxpool2_bwd", "unet_upsample2_fwd", "unet_upsample2_bwd",
             "unet_prepare_input", "unet_output_fields", "unet_head_partial_bytes", "unet_head_fwd", "unet_head_bwd",
@@ -34,10 +35,13 @@ EXPORTED = ["unet_conv3x3_fwd", "unet_conv3x3_fwd_cat", "unet_flip_weights", "un
             "unet_to_bf16", "unet_to_f32", "unet_last_error"]
 
 RELU, OUT_F32 = 1, 2
+ESHAPE = -2  # a fused call that does not cover the shape: the separate calls do
 
 _lib.unet_conv3x3_fwd.argtypes = [_V, _I, _I, _V, _V, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_conv3x3_fwd_cat.argtypes = [_V, _I, _I, _I, _I, _V, _I, _I, _V, _V, _V, _I, _I, _I, _V, _I, _I, _V, _I, _I,
                                       _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_conv3x3_fwd_pool.argtypes = [_V, _I, _I, _V, _V, _V, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _I, _V]
+_lib.unet_conv3x3_bwd_upcat.argtypes = [_V, _I, _I, _V, _V, _I, _I, _V, _I, _I, _I, _V, _I, _I, _I, _I, _I, _I, _I, _V]
 _lib.unet_flip_weights.argtypes = [_V, _V, _I, _I, _V]
 _lib.unet_flip_weights_many.argtypes = [ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.POINTER(_I),
                                         ctypes.POINTER(_I), _I, _V]
@@ -104,7 +108,7 @@ class UNet:
     gradient) and per-batch-shape activation buffers on one device."""
 
     def __init__(self, widths=(32, 64, 128, 256), in_channels=8, outputs=2, theta_scale=0.1, seed=0, device=None,
-                 stream=None, wgrad_streams=2):
+                 stream=None, wgrad_streams=2, fuse_2x2=True):
         import torch
         self.torch = torch
         self.widths = tuple(int(w) for w in widths)
@@ -125,6 +129,10 @@ class UNet:
         self.wgrad_streams = int(wgrad_streams)
         self.wstreams = [torch.cuda.Stream(self.device) for _ in range(self.wgrad_streams)] or [self.stream]
         self.ws = [ctypes.c_void_p(st.cuda_stream) for st in self.wstreams]
+        # the 2x2 max pooling in the epilogue of the convolution before it, and the
+        # upsampling's gradient in the epilogue of the decoder's input gradient, where the
+        # tiled kernel covers the shape (else, and with fuse_2x2=False, separate passes)
+        self.fuse_2x2 = bool(fuse_2x2)
         self.t = 0
         rng = np.random.Generator(np.random.PCG64(seed))
         p = {}
@@ -220,7 +228,6 @@ class UNet:
                     # the decoder's input [upsample2(lower level) | e{lvl}b] is never stored:
                     # its convolution reads the two tensors; its input gradient goes to the
                     # upsampled branch (dup, full size) and the skip branch (dskip)
-                    b[f"dup{lvl}"] = bf(N, h, w, cu)
                     b[f"dskip{lvl}"] = bf(N, h, w, c)
                     b[f"pool{lvl}"] = bf(N, h // 2, w // 2, c)
                     b[f"dpool{lvl}"] = bf(N, h // 2, w // 2, c)
@@ -271,11 +278,20 @@ class UNet:
             for lvl in range(L):
                 h, w, c = H >> lvl, W >> lvl, wd[lvl]
                 self._conv(f"e{lvl}a", x, ldx, offx, b[f"e{lvl}a"], c, 0, N, h, w)
-                self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"e{lvl}b"], c, 0, N, h, w)
                 if lvl < L - 1:
-                    _ck(_lib.unet_maxpool2_fwd(ptr(b[f"e{lvl}b"]), c, 0, ptr(b[f"pool{lvl}"]), c, 0, N, h, w, c,
-                                               self.s))
+                    rc = ESHAPE
+                    if self.fuse_2x2:
+                        rc = _lib.unet_conv3x3_fwd_pool(ptr(b[f"e{lvl}a"]), c, 0, ptr(self.w16[f"e{lvl}b"]),
+                                                        ptr(self.p[f"e{lvl}b.b"]), ptr(b[f"e{lvl}b"]), c, 0,
+                                                        ptr(b[f"pool{lvl}"]), c, 0, N, h, w, c, c, RELU, self.s)
+                    if rc == ESHAPE:
+                        self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"e{lvl}b"], c, 0, N, h, w)
+                        rc = _lib.unet_maxpool2_fwd(ptr(b[f"e{lvl}b"]), c, 0, ptr(b[f"pool{lvl}"]), c, 0, N, h, w, c,
+                                                    self.s)
+                    _ck(rc)
                     x, ldx, offx = b[f"pool{lvl}"], c, 0
+                else:
+                    self._conv(f"e{lvl}b", b[f"e{lvl}a"], c, 0, b[f"e{lvl}b"], c, 0, N, h, w)
             low = b[f"e{L - 1}b"]
             for lvl in reversed(range(L - 1)):
                 h, w, c, cu = H >> lvl, W >> lvl, wd[lvl], wd[lvl + 1]
@@ -348,14 +364,23 @@ class UNet:
                 else:
                     low, dlow = b[f"e{lvl + 1}b"], b[f"ge{lvl + 1}b"]
                 wgrad(f"d{lvl}a", low, cu, 0, b[f"gd{lvl}a"], c, h, w, skip=b[f"e{lvl}b"])
-                # input gradient, split between the upsampled branch and the skip branch
-                _ck(_lib.unet_conv3x3_fwd_cat(ptr(b[f"gd{lvl}a"]), c, 0, c, 0, None, 0, 0,
-                                              ptr(self.wf16[f"d{lvl}a"]), None, ptr(b[f"dup{lvl}"]), cu, 0, cu,
-                                              ptr(b[f"dskip{lvl}"]), c, 0, None, 0, 0, N, h, w, c, cu + c, 0,
-                                              self.s))
-                # gradient of the lower level's output, gated by its ReLU
-                _ck(_lib.unet_upsample2_bwd(ptr(b[f"dup{lvl}"]), cu, 0, ptr(low), cu, 0, ptr(dlow), cu, 0, N,
-                                            h // 2, w // 2, cu, self.s))
+                # input gradient, split between the upsampled branch (through the
+                # upsampling's gradient and the lower level's ReLU) and the skip branch
+                rc = ESHAPE
+                if self.fuse_2x2:
+                    rc = _lib.unet_conv3x3_bwd_upcat(ptr(b[f"gd{lvl}a"]), c, 0, ptr(self.wf16[f"d{lvl}a"]), ptr(dlow),
+                                                     cu, 0, ptr(low), cu, 0, cu, ptr(b[f"dskip{lvl}"]), c, 0, N, h, w,
+                                                     c, cu + c, self.s)
+                if rc == ESHAPE:
+                    if f"dup{lvl}" not in b:
+                        b[f"dup{lvl}"] = torch.empty((N, h, w, cu), dtype=torch.bfloat16, device=self.device)
+                    _ck(_lib.unet_conv3x3_fwd_cat(ptr(b[f"gd{lvl}a"]), c, 0, c, 0, None, 0, 0,
+                                                  ptr(self.wf16[f"d{lvl}a"]), None, ptr(b[f"dup{lvl}"]), cu, 0, cu,
+                                                  ptr(b[f"dskip{lvl}"]), c, 0, None, 0, 0, N, h, w, c, cu + c, 0,
+                                                  self.s))
+                    rc = _lib.unet_upsample2_bwd(ptr(b[f"dup{lvl}"]), cu, 0, ptr(low), cu, 0, ptr(dlow), cu, 0, N,
+                                                 h // 2, w // 2, cu, self.s)
+                _ck(rc)
             # encoder, bottleneck first
             for lvl in reversed(range(L)):
                 h, w, c = H >> lvl, W >> lvl, wd[lvl]

@@ -77,6 +77,18 @@ def test_network_calls_validate_before_launching(lbm):
     assert "y2" in lib.unet_last_error().decode()
     assert cat(buf, 32, 0, 32, 0, None, 0, 0, buf, None, buf, 64, 0, 64, buf, 16, 0, None, 0, 0, 1, 8, 8, 32, 96, 0,
                None) == -1  # y2's ld below the 32 channels it receives
+    # fused 2x2 forms: bfloat16 only, and UNET_ESHAPE (-2) before any launch for shapes the
+    # tiled kernel does not cover
+    assert lib.unet_conv3x3_fwd_pool(buf, 32, 0, buf, None, buf, 32, 0, buf, 32, 0, 1, 32, 32, 32, 32, 2, None) == -1
+    assert lib.unet_conv3x3_fwd_pool(buf, 32, 0, buf, None, buf, 32, 0, buf, 32, 0, 1, 8, 8, 32, 32, 1, None) == -2
+    assert lib.unet_conv3x3_fwd_pool(buf, 16, 0, buf, None, buf, 32, 0, buf, 32, 0, 1, 32, 32, 16, 32, 1, None) == -2
+    up = lib.unet_conv3x3_bwd_upcat
+    # arguments: g ld off, wf, dlow ld off, low ld off, C_low, dskip ld off, N H W C_g C_in
+    assert up(buf, 32, 0, buf, buf, 96, 0, buf, 96, 0, 96, buf, 32, 0, 1, 32, 32, 32, 96, None) == -1
+    assert "C_low" in lib.unet_last_error().decode()
+    assert up(buf, 32, 0, buf, buf, 64, 0, buf, 64, 0, 64, buf, 32, 0, 1, 8, 8, 32, 96, None) == -2
+    assert up(buf, 64, 0, buf, buf, 96, 0, buf, 96, 0, 96, buf, 96, 0, 1, 32, 32, 64, 192, None) == -2  # 96 % 64
+    assert up(buf, 32, 0, buf, buf, 64, 0, None, 64, 0, 64, buf, 32, 0, 1, 32, 32, 32, 96, None) == -1  # no gate
     wcat = lib.unet_conv3x3_wgrad_cat
     assert wcat(buf, 64, 0, 60, 1, buf, 36, 0, buf, 32, 0, buf, buf, buf, 1 << 30, 2, 64, 64, 96, 32, None) == -1
     assert "C_x" in lib.unet_last_error().decode()

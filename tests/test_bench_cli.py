@@ -59,7 +59,7 @@ def test_committed_flop_summary_matches_the_bounded_kernel_source():
 def test_unet_step_bound_sits_between_the_mfma_and_the_summed_bounds():
     """The U-Net line's per-pass bound takes, pass by pass, the longer of the MFMA time at
     the dense bf16 peak and the HBM time of the activations: at least the whole step's
-    FLOPs at peak, at most the MFMA and HBM times added, and 0.69 ms for the 16 x 256^2
+    FLOPs at peak, at most the MFMA and HBM times added, and 0.61 ms for the 16 x 256^2
     batch (most 256^2 and 128^2 passes are HBM-bound at 32 and 64 channels)."""
     sys.path.insert(0, ROOT)
     import bench
@@ -67,7 +67,7 @@ def test_unet_step_bound_sits_between_the_mfma_and_the_summed_bounds():
     b = bench.unet_step_bound_ms(*args)
     mfma_only = bench.unet_step_flops(*args) / (bench.PEAK_BF16_TFLOPS * 1e12) * 1e3
     assert mfma_only < b < 2.5 * mfma_only
-    assert 0.65 < b < 0.72
+    assert 0.58 < b < 0.65
     # halving the batch halves every term but the optimizer's (about 8 us)
     half = bench.unet_step_bound_ms((32, 64, 128, 256), 8, 8, 256, 256)
     assert 0.006 < 2 * half - b < 0.011

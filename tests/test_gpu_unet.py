@@ -460,10 +460,10 @@ def _cos(a, b):
 TS = 0.1  # temperature normalisation of the network (theta = (T / T0 - 1) / TS)
 
 
-def _net_case(widths, hw):
+def _net_case(widths, hw, fuse_2x2=True):
     import torch
     from paper_2106_01557_amd import unet
-    net = unet.UNet(widths=widths, seed=1)
+    net = unet.UNet(widths=widths, seed=1, fuse_2x2=fuse_2x2)
     arch = U.Arch(widths=widths, in_channels=8, used_inputs=3, outputs=2)
     p = U.init_params(arch, seed=2)
     p = {k: U.bf16_round(v) for k, v in p.items()}
@@ -512,7 +512,9 @@ def test_unet_every_layer_teacher_forced(widths, hw):
     activation gradient and every parameter gradient), with the strides and channel
     offsets the network really uses."""
     say(f"case: U-Net widths {widths} on {hw}x{hw}, every layer teacher-forced")
-    net, arch, p, x, rin, tn, out, loss, grads = _net_case(widths, hw)
+    # the separate 2x2 passes, so that every intermediate tensor is stored (the fused
+    # forms are bitwise the same: test_fused_2x2_passes_equal_the_separate_passes)
+    net, arch, p, x, rin, tn, out, loss, grads = _net_case(widths, hw, fuse_2x2=False)
     b = {k: host(v) for k, v in net.buf.items() if k not in ("wpart", "hpart")}
     L, wd = len(widths), widths
     ab = lambda a: np.abs(a)
@@ -676,6 +678,102 @@ def test_weight_gradients_on_their_own_streams_equal_one_stream():
             assert torch.equal(nets[0].flat, other.flat), step
             assert torch.equal(nets[0].w16flat, other.w16flat), step
     assert float(nets[2].gflat.abs().max()) > 0
+
+
+def test_fused_2x2_passes_equal_the_separate_passes():
+    """The encoder's 2x2 pooling in the epilogue of the convolution before it, and the
+    upsampling's gradient in the epilogue of the decoder's input gradient: three
+    training steps of the full network on four 64 x 64 problems (fused at the 64, 32 and
+    16 levels) are bitwise those of the separate passes."""
+    import torch
+    from paper_2106_01557_amd import unet
+    say("case: U-Net widths (32, 64, 128, 256), 4 x 64 x 64, fused against separate 2x2 passes")
+    N, hw = 4, 64
+    nets = [unet.UNet(widths=(32, 64, 128, 256), seed=6, fuse_2x2=f) for f in (False, True)]
+    rng = np.random.Generator(np.random.PCG64(9))
+    yy, xx = np.meshgrid(np.arange(hw), np.arange(hw), indexing="ij")
+    rho = np.stack([0.3 + 0.25 * np.tanh((10 + 2 * n - np.hypot(xx - 30, yy - 34)) / 2) for n in range(N)])
+    rho += 0.01 * rng.standard_normal(rho.shape)
+    T0 = np.array([0.07, 0.075, 0.08, 0.085])
+    Tf = T0[:, None, None] * (1 + 0.002 * rng.standard_normal(rho.shape))
+    tgt = rho + 0.02 * rng.standard_normal(rho.shape)
+    rv, rl, cond = np.full(N, 0.02), np.full(N, 0.55), np.linspace(-0.1, 0.1, N)
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64).cuda()  # noqa: E731
+    args = [T(a) for a in (rho, Tf, tgt, Tf, rv, rl, T0, cond)]
+    for step in range(3):
+        losses = [host(net.train_step(*args)).copy() for net in nets]
+        torch.cuda.synchronize()
+        assert np.array_equal(losses[0], losses[1]), step
+        for k in ("pool0", "pool1", "pool2", "ge1b", "gd1b", "ge3b", "dskip0"):
+            assert torch.equal(nets[0].buf[k], nets[1].buf[k]), (step, k)
+        assert torch.equal(nets[0].gflat, nets[1].gflat), step
+        assert torch.equal(nets[0].flat, nets[1].flat), step
+    assert "dup0" in nets[0].buf and "dup0" not in nets[1].buf  # the fused form never stores it
+
+
+@pytest.mark.parametrize("case", [(2, 32, 32, 32, 32), (1, 32, 64, 64, 64), (1, 16, 16, 128, 128)],
+                         ids=lambda c: "x".join(map(str, c)))
+def test_conv_with_pooling_equals_conv_then_pooling(case):
+    """unet_conv3x3_fwd_pool: the output and its 2x2 max pooling bitwise those of
+    unet_conv3x3_fwd followed by unet_maxpool2_fwd (32- and 64-wide workgroups)."""
+    import torch
+    N, H, W, ci, co = case
+    say(f"case: convolution with pooling {case}")
+    u = lib()
+    L = u.library()
+    x, w, b = dev_bf16(bf((N, H, W, ci), 60)), dev_bf16(bf((co, 3, 3, ci), 61, 0.2)), dev_f32(bf((co,), 62, 0.1))
+    y1, y2 = (torch.empty((N, H, W, co), dtype=torch.bfloat16, device="cuda") for _ in range(2))
+    p1, p2 = (torch.full((N, H // 2, W // 2, co), 9.0, dtype=torch.bfloat16, device="cuda") for _ in range(2))
+    ck(L.unet_conv3x3_fwd(u.ptr(x), ci, 0, u.ptr(w), u.ptr(b), u.ptr(y1), co, 0, None, 0, 0, N, H, W, ci, co, u.RELU,
+                          None))
+    ck(L.unet_maxpool2_fwd(u.ptr(y1), co, 0, u.ptr(p1), co, 0, N, H, W, co, None))
+    ck(L.unet_conv3x3_fwd_pool(u.ptr(x), ci, 0, u.ptr(w), u.ptr(b), u.ptr(y2), co, 0, u.ptr(p2), co, 0, N, H, W, ci, co,
+                               u.RELU, None))
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.int16), y2.view(torch.int16))
+    assert torch.equal(p1.view(torch.int16), p2.view(torch.int16))
+    # shapes the tiled kernel does not cover: UNET_ESHAPE, nothing written
+    p3 = torch.full((N, 4, 4, co), 9.0, dtype=torch.bfloat16, device="cuda")
+    y3 = torch.full((N, 8, 8, co), 9.0, dtype=torch.bfloat16, device="cuda")
+    x3 = dev_bf16(bf((N, 8, 8, ci), 63))
+    assert L.unet_conv3x3_fwd_pool(u.ptr(x3), ci, 0, u.ptr(w), u.ptr(b), u.ptr(y3), co, 0, u.ptr(p3), co, 0, N, 8, 8,
+                                   ci, co, u.RELU, None) == u.ESHAPE
+    torch.cuda.synchronize()
+    assert bool((y3 == 9.0).all()) and bool((p3 == 9.0).all())
+
+
+@pytest.mark.parametrize("case", [(2, 32, 32, 32, 64, 32), (1, 32, 32, 64, 128, 64), (1, 16, 32, 128, 256, 128)],
+                         ids=lambda c: "x".join(map(str, c)))
+def test_decoder_input_gradient_through_upsampling_equals_the_separate_calls(case):
+    """unet_conv3x3_bwd_upcat: the skip branch's gradient and the lower level's gradient
+    (2x2 sums of the upsampled branch's gradient, gated by the lower level's ReLU) bitwise
+    those of unet_conv3x3_fwd_cat with the output split, then unet_upsample2_bwd."""
+    import torch
+    N, H, W, cg, clow, cs = case
+    cin = clow + cs
+    say(f"case: decoder input gradient through the upsampling {case}")
+    u = lib()
+    L = u.library()
+    g, wf = dev_bf16(bf((N, H, W, cg), 70)), dev_bf16(bf((cin, 3, 3, cg), 71, 0.2))
+    low = dev_bf16(bf((N, H // 2, W // 2, clow), 72))        # both signs: the gate is exercised
+    dup = torch.empty((N, H, W, clow), dtype=torch.bfloat16, device="cuda")
+    ds1, ds2 = (torch.empty((N, H, W, cs), dtype=torch.bfloat16, device="cuda") for _ in range(2))
+    dl1, dl2 = (torch.full((N, H // 2, W // 2, clow), 9.0, dtype=torch.bfloat16, device="cuda") for _ in range(2))
+    ck(L.unet_conv3x3_fwd_cat(u.ptr(g), cg, 0, cg, 0, None, 0, 0, u.ptr(wf), None, u.ptr(dup), clow, 0, clow,
+                              u.ptr(ds1), cs, 0, None, 0, 0, N, H, W, cg, cin, 0, None))
+    ck(L.unet_upsample2_bwd(u.ptr(dup), clow, 0, u.ptr(low), clow, 0, u.ptr(dl1), clow, 0, N, H // 2, W // 2, clow,
+                            None))
+    ck(L.unet_conv3x3_bwd_upcat(u.ptr(g), cg, 0, u.ptr(wf), u.ptr(dl2), clow, 0, u.ptr(low), clow, 0, clow, u.ptr(ds2),
+                                cs, 0, N, H, W, cg, cin, None))
+    torch.cuda.synchronize()
+    assert torch.equal(ds1.view(torch.int16), ds2.view(torch.int16))
+    assert torch.equal(dl1.view(torch.int16), dl2.view(torch.int16))
+    assert bool((dl2 == 0).any()) and bool((dl2 != 0).any())
+    # a split that is not a multiple of the workgroup's output width: UNET_ESHAPE
+    if cin % 64 == 0 and cg != 32:
+        ds3 = torch.empty((N, H, W, cs + 32), dtype=torch.bfloat16, device="cuda")  # sized as the call says
+        assert L.unet_conv3x3_bwd_upcat(u.ptr(g), cg, 0, u.ptr(wf), u.ptr(dl2), clow, 0, u.ptr(low), clow, 0, clow - 32,
+                                        u.ptr(ds3), cs + 32, 0, N, H, W, cg, cin, None) == u.ESHAPE
 
 
 LARGE_CONV = [  # N, H, W, Cin, Cout: thousands of pixels, every LDS tile shape, XCD-ordered grids
