@@ -1077,9 +1077,11 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
     constexpr int PPR = OC / 8;     // 16-byte pieces per pixel of g
     constexpr int RP = 256 / PPR;   // g pixels loaded per pass of the workgroup
     constexpr int MH = OC / 16;     // 16-row output blocks
+    constexpr int KU = OC == 64 ? 1 : 2;
     __shared__ __attribute__((aligned(16))) bf16_t Gs[256 * GP + 32 * 32];
     __shared__ __attribute__((aligned(16))) bf16_t Hs[18 * kWgHaloRow];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // the wavefront index is uniform: its column blocks, taps and LDS offsets are scalars
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     // flat grid: input-channel blocks, then output-channel blocks, then slabs
     const int L = xcd_block(blockIdx.x, gridDim.x);
     const int cc = L % a.ktiles, rest = L / a.ktiles, ob = rest % a.ctiles, z = rest / a.ctiles;
@@ -1144,7 +1146,9 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
         }
         __syncthreads();
         if (tile + 1 < te) gload(tile + 1);
-#pragma unroll 2
+        // two reduction steps per iteration for 32 outputs; one for 64, whose second
+        // set of A fragments would not fit two workgroups per CU
+#pragma unroll KU
         for (int ks = 0; ks < 8; ++ks) {
             bf16x8 A[MH];
 #pragma unroll
@@ -1152,14 +1156,15 @@ __global__ void __launch_bounds__(256) k_wgrad_halo(const WgArgs a) {
                 A[h] = tr_frag_pad<GP>(Gs, ks * 32, 16 * h, lane);
 #pragma unroll
             for (int i = 0; i < NCB; ++i) {
-                const int cb = wave + 4 * i;
-                if (cb < 18) {
-                    const int tap = cb >> 1, dy = tap / 3, dx = tap - 3 * (tap / 3);
-                    const bf16x8 B = halo_frag(Hs, ks, dy, dx, 16 * (cb & 1), lane);
+                // no branch in the loop, so the LDS reads of later blocks overlap the MFMAs:
+                // the fifth block of wavefronts 2 and 3 (blocks 18, 19) repeats block 17 and
+                // is not stored; wavefronts 0 and 1 do five blocks anyway
+                const int cb = min(wave + 4 * i, 17);
+                const int tap = cb >> 1, dy = tap / 3, dx = tap - 3 * (tap / 3);
+                const bf16x8 B = halo_frag(Hs, ks, dy, dx, 16 * (cb & 1), lane);
 #pragma unroll
-                    for (int h = 0; h < MH; ++h)
-                        acc[h][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], B, acc[h][i], 0, 0, 0);
-                }
+                for (int h = 0; h < MH; ++h)
+                    acc[h][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], B, acc[h][i], 0, 0, 0);
             }
         }
     }
@@ -1226,7 +1231,7 @@ __global__ void __launch_bounds__(256) k_wgrad_halo8(const WgArgs a) {
     constexpr int MH = OC / 16;     // 16-row output blocks
     __shared__ __attribute__((aligned(16))) bf16_t Gs[256 * GP];
     __shared__ __attribute__((aligned(16))) bf16_t Hs[kHalo * kWg8Pitch];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     // flat grid: output-channel blocks, then slabs (one input-channel block)
     const int L = xcd_block(blockIdx.x, gridDim.x);
     const int ob = L % a.ctiles, z = L / a.ctiles;
@@ -1290,13 +1295,13 @@ __global__ void __launch_bounds__(256) k_wgrad_halo8(const WgArgs a) {
                 A[h] = tr_frag<GP>(reinterpret_cast<const bf16_t(*)[GP]>(Gs), ks * 32, 16 * h, lane);
 #pragma unroll
             for (int i = 0; i < NCB; ++i) {
-                const int cb = wave + 4 * i;
-                if (cb < 5) {
-                    const bf16x8 B = halo_frag8(Hs, ks, cb, lane);
+                // branch-free as in k_wgrad_halo: wavefronts 1 to 3 repeat block 4 as their
+                // second block, which is not stored
+                const int cb = min(wave + 4 * i, 4);
+                const bf16x8 B = halo_frag8(Hs, ks, cb, lane);
 #pragma unroll
-                    for (int h = 0; h < MH; ++h)
-                        acc[h][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], B, acc[h][i], 0, 0, 0);
-                }
+                for (int h = 0; h < MH; ++h)
+                    acc[h][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], B, acc[h][i], 0, 0, 0);
             }
         }
     }
