@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(256, kOne ? 3 : 1) k_conv_halo(const ConvArgs 
     static_assert(BM * OP <= (BN == 32 ? kHalo * 32 : 9 * BN * 32), "output tile fits its staging buffer");
     __shared__ __attribute__((aligned(16))) bf16_t Ah[kHalo * 32];
     __shared__ __attribute__((aligned(16))) bf16_t Bh[9 * BN * 32];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int ctiles = a.Cout / BN, L = xcd_block(blockIdx.x, gridDim.x);
     const int tile = L / ctiles, co0 = (L % ctiles) * BN;
     const int W = 1 << a.lw, Hm = (1 << a.lh) - 1, Wm = W - 1;
@@ -1343,7 +1343,7 @@ __global__ void __launch_bounds__(64 * WV) k_wgrad_reduce(const float* __restric
                                                           int Kt) {
     static_assert((WV & (WV - 1)) == 0 && WV >= 2 && (NA == 4 || NA == 8), "power-of-two waves, 4 or 8 sums");
     __shared__ float sm[WV][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int idx = blockIdx.x * 64 + lane;
     const bool on = idx < Cout * (K + 1);
     const int o = on ? idx / (K + 1) : 0, k = on ? idx - o * (K + 1) : 0;
@@ -1640,16 +1640,15 @@ __global__ void __launch_bounds__(kHeadBlock) k_head_bwd(const bf16_t* d, int ld
 // s_k = hw_k . d + hb_k + rin_k, dout_k = 2 (s_k - target_k) / (K P) and the gradient of d,
 // g = sum_k dout_k hw_k where d > 0 (the ReLU of the last convolution).  Per workgroup:
 // the sums of dout_k d and of dout_k (weight and bias gradients) combined as in
-// k_head_bwd, in rows part[b][K (C + 1)], and the sum of (s_k - target_k)^2 in
-// lpart[b].  Thread layout of k_head_bwd: the C / 8 channel groups of a pixel on
+// k_head_bwd, in rows part[b][K (C + 1) + 1] whose last entry is the sum of
+// (s_k - target_k)^2.  Thread layout of k_head_bwd: the C / 8 channel groups of a pixel on
 // consecutive lanes, each with its 8 products per output, summed across the pixel's
 // lanes by a fixed xor butterfly (C / 8 a power of two).  d is read once where the two
 // separate passes read it twice, and dout is not read back.
 template <int KK>
 __global__ void __launch_bounds__(kHeadBlock) k_head_train(const bf16_t* d, int ldd, const float* hw, const float* hb,
                                                            const float* rin, const float* target, float* out,
-                                                           float* dout, bf16_t* g, float* part, float* lpart, int C,
-                                                           int P) {
+                                                           float* dout, bf16_t* g, float* part, int C, int P) {
     constexpr int K = KK;
     __shared__ float red[kHeadBlock * 9];
     const int G = C >> 3, t = threadIdx.x;
@@ -1715,10 +1714,10 @@ __global__ void __launch_bounds__(kHeadBlock) k_head_train(const bf16_t* d, int 
         pixel(p, va, ra, ta);
         if (two) pixel(pb, vb, rb, tb);
     }
-    const float lb = block_sum(r2, red);
-    if (t == 0) lpart[blockIdx.x] = lb;
     const int m = K * (C + 1);
-    float* row = part + (size_t)blockIdx.x * m;
+    float* row = part + (size_t)blockIdx.x * (m + 1);  // weight sums, then the loss sum
+    const float lb = block_sum(r2, red);
+    if (t == 0) row[m] = lb;
     for (int k = 0; k < K; ++k) {
         __syncthreads();
 #pragma unroll
@@ -1738,12 +1737,13 @@ __global__ void __launch_bounds__(kHeadBlock) k_head_train(const bf16_t* d, int 
     }
 }
 
-// out[j] = sum over blocks of part[b][j] (j < m) times scale, one workgroup per j:
+// out[j] = sum over blocks of part[b][j] (j < m) times scale, one workgroup per j (with
+// `last`, column m - 1 goes to last[0] times last_scale instead):
 // thread t sums rows t, t + 256, ... in order, then a fixed tree combines the 256
 // partial sums (deterministic).  With stride > 0 the entries j % stride == stride - 1
 // go to out1[j / stride] and the others to out0 with those entries skipped.
 __global__ void __launch_bounds__(256) k_sum_partials(const float* part, int blocks, int m, float scale, float* out0,
-                                                      float* out1, int stride) {
+                                                      float* out1, int stride, float* last, float last_scale) {
     __shared__ double sm[256];
     const int j = blockIdx.x;
     double s = 0.0;
@@ -1755,6 +1755,10 @@ __global__ void __launch_bounds__(256) k_sum_partials(const float* part, int blo
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
+    if (last && j == m - 1) {  // an extra last column with a scale and destination of its own
+        last[0] = (float)(sm[0] * last_scale);
+        return;
+    }
     const float v = (float)(sm[0] * scale);
     if (stride > 0 && j % stride == stride - 1) out1[j / stride] = v;
     else if (stride > 0) out0[(j / stride) * (stride - 1) + j % stride] = v;
@@ -2414,7 +2418,7 @@ int unet_head_fwd(const void* d, int32_t ldd, const float* hw, const float* hb, 
     if ((r = launched("head launch"))) return r;
     if (target) {
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, static_cast<const float*>(partials), blocks, 1,
-                           1.0f / (float)((size_t)K * P), loss, (float*)nullptr, 0);
+                           1.0f / (float)((size_t)K * P), loss, (float*)nullptr, 0, (float*)nullptr, 0.f);
         return launched("loss reduce launch");
     }
     return UNET_OK;
@@ -2439,7 +2443,7 @@ int unet_head_bwd(const void* d, int32_t ldd, const float* hw, const float* dout
     if ((r = launched("head bwd launch"))) return r;
     const int m = K * (C + 1);
     hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(256), 0, s, static_cast<const float*>(partials), blocks, m,
-                       1.0f, dhw, dhb, C + 1);
+                       1.0f, dhw, dhb, C + 1, (float*)nullptr, 0.f);
     return launched("head reduce launch");
 }
 
@@ -2457,31 +2461,28 @@ int unet_head_train(const void* d, int32_t ldd, const float* hw, const float* hb
     if (kHeadBlock % G != 0 || (G & (G - 1)))
         return fail(UNET_EINVAL, "head train: C / 8 must be a power of two dividing %d (got C = %d)", kHeadBlock, C);
     const int P = N * H * W;
-    // weight rows then one loss entry per workgroup: within the partials size, which
-    // allows (kHeadBlock / 64) rows per forward workgroup
+    // one row of K (C + 1) weight sums and the loss sum per workgroup: within the
+    // partials size, which allows (kHeadBlock / 64) rows of K (C + 1) per forward workgroup
     const int blocks = std::min((P + kHeadBlock - 1) / kHeadBlock, kHeadBwdBlocks);
     const int m = K * (C + 1);
     float* part = static_cast<float*>(partials);
-    float* lpart = part + (size_t)blocks * m;
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto* gb = static_cast<bf16_t*>(g);
     const auto* db = static_cast<const bf16_t*>(d);
     switch (K) {
         case 1: hipLaunchKernelGGL(k_head_train<1>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
-                                   out, dout, gb, part, lpart, C, P); break;
+                                   out, dout, gb, part, C, P); break;
         case 2: hipLaunchKernelGGL(k_head_train<2>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
-                                   out, dout, gb, part, lpart, C, P); break;
+                                   out, dout, gb, part, C, P); break;
         case 3: hipLaunchKernelGGL(k_head_train<3>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
-                                   out, dout, gb, part, lpart, C, P); break;
+                                   out, dout, gb, part, C, P); break;
         default: hipLaunchKernelGGL(k_head_train<4>, dim3(blocks), dim3(kHeadBlock), 0, s, db, ldd, hw, hb, rin, target,
-                                    out, dout, gb, part, lpart, C, P); break;
+                                    out, dout, gb, part, C, P); break;
     }
     if ((r = launched("head train launch"))) return r;
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, static_cast<const float*>(lpart), blocks, 1,
-                       1.0f / (float)((size_t)K * P), loss, (float*)nullptr, 0);
-    if ((r = launched("loss reduce launch"))) return r;
-    hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(256), 0, s, static_cast<const float*>(part), blocks, m, 1.0f,
-                       dhw, dhb, C + 1);
+    // weight and bias gradients and the loss in one launch (the loss is the last column)
+    hipLaunchKernelGGL(k_sum_partials, dim3(m + 1), dim3(256), 0, s, static_cast<const float*>(part), blocks, m + 1,
+                       1.0f, dhw, dhb, C + 1, loss, 1.0f / (float)((size_t)K * P));
     return launched("head reduce launch");
 }
 
