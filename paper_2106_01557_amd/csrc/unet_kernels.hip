@@ -2461,9 +2461,23 @@ int unet_head_train(const void* d, int32_t ldd, const float* hw, const float* hb
     if (kHeadBlock % G != 0 || (G & (G - 1)))
         return fail(UNET_EINVAL, "head train: C / 8 must be a power of two dividing %d (got C = %d)", kHeadBlock, C);
     const int P = N * H * W;
-    // one row of K (C + 1) weight sums and the loss sum per workgroup: within the
-    // partials size, which allows (kHeadBlock / 64) rows of K (C + 1) per forward workgroup
-    const int blocks = std::min((P + kHeadBlock - 1) / kHeadBlock, kHeadBwdBlocks);
+    // one full round of resident workgroups (a partial last round would run at a
+    // fraction of the occupancy), at most one per 256 pixels; one row of K (C + 1) weight
+    // sums and the loss sum per workgroup fits the partials size, which allows
+    // (kHeadBlock / 64) rows of K (C + 1) per 256 pixels
+    int resident = 0, cus = 0, dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) {
+        switch (K) {
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<1>, kHeadBlock, 0); break;
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<2>, kHeadBlock, 0); break;
+            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<3>, kHeadBlock, 0); break;
+            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<4>, kHeadBlock, 0);
+        }
+    }
+    if (e != hipSuccess) return fail(UNET_EHIP, "head train: occupancy query: %s", hipGetErrorString(e));
+    const int blocks = std::max(1, std::min((P + kHeadBlock - 1) / kHeadBlock, std::max(resident, 1) * cus));
     const int m = K * (C + 1);
     float* part = static_cast<float*>(partials);
     hipStream_t s = static_cast<hipStream_t>(stream);
