@@ -95,29 +95,34 @@ def measured_flops(tag: str, srcs) -> float | None:
 
 
 def cpu_baseline(seconds: float) -> dict:
-    """The FP64 oracle as it stands, on the same recipe scaled to 256 x 256 (R = 32)."""
+    """The FP64 oracle as it stands, on the same recipe scaled to 256 x 256 (R = 32) and
+    512 x 512 (R = 64), one thread, each timed for about half of `seconds` after one
+    warm-up step; `value` is the 256 x 256 rate, both are in `sizes`."""
     import numpy as np
     from oracle import lbm as olbm
     from oracle import thermo
     from paper_2106_01557_amd import inputs
+    from threadpoolctl import threadpool_limits
 
     model = olbm.Model.build(thermo.paper_cs_eos(), thermo.Params(Tr0=0.75))
     d = model.d
-    n = 256
-    f = inputs.droplet(n, n, d.rho_l, d.rho_v, d.T0, 32, 4, eps=0.005, seed=1)
-    st = olbm.init_state(model, *f.as_tuple())
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):  # one thread: any BLAS call the oracle makes stays serial
-        st = olbm.step(model, st)  # warm-up
-        steps, t0 = 0, time.perf_counter()
-        while time.perf_counter() - t0 < seconds:
-            st = olbm.step(model, st)
-            steps += 1
-        dt = time.perf_counter() - t0
-    assert np.isfinite(st.f).all()
-    return {"value": round(n * n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 numpy oracle, {n}x{n} droplet R=32 (same recipe), {steps} steps in {dt:.1f} s, "
-                      f"one thread (numpy einsum/roll, BLAS pools limited to 1) on {_host_cpu()}"}
+    rates, notes = {}, []
+    for n in (256, 512):
+        f = inputs.droplet(n, n, d.rho_l, d.rho_v, d.T0, n // 8, 4, eps=0.005, seed=1)
+        st = olbm.init_state(model, *f.as_tuple())
+        with threadpool_limits(limits=1):  # one thread: any BLAS call the oracle makes stays serial
+            st = olbm.step(model, st)  # warm-up
+            steps, t0 = 0, time.perf_counter()
+            while time.perf_counter() - t0 < seconds / 2:
+                st = olbm.step(model, st)
+                steps += 1
+            dt = time.perf_counter() - t0
+        assert np.isfinite(st.f).all()
+        rates[f"{n}x{n}"] = round(n * n * steps / dt / 1e6, 4)
+        notes.append(f"{n}x{n} droplet R={n // 8}: {steps} steps in {dt:.1f} s")
+    return {"value": rates["256x256"], "unit": "MLUPS", "cores": 1, "kind": "oracle", "sizes": rates,
+            "sample": "FP64 numpy oracle, same recipe, " + "; ".join(notes)
+                      + f"; one thread (numpy einsum/roll, BLAS pools limited to 1) on {_host_cpu()}"}
 
 
 def _host_cpu() -> str:
@@ -721,7 +726,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--wgrad-streams", type=int, default=2,
                     help="unet_step: streams for the weight gradients beside the input gradients (0: one stream)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--hbm-probe", action="store_true",
                     help="only time a plain 1 GiB copy, read-only reduction and write-only fill (reference HBM rates)")
     ap.add_argument("--copy-calibration", action="store_true",
