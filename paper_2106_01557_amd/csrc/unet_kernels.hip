@@ -2241,8 +2241,37 @@ int wgrad_launch(const WgIn& in, const void* g, int32_t ldg, int32_t offg, float
 }
 
 constexpr int kMaxDevices = 64;
-std::mutex g_scratch_mutex;
+std::mutex g_device_mutex;  // guards the per-device lookups below
 float* g_scratch_ptr[kMaxDevices] = {};
+
+// Workgroups of k_head_train<K> resident on the whole current device at once (the
+// occupancy query times the CU count), looked up on the first call per device and K.
+int g_head_round[kMaxDevices][4] = {};
+
+int head_train_round(int K, int* out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(UNET_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(UNET_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_device_mutex);
+    int& slot = g_head_round[dev][K - 1];
+    if (!slot) {
+        int resident = 0, cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) {
+            switch (K) {
+                case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<1>, kHeadBlock, 0); break;
+                case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<2>, kHeadBlock, 0); break;
+                case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<3>, kHeadBlock, 0); break;
+                default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<4>, kHeadBlock, 0);
+            }
+        }
+        if (e != hipSuccess) return fail(UNET_EHIP, "head train: occupancy query: %s", hipGetErrorString(e));
+        slot = std::max(resident, 1) * std::max(cus, 1);
+    }
+    *out = slot;
+    return UNET_OK;
+}
 
 // Device address of `scratch` on the current device (looked up on the first call there).
 int scratch_on_current_device(float** out) {
@@ -2250,7 +2279,7 @@ int scratch_on_current_device(float** out) {
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(UNET_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
     if (dev < 0 || dev >= kMaxDevices) return fail(UNET_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
-    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    std::lock_guard<std::mutex> lock(g_device_mutex);
     if (!g_scratch_ptr[dev]) {
         void* p = nullptr;
         e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
@@ -2465,19 +2494,9 @@ int unet_head_train(const void* d, int32_t ldd, const float* hw, const float* hb
     // fraction of the occupancy), at most one per 256 pixels; one row of K (C + 1) weight
     // sums and the loss sum per workgroup fits the partials size, which allows
     // (kHeadBlock / 64) rows of K (C + 1) per 256 pixels
-    int resident = 0, cus = 0, dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) {
-        switch (K) {
-            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<1>, kHeadBlock, 0); break;
-            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<2>, kHeadBlock, 0); break;
-            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<3>, kHeadBlock, 0); break;
-            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_head_train<4>, kHeadBlock, 0);
-        }
-    }
-    if (e != hipSuccess) return fail(UNET_EHIP, "head train: occupancy query: %s", hipGetErrorString(e));
-    const int blocks = std::max(1, std::min((P + kHeadBlock - 1) / kHeadBlock, std::max(resident, 1) * cus));
+    int round = 0;
+    if ((r = head_train_round(K, &round))) return r;
+    const int blocks = std::max(1, std::min((P + kHeadBlock - 1) / kHeadBlock, round));
     const int m = K * (C + 1);
     float* part = static_cast<float*>(partials);
     hipStream_t s = static_cast<hipStream_t>(stream);
