@@ -6,6 +6,7 @@
     python bench.py --workload batch64 [--steps K] [--coexistence STEPS]
     python bench.py --workload warmstart [--train-runs 2000] [--horizon 5000] [--epochs 20]
     python bench.py --workload stefan [--steps K] [--stefan-physics 40000000]
+    python bench.py --workload laplace [--laplace-steps 2000000]  # FP64 Laplace series over long runs
 
 Workload: a static droplet on a periodic 4096 x 4096 D2Q9 lattice, radius 512 at
 the domain centre, tanh interface of width 4 nodes, Carnahan-Starling EOS with the
@@ -552,6 +553,64 @@ def interface_x(rho_row, rho_v: float, rho_l: float) -> float:
     return (j - 1) + (mid - rho_row[j - 1]) / (rho_row[j] - rho_row[j - 1])
 
 
+def run_laplace(args) -> dict:
+    """Long FP64 runs of the Laplace radius series (droplets R0 = 16, 32, 64 at the
+    centre of 256 x 256, T/Tc 0.8, the paper's constants): at every sample, the
+    temperature spread over the domain, the droplet's equimolar radius and
+    sigma = (p_in - p_out) R against the square-gradient sigma_ref at the droplet's mean
+    temperature.  The energy equation is solved, so T is not held fixed: these runs show
+    how far the temperature field settles and what sigma does as it does."""
+    import numpy as np
+    import torch
+    from oracle import thermo
+    from paper_2106_01557_amd import inputs, lbm
+
+    torch.cuda.set_device(0)
+    n, every, total = 256, args.laplace_every, args.laplace_steps
+    eos = thermo.paper_cs_eos()
+    d = thermo.derive(eos, thermo.Params(Tr0=0.8))
+    Tc = float(d.Tc)
+    out = {"metric": "Laplace law over long runs (FP64)", "unit": "sigma / sigma_ref - 1", "n_gpus": 1,
+           "data": "synthetic", "config": {"workload": f"FP64 droplets R0 = 16, 32, 64 on {n}x{n}, T/Tc 0.8, "
+                                            "CS EOS with the paper's K_EOS, K_INT, tanh W = 4, no noise",
+                                            "steps": total, "sample_every": every}, "droplets": []}
+    t0 = time.perf_counter()
+    for R0 in (16, 32, 64):
+        s = lbm.Solver(n, n, params={"Tr0": 0.8, "precision": "f64", "rows_per_wave": 16})
+        rows = []
+        try:
+            c = s.derived()
+            f = inputs.droplet(n, n, c["rho_l"], c["rho_v"], c["T0"], R0, 4.0, eps=0.0)
+            s.set_fields(*f.as_tuple())
+            done = 0
+            while done < total:
+                k = min(every, total - done)
+                s.step(k)
+                done += k
+                torch.cuda.synchronize()
+                m = s.moments_numpy()
+                rho, T = m["rho"], m["T"]
+                if not (np.isfinite(rho).all() and np.isfinite(T).all()):
+                    rows.append({"step": done, "finite": False})
+                    break
+                i0 = n // 2
+                rl, rv = rho[i0, i0], rho[0, 0]
+                dp = float(thermo.pressure(eos, rl, T[i0, i0])) - float(thermo.pressure(eos, rv, T[0, 0]))
+                Req = float(np.sqrt(((rho - rv) / (rl - rv)).sum() / np.pi))
+                ref = float(thermo.surface_tension(eos, 0.5 * (T[i0, i0] + T[0, 0]), d.kappa))
+                rows.append({"step": done, "T_spread_over_Tc": float((T.max() - T.min()) / Tc),
+                             "T_in_over_Tc": float(T[i0, i0] / Tc), "T_out_over_Tc": float(T[0, 0] / Tc),
+                             "R_eq": round(Req, 4), "sigma_rel": float(dp * Req / ref - 1)})
+                print(f"# laplace R0={R0}: {done} steps, T spread {rows[-1]['T_spread_over_Tc']:.2e} Tc, "
+                      f"sigma {rows[-1]['sigma_rel'] * 100:+.2f} %, {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+        finally:
+            s.close()
+        out["droplets"].append({"R0": R0, "samples": rows})
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def run_stefan(args) -> dict:
     """The one-dimensional Stefan problem (the paper's Fig. 1 setting): 1024 x rows, heated
     side at T_r1 = 0.85 with outflow at constant pressure, liquid at rest at T_r0 = 0.8
@@ -686,7 +745,10 @@ def hbm_probe(nbytes: int = 1 << 30, reps: int = 20) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="droplet4096", choices=["droplet4096", "batch64", "warmstart", "unet_step", "stefan"])
+    ap.add_argument("--workload", default="droplet4096",
+                    choices=["droplet4096", "batch64", "warmstart", "unet_step", "stefan", "laplace"])
+    ap.add_argument("--laplace-steps", type=int, default=2_000_000, help="laplace: steps per droplet")
+    ap.add_argument("--laplace-every", type=int, default=200_000, help="laplace: steps between samples")
     ap.add_argument("--train-runs", type=int, default=2000)
     ap.add_argument("--test-runs", type=int, default=64)
     ap.add_argument("--horizon", type=int, default=5000)
@@ -754,6 +816,9 @@ def main() -> int:
         return 0
     if args.workload == "stefan":
         print(json.dumps(run_stefan(args)), flush=True)
+        return 0
+    if args.workload == "laplace":
+        print(json.dumps(run_laplace(args)), flush=True)
         return 0
 
     import torch
