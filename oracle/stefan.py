@@ -30,8 +30,9 @@ The cubic-velocity correction the paper also applies (its reference [Huang2020])
 left out: with Ste = 0.005 the flow is slow (|u| / c_s ~ 1e-3), where those terms are
 negligible.
 
-Pins (tests/test_oracle_stefan.py): the wall density, a uniform wall state staying
-steady, steady conduction (linear temperature, no flow), the f populations'
+Pins (tests/test_oracle_stefan.py): the wall density, the imposed boundary state, a
+uniform wall state staying steady (at rest, and flowing towards the outflow, which fixes
+the velocity-dependent parts of the equilibria the extrapolation uses), steady conduction (linear temperature, no flow), the f populations'
 non-equilibrium part through the viscous decay of a shear mode between the walls
 (second order in the width), and the g populations' non-equilibrium part through the
 conduction profile's slope at the default vapour conductivity (no temperature jump at

@@ -55,6 +55,46 @@ def test_uniform_vapour_at_the_wall_state_is_steady(model):
     assert np.allclose(st.f[:, :, 1:-1], st0.f[:, :, 1:-1], rtol=0, atol=1e-15)
 
 
+def test_moving_vapour_at_the_wall_state_keeps_its_state_next_to_the_heated_wall(model):
+    """Uniform vapour at the heated wall's state, flowing towards the outflow with a
+    tangential component (u/c_s = -0.05, 0.03): the boundary's equilibrium is then the
+    fluid's and the extrapolated non-equilibrium is zero, so the nodes next to the heated
+    wall keep their populations (to rounding) until the far wall's disturbance arrives.
+    This pins the velocity-dependent parts of both equilibria the extrapolation uses,
+    rho |u|^2 / 2 in rho e_k and the enthalpy flux rho h_k u, which vanish at rest."""
+    d = model.d
+    w = stefan.walls(model, 0.85, Tr_far=0.85)
+    rho = np.full((3, 16), w.rho_wall)
+    ux, uy = -0.05 * d.cs + 0 * rho, 0.03 * d.cs + 0 * rho
+    st0 = stefan.init_state(model, rho, ux, uy, 0 * rho + w.T_wall)
+    st = stefan.run(model, w, st0, 2)
+    scale_f, scale_g = np.abs(st0.f[:, :, 1:4]).max(), np.abs(st0.g[:, :, 1:4]).max()
+    assert np.allclose(st.f[:, :, 1:4], st0.f[:, :, 1:4], rtol=0, atol=1e-14 * scale_f)
+    assert np.allclose(st.g[:, :, 1:4], st0.g[:, :, 1:4], rtol=0, atol=1e-14 * scale_g)
+
+
+def test_boundary_state_is_the_stated_one(model):
+    """The imposed boundary state: heated side T_wall, the vapour density at p_out and the
+    first fluid column's velocity (zero-gradient outflow); far side T_far (by default the
+    saturation temperature T0 of the liquid), no velocity and the last fluid column's
+    density (zero gradient)."""
+    d = model.d
+    w = stefan.walls(model, 0.85)
+    assert w.T_far == d.T0
+    rng = np.random.default_rng(3)
+    nx = 10
+    rho = np.linspace(w.rho_wall, d.rho_l, nx)[None, :] * (1 + 0.01 * rng.standard_normal((2, nx)))
+    ux, uy = 1e-3 * rng.standard_normal((2, 2, nx))
+    T = d.T0 * (1 + 0.01 * rng.standard_normal((2, nx)))
+    mac, _ = stefan.macros(model, w, stefan.init_state(model, rho, ux, uy, T))
+    assert np.all(mac.T[:, 0] == w.T_wall) and np.all(mac.T[:, -1] == w.T_far)
+    # (the boundary densities come back as sums of stand-in populations: equal to rounding)
+    assert np.allclose(mac.rho[:, 0], w.rho_wall, rtol=1e-14, atol=0)
+    assert np.allclose(mac.rho[:, -1], mac.rho[:, -2], rtol=1e-14, atol=0)
+    assert np.all(mac.ux[:, 0] == mac.ux[:, 1]) and np.all(mac.uy[:, 0] == mac.uy[:, 1])
+    assert np.all(mac.ux[:, -1] == 0) and np.all(mac.uy[:, -1] == 0)
+
+
 def _isobaric_vapour(model, w, T):
     """Vapour densities with p_EOS(rho, T) = p_out (the steady state has uniform pressure)."""
     out = []

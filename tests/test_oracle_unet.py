@@ -85,6 +85,10 @@ def test_pool_and_upsample():
     t = np.zeros((1, 2, 2, 1))
     gt = U.maxpool2_grad(t, np.ones((1, 1, 1, 1)))
     assert gt[0, 0, 0, 0] == 1 and gt.sum() == 1
+    # a tie between (0, 1) and (1, 0) goes to (0, 1), which comes first row by row
+    t = np.array([[0.0, 2.0], [2.0, 1.0]]).reshape(1, 2, 2, 1)
+    gt = U.maxpool2_grad(t, np.ones((1, 1, 1, 1)))
+    assert gt[0, 0, 1, 0] == 1 and gt.sum() == 1
     # upsample: repetition, and its gradient is the adjoint
     u = U.upsample2(m)
     assert u.shape == x.shape and u[0, 3, 1, 2] == m[0, 1, 0, 2]
@@ -172,3 +176,35 @@ def test_unet_mutations_are_caught():
     good = U.conv3x3_grad_input(g, w)
     bad = U.conv3x3_grad_input(g, w[:, ::-1, ::-1, :])  # taps flipped
     assert np.abs(good - bad).max() > 1e-3
+
+
+def test_init_scales_are_he_normal():
+    """He et al. (2015) normal initialisation: std sqrt(2 / fan_in) with fan_in = 9 C_in for a
+    3x3 convolution, zero biases; the head's std is 1/sqrt(C).  Sample std within 3 % on
+    the widest layers (tens of thousands of draws each)."""
+    arch = U.Arch()
+    p = U.init_params(arch, 5)
+    for name, ci, co in arch.convs():
+        w = p[name + ".w"]
+        if w.size >= 20000:
+            assert abs(w.std() / np.sqrt(2.0 / (9 * ci)) - 1) < 0.03, name
+        assert not p[name + ".b"].any()
+    arch1 = U.Arch(widths=(256, 512), outputs=1)
+    hw = U.init_params(arch1, 6)["head.w"]
+    assert hw.shape == (1, 256) and abs(hw.std() * np.sqrt(256) - 1) < 0.15
+
+
+def test_head_adds_the_density_and_temperature_channels():
+    """The input layout: channel 0 the normalised density, channel 1 the conditioning value
+    (the run's reduced temperature), channel 2 the normalised temperature deviation; a
+    one-output head is a residual on the density, a two-output head on density and
+    temperature, never on the conditioning channel.  With the head's weights and bias
+    zero the outputs are those input channels."""
+    for outputs, want in ((1, [10.0]), (2, [10.0, 30.0])):
+        arch = U.Arch(widths=(8, 16), outputs=outputs)
+        p = U.init_params(arch, 7)
+        p["head.w"][:] = 0
+        x = np.zeros((1, 4, 4, arch.in_channels))
+        x[..., 0], x[..., 1], x[..., 2] = 10.0, 20.0, 30.0
+        out, _ = U.forward(arch, p, x)
+        assert np.array_equal(out[0, 1, 2], np.array(want))
