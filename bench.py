@@ -559,17 +559,29 @@ def run_laplace(args) -> dict:
     temperature spread over the domain, the droplet's equimolar radius and
     sigma = (p_in - p_out) R against the square-gradient sigma_ref at the droplet's mean
     temperature.  The energy equation is solved, so T is not held fixed: these runs show
-    how far the temperature field settles and what sigma does as it does."""
+    how far the temperature field settles and what sigma does as it does.  The pressures
+    and sigma_ref come from the library's host thermodynamics: p_EOS of Eq. (17) with the
+    solver's constants, and sigma_ref(T) = 0.01 K_EOS K_INT / (K_EOS' K_INT') with
+    (K_EOS', K_INT') the constants that give sigma = 0.01 at T (sigma scales as K_EOS K_INT,
+    text after Eq. (19))."""
     import numpy as np
     import torch
-    from oracle import thermo
     from paper_2106_01557_amd import inputs, lbm
 
     torch.cuda.set_device(0)
     n, every, total = 256, args.laplace_every, args.laplace_steps
-    eos = thermo.paper_cs_eos()
-    d = thermo.derive(eos, thermo.Params(Tr0=0.8))
-    Tc = float(d.Tc)
+    eos = lbm.Eos()
+    K_int = lbm.default_params()["K_int"]
+    Tc = lbm.maxwell(0.8, eos)["Tc"]
+
+    def p_eos(rho, T):
+        """Eq. (17), Carnahan-Starling with the attraction a~ rho^2, times K_EOS."""
+        t = eos.b_t * rho / 4.0
+        return eos.K_eos * (rho * eos.R * T * (1 + t + t * t - t ** 3) / (1 - t) ** 3 - eos.a_t * rho * rho)
+
+    def sigma_ref(T):
+        k = lbm.interface_constants(T / Tc, 0.01, 10.0, eos)
+        return 0.01 * eos.K_eos * K_int / (k["K_eos"] * k["K_int"])
     out = {"metric": "Laplace law over long runs (FP64)", "unit": "sigma / sigma_ref - 1", "n_gpus": 1,
            "data": "synthetic", "config": {"workload": f"FP64 droplets R0 = 16, 32, 64 on {n}x{n}, T/Tc 0.8, "
                                             "CS EOS with the paper's K_EOS, K_INT, tanh W = 4, no noise",
@@ -595,9 +607,9 @@ def run_laplace(args) -> dict:
                     break
                 i0 = n // 2
                 rl, rv = rho[i0, i0], rho[0, 0]
-                dp = float(thermo.pressure(eos, rl, T[i0, i0])) - float(thermo.pressure(eos, rv, T[0, 0]))
+                dp = float(p_eos(rl, T[i0, i0]) - p_eos(rv, T[0, 0]))
                 Req = float(np.sqrt(((rho - rv) / (rl - rv)).sum() / np.pi))
-                ref = float(thermo.surface_tension(eos, 0.5 * (T[i0, i0] + T[0, 0]), d.kappa))
+                ref = sigma_ref(0.5 * float(T[i0, i0] + T[0, 0]))
                 rows.append({"step": done, "T_spread_over_Tc": float((T.max() - T.min()) / Tc),
                              "T_in_over_Tc": float(T[i0, i0] / Tc), "T_out_over_Tc": float(T[0, 0] / Tc),
                              "R_eq": round(Req, 4), "sigma_rel": float(dp * Req / ref - 1)})

@@ -71,3 +71,24 @@ def test_unet_step_bound_sits_between_the_mfma_and_the_summed_bounds():
     # halving the batch halves every term but the optimizer's (about 8 us)
     half = bench.unet_step_bound_ms((32, 64, 128, 256), 8, 8, 256, 256)
     assert 0.006 < 2 * half - b < 0.011
+
+
+def test_bench_uses_the_oracle_only_in_the_cpu_baseline():
+    """The oracle is test infrastructure: in bench.py only the CPU-baseline leg imports it;
+    every GPU workload, and its analysis, runs on the library."""
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+
+    def imports_oracle(node):
+        if isinstance(node, ast.ImportFrom):
+            mods = [node.module or ""]
+        elif isinstance(node, ast.Import):
+            mods = [a.name for a in node.names]
+        else:
+            return False
+        return any(m == "oracle" or m.startswith("oracle.") for m in mods)
+
+    assert not any(imports_oracle(n) for n in tree.body)  # nothing at module level
+    seen = {fn.name for fn in ast.walk(tree) if isinstance(fn, ast.FunctionDef)
+            and any(imports_oracle(n) for n in ast.walk(fn))}
+    assert seen == {"cpu_baseline"}, seen
