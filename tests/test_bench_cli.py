@@ -26,10 +26,11 @@ def test_committed_traffic_summaries_match_the_kernel_source_and_default_shapes(
     figure is within a few percent of the algorithmic 144 B per node."""
     sys.path.insert(0, ROOT)
     import bench
-    single = bench.measured_traffic("step_ab_f32_4096", (2, 2, 2))
-    assert single is not None
     alg = 36 * 4 * 4096 * 4096
-    assert 1.0 <= single / alg < 1.05
+    for shape in ((3, 4, 2), (2, 2, 2)):  # the default, and the earlier default
+        single = bench.measured_traffic("step_ab_f32_4096", shape)
+        assert single is not None, shape
+        assert 1.0 <= single / alg < 1.05
     with open(os.path.join(ROOT, "profiles", "traffic_step_ab_batch_f32_batch64.txt")) as fh:
         kv = dict(line.strip().split("=", 1) for line in fh if "=" in line and not line.startswith("#"))
     assert kv["kernel_source_sha"] == bench.kernel_sha()
